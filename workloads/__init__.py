@@ -1,0 +1,137 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds no arithmetic of the solver: it only places the grid nodes,
+samples potential functions at them and draws seeded random data.  Both the
+oracle and the GPU library receive exactly the arrays produced here.
+
+Grid: n interior nodes of [-L, L], x_j = -L + j h, h = 2L/(n+1), j = 1..n
+(homogeneous Dirichlet; the paper's n interior grid points per direction).
+Axis order is C order: axis d-1 is the fastest index (the paper's x).
+
+Workload recipes (each reading is listed in the design doc):
+* ``rhs_normal``: i.i.d. N(0, 1) right-hand side (numpy PCG64 from the seed).
+* ``gaussian_wavepacket``: psi0(x) = exp(-|x - x0|^2 / (2 s^2) + i k0 . x),
+  x0 ~ U[-2, 2]^d, s ~ U(0.5, 1.5), k0 ~ U[-2, 2]^d, normalised to unit 2-norm.
+  It is a product of per-axis factors, returned as such by ``wavepacket_factors``.
+* ``gaussian_bumps``: V2(x) = sum_b a_b exp(-|x - c_b|^2 / (2 w_b^2)), per bump
+  a ~ U(-5, 5), w ~ U(0.5, 2), c ~ U[-4, 4]^d, drawn in that order.
+* ``pairwise_v2``: V2(x) = sum_{i<j} 0.5 / (1 + (x_i - x_j)^2) over all axis pairs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def grid_nodes(n: int, L: float) -> np.ndarray:
+    h = 2.0 * L / (n + 1)
+    return -L + h * np.arange(1, n + 1, dtype=np.float64)
+
+
+# ---- separable potential samples f_k(x_j) ------------------------------------
+
+def f_harmonic(n: int, L: float, coef: float = 1.0) -> np.ndarray:
+    """f(x) = coef * x^2."""
+    x = grid_nodes(n, L)
+    return coef * x * x
+
+
+def f_harmonic_cos(n: int, L: float) -> np.ndarray:
+    """f(x) = x^2 + 0.5 cos(2x) (the 1e9-DoF workload's per-axis potential)."""
+    x = grid_nodes(n, L)
+    return x * x + 0.5 * np.cos(2.0 * x)
+
+
+def f_separable_v1(n: int, L: float) -> np.ndarray:
+    """f(x) = x^2 + 100 sin^2(pi x / 4): per-axis term of eq. (separable_V1)."""
+    x = grid_nodes(n, L)
+    return x * x + 100.0 * np.sin(np.pi * x / 4.0) ** 2
+
+
+def f_test_potential(n: int, L: float, c: float) -> np.ndarray:
+    """f(x) = 1600 sin^2(pi x / 4) + c x^2: one axis of eq. (test_potential)."""
+    x = grid_nodes(n, L)
+    return 1600.0 * np.sin(np.pi * x / 4.0) ** 2 + c * x * x
+
+
+# ---- random data -------------------------------------------------------------
+
+def rhs_normal(shape, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(size=tuple(shape))
+
+
+def wavepacket_factors(shape, L: float, seed: int):
+    """Per-axis complex factors g_k with psi0 = g_0 (x) g_1 (x) ... (outer product).
+
+    The overall normalisation is folded into the factors so that the outer
+    product has unit 2-norm.
+    """
+    d = len(shape)
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(-2.0, 2.0, size=d)
+    s = rng.uniform(0.5, 1.5)
+    k0 = rng.uniform(-2.0, 2.0, size=d)
+    facs = []
+    for k in range(d):
+        x = grid_nodes(shape[k], L)
+        g = np.exp(-((x - x0[k]) ** 2) / (2.0 * s * s) + 1j * k0[k] * x)
+        facs.append(g / np.linalg.norm(g))
+    return facs
+
+
+def outer(factors) -> np.ndarray:
+    out = np.ones((), dtype=np.result_type(*factors))
+    for g in factors:
+        out = np.multiply.outer(out, g)
+    return np.ascontiguousarray(out)
+
+
+def gaussian_wavepacket(shape, L: float, seed: int) -> np.ndarray:
+    return outer(wavepacket_factors(shape, L, seed))
+
+
+def bump_params(d: int, nbumps: int, seed: int):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nbumps):
+        a = rng.uniform(-5.0, 5.0)
+        w = rng.uniform(0.5, 2.0)
+        c = rng.uniform(-4.0, 4.0, size=d)
+        out.append((a, w, c))
+    return out
+
+
+def gaussian_bumps(shape, L: float, nbumps: int, seed: int) -> np.ndarray:
+    d = len(shape)
+    params = bump_params(d, nbumps, seed)
+    V = np.zeros(tuple(shape))
+    axes = [grid_nodes(n, L) for n in shape]
+    for a, w, c in params:
+        # exp(-|x-c|^2/(2w^2)) = prod_k exp(-(x_k-c_k)^2/(2w^2))
+        fac = [np.exp(-((axes[k] - c[k]) ** 2) / (2.0 * w * w)) for k in range(d)]
+        V += a * outer(fac)
+    return V
+
+
+def pairwise_v2(shape, L: float) -> np.ndarray:
+    d = len(shape)
+    axes = [grid_nodes(n, L) for n in shape]
+    V = np.zeros(tuple(shape))
+    for i in range(d):
+        for j in range(i + 1, d):
+            xi = axes[i].reshape([-1 if k == i else 1 for k in range(d)])
+            xj = axes[j].reshape([-1 if k == j else 1 for k in range(d)])
+            V += 0.5 / (1.0 + (xi - xj) ** 2)
+    return V
+
+
+def complex_normal(shape, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(size=tuple(shape)) + 1j * rng.standard_normal(size=tuple(shape))
+
+
+
+
+__all__ = [n for n in dir() if not n.startswith("_") and n not in ("math", "np", "annotations")]
