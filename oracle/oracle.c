@@ -45,8 +45,9 @@ void or_fd_axis_matrix(int64_t n, double L, const double* f, double* H) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Cyclic-by-row Jacobi eigensolver (Rutishauser's rotation formulas;         */
-/* Golub & Van Loan, "Matrix Computations", Sec. 8.5).  Plain and slow on     */
+/* Cyclic-by-row Jacobi eigensolver with Rutishauser's rotation and update   */
+/* formulas (Golub & Van Loan, "Matrix Computations", Sec. 8.5; Rutishauser,  */
+/* Handbook for Automatic Computation II/1, 1971).  Plain and slow on         */
 /* purpose.  A is symmetric row-major n x n (not modified).  Output: w        */
 /* ascending, V row-major with column j the unit eigenvector of w[j], sign    */
 /* fixed so that its largest-magnitude entry (lowest index on ties) is > 0.   */
@@ -82,25 +83,29 @@ int or_jacobi_eigh(int64_t n, const double* A_in, double* w, double* V, int max_
         double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
         double c = 1.0 / sqrt(t * t + 1.0);
         double s = t * c;
-        /* columns p and q: A <- A J */
-        for (int64_t k = 0; k < n; ++k) {
-          double akp = A[k * n + p], akq = A[k * n + q];
-          A[k * n + p] = c * akp - s * akq;
-          A[k * n + q] = s * akp + c * akq;
-        }
-        /* rows p and q: A <- J^T A */
-        for (int64_t k = 0; k < n; ++k) {
-          double apk = A[p * n + k], aqk = A[q * n + k];
-          A[p * n + k] = c * apk - s * aqk;
-          A[q * n + k] = s * apk + c * aqk;
-        }
+        double tau = s / (1.0 + c);
+        /* A <- J^T A J with Rutishauser's update: the diagonal moves by
+           -/+ t a_pq, every other entry of rows/columns p and q rotates as
+           x_p <- x_p - s (x_q + tau x_p), x_q <- x_q + s (x_p - tau x_q). */
+        A[p * n + p] = app - t * apq;
+        A[q * n + q] = aqq + t * apq;
         A[p * n + q] = 0.0;
         A[q * n + p] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+          if (k == p || k == q) continue;
+          double akp = A[k * n + p], akq = A[k * n + q];
+          double nkp = akp - s * (akq + tau * akp);
+          double nkq = akq + s * (akp - tau * akq);
+          A[k * n + p] = nkp;
+          A[p * n + k] = nkp;
+          A[k * n + q] = nkq;
+          A[q * n + k] = nkq;
+        }
         /* accumulate eigenvectors: V <- V J */
         for (int64_t k = 0; k < n; ++k) {
           double vkp = V[k * n + p], vkq = V[k * n + q];
-          V[k * n + p] = c * vkp - s * vkq;
-          V[k * n + q] = s * vkp + c * vkq;
+          V[k * n + p] = vkp - s * (vkq + tau * vkp);
+          V[k * n + q] = vkq + s * (vkp - tau * vkq);
         }
       }
     }

@@ -92,3 +92,15 @@ def test_continuum_ground_state_separable_v1():
     # the raw second-order values approach from below at rate ~4
     e = [abs(3 * m - ref) for m in mus]
     assert 3.5 < e[0] / e[1] < 4.5 and 3.5 < e[1] / e[2] < 4.5
+
+
+@pytest.mark.parametrize("n,kind", [(200, "cos"), (333, "sepv1")])
+def test_jacobi_accuracy_against_lapack_tridiagonal(n, kind):
+    """LAPACK's tridiagonal eigensolver (scipy) as the library-routine special case."""
+    import scipy.linalg
+    L = 8.0
+    f = {"cos": W.f_harmonic_cos, "sepv1": W.f_separable_v1}[kind](n, L)
+    h = 2 * L / (n + 1)
+    ref = scipy.linalg.eigh_tridiagonal(2 / h**2 + f, np.full(n - 1, -1 / h**2), eigvals_only=True)
+    w, _ = oracle.jacobi_eigh(oracle.fd_axis_matrix(n, L, f))
+    assert np.max(np.abs(w - ref)) <= 1e-14 * np.abs(ref).max()
