@@ -1,0 +1,227 @@
+/*
+ * ts.h -- C ABI of the MI355X separable tensor-product solver for the
+ * Schroedinger operator H = -Delta + V1 (+ V2), V1(x) = sum_k f_k(x_k).
+ *
+ * Discretisation (paper Sec. 2.1, eq. (general_system), eq. (tensor_system)):
+ * second-order finite differences (the Q^1 case) on n_k interior nodes of
+ * [-L, L] per axis, x_{k,j} = -L + j h_k, h_k = 2L/(n_k+1), homogeneous
+ * Dirichlet.  Per axis H_k = h_k^-2 tridiag(-1, 2, -1) + diag(f_k(x_{k,j})),
+ * and H1 = sum_k I (x) ... (x) H_k (x) ... (x) I (the Kronecker sum).
+ *
+ * Data layout: a grid function is a C-contiguous array of shape
+ * (n_0, ..., n_{d-1}); axis d-1 is the fastest index (the paper's x).
+ * Complex data is interleaved (re, im).  Per-axis arrays f[k] follow the same
+ * axis order.  All grid-function pointers are DEVICE pointers owned by the
+ * caller; the library never frees them.  f[k] in ts_setup are HOST pointers.
+ *
+ * Streams: work is enqueued on the caller's HIP stream (hipStream_t passed as
+ * void*, NULL = the legacy default stream) and the call returns without
+ * synchronising, except where a scalar result is returned to the host
+ * (iteration counts, residuals, eigenvalue histories): those calls
+ * synchronise the stream before returning.
+ *
+ * Errors: every call returns a ts_status; no exception crosses the ABI.  A
+ * human-readable message for the last failure on the calling thread is
+ * available from ts_last_error().  On error, caller-owned outputs are left in
+ * an unspecified state, and the plan stays valid.
+ *
+ * Concurrency: a plan is immutable after ts_setup except for its lazily
+ * allocated scratch buffers; calls that use the same plan must be issued on
+ * one stream (or otherwise ordered).  Distinct plans are independent.
+ */
+#ifndef TS_H
+#define TS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ts_plan ts_plan;
+
+typedef enum {
+  TS_OK = 0,
+  TS_ERR_INVALID = 1,   /* bad argument: null pointer, shape, dtype, precision   */
+  TS_ERR_NOT_SPD = 2,   /* lambda_min(H1) + sigma <= 0: the inverse is undefined  */
+  TS_ERR_NOMEM = 3,     /* device or host allocation failed                       */
+  TS_ERR_DEVICE = 4,    /* a HIP runtime call failed                              */
+  TS_ERR_NOCONV = 5,    /* iteration limit reached before the tolerance           */
+  TS_ERR_NONFINITE = 6, /* NaN or Inf met in a residual or inner product          */
+  TS_ERR_BUSY = 7,      /* serving: request not admitted yet (memory or slots)    */
+  TS_ERR_BREAKDOWN = 8  /* PCG: <p, A p> <= 0 (operator not positive definite)    */
+} ts_status;
+
+/* Element type of the grid functions passed to an apply. */
+typedef enum { TS_F64 = 0, TS_F32 = 1, TS_C128 = 2, TS_C64 = 3 } ts_dtype;
+
+/* Arithmetic of the per-axis transforms inside an apply.
+ * FP64: FP64 MFMA, FP64 intermediates.  FP32: FP32 MFMA, FP32 intermediates.
+ * BF16: BF16 MFMA operands with FP32 accumulation, BF16 intermediates.
+ * Denominators and phase factors are always formed in FP64 and then cast. */
+typedef enum { TS_PREC_FP64 = 0, TS_PREC_FP32 = 1, TS_PREC_BF16 = 2 } ts_prec;
+
+/* Splitting schemes for ts_split_step (paper Sec. 5.1).  A = H1 (exact
+ * propagator), B = V2 (pointwise).
+ *   STRANG_BAB : e^{-iB dt/2} e^{-iA dt} e^{-iB dt/2}   (potential outside)
+ *   STRANG_ABA : e^{-iA dt/2} e^{-iB dt} e^{-iA dt/2}   (= qHOP with M = 1)
+ *   YOSHIDA_*  : eq. (yoshida) -- S(g1 dt) S(g2 dt) S(g1 dt) with the Strang
+ *                step S of the same form, g1 = 1/(2 - 2^{1/3}),
+ *                g2 = -2^{1/3}/(2 - 2^{1/3}).
+ * Adjacent factors of the same operator are merged across sub-steps and steps
+ * (Remark rem:cost_naive_merged), which changes rounding only. */
+typedef enum {
+  TS_STRANG_BAB = 0,
+  TS_STRANG_ABA = 1,
+  TS_YOSHIDA_BAB = 2,
+  TS_YOSHIDA_ABA = 3
+} ts_scheme;
+
+/* ---------------------------------------------------------------- setup -- */
+
+/* Build a plan for H1 + sigma I (Sec. 2.1, step 1 "off-line setup").
+ *   d      : number of axes, 1 <= d <= 12
+ *   n[k]   : interior nodes on axis k, 1 <= n[k] <= 16384, prod(n) < 2^40
+ *   L      : half-width of the box [-L, L]^d, L > 0
+ *   f[k]   : HOST array of n[k] samples f_k(x_{k,j}), j = 1..n[k]
+ *   sigma  : shift; the inverse apply computes (H1 + sigma I)^{-1}
+ *   out    : receives the plan (owned by the caller, release with ts_destroy)
+ * Computes, on the host in FP64, the eigendecomposition H_k = Q_k diag(lam_k)
+ * Q_k^T of every distinct axis (eq. (eigen_decomp); for FD the mass matrix is
+ * a multiple of I, so T_k = Q_k and T_k^{-1} = Q_k^T), uploads Q_k, Q_k^T and
+ * lam_k to the current HIP device, and derives FP32 and BF16 copies of Q_k on
+ * the device from the FP64 copy (round to nearest even).  Synchronous.
+ * Errors: TS_ERR_INVALID, TS_ERR_NOMEM, TS_ERR_DEVICE.  A negative definite
+ * shift is not an error here (the propagator does not need it); the inverse
+ * apply reports TS_ERR_NOT_SPD. */
+int ts_setup(int d, const int64_t* n, double L, const double* const* f, double sigma,
+             ts_plan** out);
+
+/* Release a plan and every device buffer it owns.  NULL is a no-op.
+ * Synchronises the device first, so pending work that uses the plan ends. */
+int ts_destroy(ts_plan* plan);
+
+/* --------------------------------------------------------------- applies -- */
+
+/* u = (H1 + sigma I)^{-1} b by the four steps of Sec. 2.1: forward transform
+ * with Q_k^T on every axis, divide by (sum_k lam_k[j_k] + sigma) formed in
+ * FP64, backward transform with Q_k.
+ *   b, u  : device arrays of prod(n) elements of dtype TS_F64 or TS_F32; u may
+ *           alias b (in place)
+ *   prec  : transform arithmetic (see ts_prec); FP64 requires dtype TS_F64
+ * Errors: TS_ERR_INVALID (dtype/prec), TS_ERR_NOT_SPD, TS_ERR_NOMEM. */
+int ts_apply_inverse(ts_plan* plan, const void* b, void* u, int dtype, int prec,
+                     void* hip_stream);
+
+/* Same, with an explicit shift s replacing the plan's sigma: u = (H1 + s)^{-1} b.
+ * Used for shifted inverse iteration, where s = -(shift) sits close to
+ * -lambda_1 and the denominators must be formed in FP64. */
+int ts_apply_inverse_shift(ts_plan* plan, double s, const void* b, void* u, int dtype, int prec,
+                           void* hip_stream);
+
+/* psi_out = exp(-i tau H1) psi_in (eq. (exact_prop)): forward transform,
+ * multiply by exp(-i tau sum_k lam_k[j_k]) (per-axis FP64 phase factors,
+ * multiplied together), backward transform.
+ *   psi_in, psi_out : device arrays of prod(n) complex elements (TS_C128 or
+ *                     TS_C64, interleaved); psi_out may alias psi_in
+ *   tau             : any real time step, including 0 and negative values
+ * Errors: TS_ERR_INVALID, TS_ERR_NOMEM. */
+int ts_apply_exp(ts_plan* plan, double tau, const void* psi_in, void* psi_out, int dtype, int prec,
+                 void* hip_stream);
+
+/* --------------------------------------------------------------- solvers -- */
+
+/* Solve (H1 + sigma I) u = f with the transforms in `inner` precision and
+ * FP64 iterative refinement: u <- u + M^{-1}(f - (H1 + sigma) u), the
+ * residual formed in FP64 with the (2d+1)-point stencil, until
+ * ||r||_2 / ||f||_2 <= rtol or maxit sweeps.  f, u: device FP64.
+ * u is an output (its input value is ignored).  If a sweep contracts the
+ * residual by less than a factor 0.9 twice, the remaining work switches to
+ * flexible CG with the same inner apply.  Synchronises.
+ *   iters  : (out, may be NULL) sweeps + CG iterations used
+ *   relres : (out, may be NULL) final true relative residual
+ * Errors: TS_ERR_NOCONV (u holds the last iterate), TS_ERR_NONFINITE. */
+int ts_solve_refined(ts_plan* plan, const double* f, double* u, int inner, double rtol, int maxit,
+                     int* iters, double* relres, void* hip_stream);
+
+/* PCG for (H1 + diag(V2) + sigma I) u = f (Sec. 3.2), preconditioner
+ * (H1 + sigma I)^{-1} applied in `precond` precision with FP64 input and
+ * output.  All vectors, inner products, alpha and beta are FP64 on the
+ * device; with a reduced-precision preconditioner beta takes the flexible
+ * (Polak-Ribiere) form <z_{k+1}, r_{k+1} - r_k> / <z_k, r_k>.
+ *   V2     : device FP64 array of prod(n) values, or NULL for V2 = 0
+ *   f      : device FP64 right-hand side
+ *   u      : device FP64; in: initial guess, out: solution
+ *   rtol   : stop when the recurrence residual ||r||/||f|| <= rtol; the true
+ *            residual is then recomputed with the stencil and reported
+ *   maxit  : iteration limit
+ * Synchronises.  Errors: TS_ERR_NOCONV, TS_ERR_BREAKDOWN, TS_ERR_NONFINITE,
+ * TS_ERR_NOT_SPD (H1 + sigma not positive definite). */
+int ts_pcg_solve(ts_plan* plan, const double* V2, const double* f, double* u, double rtol, int maxit,
+                 int precond, int* iters, double* relres, void* hip_stream);
+
+/* Shifted inverse iteration for the lowest eigenpair of H = H1 + diag(V2)
+ * (Sec. 4.1, Sec. 5.3.1).  Each step solves (H - shift) w = u by PCG
+ * (preconditioner (H1 - shift)^{-1} in `precond` precision, denominators in
+ * FP64), warm-started from the previous step's w, to pcg_rtol; then
+ * u <- w / ||w||_2 and lambda <- u^T H u.  The plan's sigma is not used.
+ *   V2        : device FP64 or NULL
+ *   u         : device FP64; in: start vector (need not be normalised),
+ *               out: final normalised eigenvector estimate
+ *   steps     : number of steps
+ *   lam_hist  : HOST array of steps + 1 doubles (lambda before the first
+ *               step, then after each step), may be NULL
+ *   pcg_iters : HOST array of `steps` ints, may be NULL
+ * Requires H - shift positive definite (shift below lambda_1(H)).
+ * Synchronises.  Errors: as ts_pcg_solve. */
+int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* u, int steps,
+                         double pcg_rtol, int maxit, int precond, double* lam_hist, int* pcg_iters,
+                         void* hip_stream);
+
+/* nsteps steps of a splitting scheme for i psi_t = (H1 + V2) psi (Sec. 5.1).
+ *   V2    : device array of prod(n) real values, FP64 for TS_C128 data and
+ *           FP32 for TS_C64 data
+ *   psi   : device complex array (TS_C128 or TS_C64), updated in place
+ *   dt    : time step; nsteps >= 0
+ *   prec  : transform arithmetic of the exact propagator of H1
+ * Errors: TS_ERR_INVALID, TS_ERR_NOMEM. */
+int ts_split_step(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme,
+                  int dtype, int prec, void* hip_stream);
+
+/* ---------------------------------------------------------- operators -- */
+
+/* out = (H1 + diag(V2) + s I) u by the (2d+1)-point stencil, FP64, zero ghost
+ * values (the operator of eq. (general_system)).  V2 may be NULL.  u and out
+ * must not alias.  Device FP64 arrays. */
+int ts_operator_apply(ts_plan* plan, const double* V2, double s, const double* u, double* out,
+                      void* hip_stream);
+
+/* ---------------------------------------------------------- accessors -- */
+
+/* Host copy of the ascending eigenvalues of H_axis (n[axis] doubles). */
+int ts_eigvals(const ts_plan* plan, int axis, double* out);
+
+/* Host copy of Q_axis, row-major, column j = unit eigenvector of lam[j]
+ * (n[axis]^2 doubles).  Eigenvectors are unique up to sign only. */
+int ts_eigvecs(const ts_plan* plan, int axis, double* out);
+
+/* Device bytes a single apply of the given dtype may allocate as scratch. */
+int ts_workspace_bytes(const ts_plan* plan, int dtype, size_t* bytes);
+
+/* Host FP64 eigendecomposition of the symmetric tridiagonal matrix with
+ * diagonal diag[0..n-1] and off-diagonal off[0..n-2] by implicit QL
+ * (the per-axis step of eq. (eigen_decomp) that ts_setup runs).  Needs no
+ * GPU.  lam: n ascending eigenvalues; Q: row-major n x n, column j = unit
+ * eigenvector of lam[j], sign chosen so its largest-magnitude entry is
+ * positive.  Host pointers.  Errors: TS_ERR_INVALID, TS_ERR_NOCONV. */
+int ts_tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* ts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TS_H */

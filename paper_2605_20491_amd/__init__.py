@@ -1,0 +1,293 @@
+"""Python binding of libts.so, the MI355X separable tensor-product solver.
+
+Thin marshalling over the C ABI declared in ``include/ts.h``: every function
+has the name of the C entry point it calls and does no arithmetic of its own.
+PyTorch provides device memory (tensors) and streams only.  There is no CPU
+fallback: importing a function whose library is missing raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libts.so")
+
+TS_OK, TS_ERR_INVALID, TS_ERR_NOT_SPD, TS_ERR_NOMEM, TS_ERR_DEVICE = 0, 1, 2, 3, 4
+TS_ERR_NOCONV, TS_ERR_NONFINITE, TS_ERR_BUSY, TS_ERR_BREAKDOWN = 5, 6, 7, 8
+STATUS_NAMES = {0: "TS_OK", 1: "TS_ERR_INVALID", 2: "TS_ERR_NOT_SPD", 3: "TS_ERR_NOMEM",
+                4: "TS_ERR_DEVICE", 5: "TS_ERR_NOCONV", 6: "TS_ERR_NONFINITE", 7: "TS_ERR_BUSY",
+                8: "TS_ERR_BREAKDOWN"}
+TS_F64, TS_F32, TS_C128, TS_C64 = 0, 1, 2, 3
+TS_PREC_FP64, TS_PREC_FP32, TS_PREC_BF16 = 0, 1, 2
+TS_STRANG_BAB, TS_STRANG_ABA, TS_YOSHIDA_BAB, TS_YOSHIDA_ABA = 0, 1, 2, 3
+
+PREC = {"fp64": TS_PREC_FP64, "fp32": TS_PREC_FP32, "bf16": TS_PREC_BF16}
+SCHEME = {"strang_bab": TS_STRANG_BAB, "strang_aba": TS_STRANG_ABA,
+          "yoshida_bab": TS_YOSHIDA_BAB, "yoshida_aba": TS_YOSHIDA_ABA}
+
+
+class TSError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        self.code = code
+        self.status = STATUS_NAMES.get(code, str(code))
+        super().__init__("%s: %s (%s)" % (where, self.status, msg))
+
+
+_lib = None
+_vp, _dp, _ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    """Load libts.so (built by paper_2605_20491_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libts.so is not built (%s); run paper_2605_20491_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "ts_setup": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_double,
+                         ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
+            "ts_destroy": [_vp],
+            "ts_apply_inverse": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
+            "ts_apply_inverse_shift": [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
+            "ts_apply_exp": [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
+            "ts_solve_refined": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _dp, _vp],
+            "ts_pcg_solve": [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp, _vp],
+            "ts_inverse_iteration": [_vp, _vp, ctypes.c_double, _vp, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_int, _dp, _ip, _vp],
+            "ts_split_step": [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_int, _vp],
+            "ts_operator_apply": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp],
+            "ts_eigvals": [_vp, ctypes.c_int, _dp],
+            "ts_eigvecs": [_vp, ctypes.c_int, _dp],
+            "ts_workspace_bytes": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+            "ts_tridiag_eig": [ctypes.c_int64, _dp, _dp, _dp, _dp],
+        }
+        for name, argt in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = argt
+            fn.restype = ctypes.c_int
+        L.ts_last_error.argtypes = []
+        L.ts_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def ts_last_error() -> str:
+    return lib().ts_last_error().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != TS_OK:
+        raise TSError(rc, where, ts_last_error())
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+# ---------------------------------------------------------------- torch glue --
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+_DTYPE_CODES = None
+
+
+def _dtype_code(t) -> int:
+    global _DTYPE_CODES
+    torch = _torch()
+    if _DTYPE_CODES is None:
+        _DTYPE_CODES = {torch.float64: TS_F64, torch.float32: TS_F32,
+                        torch.complex128: TS_C128, torch.complex64: TS_C64}
+    if t.dtype not in _DTYPE_CODES:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return _DTYPE_CODES[t.dtype]
+
+
+def _dev(t, plan, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if plan is not None and t.numel() != plan.N:
+        raise ValueError("%s has %d elements, the grid has %d" % (name, t.numel(), plan.N))
+    return _vp(t.data_ptr())
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+class Plan:
+    """Owner of a ts_plan*; released by ts_destroy when collected."""
+
+    def __init__(self, handle, shape, L, sigma):
+        self._h = handle
+        self.shape = tuple(int(s) for s in shape)
+        self.d = len(self.shape)
+        self.N = int(np.prod(self.shape))
+        self.L = float(L)
+        self.sigma = float(sigma)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.ts_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ entries --
+
+def ts_setup(shape, L: float, f_list, sigma: float) -> Plan:
+    d = len(shape)
+    n = (ctypes.c_int64 * d)(*[int(s) for s in shape])
+    fs = [np.ascontiguousarray(f, dtype=np.float64) for f in f_list]
+    if len(fs) != d or any(f.shape != (int(s),) for f, s in zip(fs, shape)):
+        raise ValueError("f_list must hold one array of n_k samples per axis")
+    fp = (_dp * d)(*[_dptr(f) for f in fs])
+    h = _vp()
+    _check(lib().ts_setup(d, n, float(L), fp, float(sigma), ctypes.byref(h)), "ts_setup")
+    return Plan(h, shape, L, sigma)
+
+
+def ts_destroy(plan: Plan):
+    plan.close()
+
+
+def ts_apply_inverse(plan: Plan, b, u=None, prec="fp64", stream=None):
+    torch = _torch()
+    if u is None:
+        u = torch.empty_like(b)
+    _check(lib().ts_apply_inverse(plan.handle, _dev(b, plan, "b"), _dev(u, plan, "u"), _dtype_code(b),
+                                  _prec(prec), _stream(stream)), "ts_apply_inverse")
+    return u
+
+
+def ts_apply_inverse_shift(plan: Plan, s: float, b, u=None, prec="fp64", stream=None):
+    torch = _torch()
+    if u is None:
+        u = torch.empty_like(b)
+    _check(lib().ts_apply_inverse_shift(plan.handle, float(s), _dev(b, plan, "b"), _dev(u, plan, "u"),
+                                        _dtype_code(b), _prec(prec), _stream(stream)),
+           "ts_apply_inverse_shift")
+    return u
+
+
+def ts_apply_exp(plan: Plan, tau: float, psi, out=None, prec="fp64", stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(psi)
+    _check(lib().ts_apply_exp(plan.handle, float(tau), _dev(psi, plan, "psi"), _dev(out, plan, "out"),
+                              _dtype_code(psi), _prec(prec), _stream(stream)), "ts_apply_exp")
+    return out
+
+
+def ts_solve_refined(plan: Plan, f, u=None, inner="fp32", rtol=1e-10, maxit=50, stream=None):
+    torch = _torch()
+    if u is None:
+        u = torch.empty_like(f)
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    rc = lib().ts_solve_refined(plan.handle, _dev(f, plan, "f"), _dev(u, plan, "u"), _prec(inner),
+                                float(rtol), int(maxit), ctypes.byref(it), ctypes.byref(rr),
+                                _stream(stream))
+    _check(rc, "ts_solve_refined")
+    return u, it.value, rr.value
+
+
+def ts_pcg_solve(plan: Plan, V2, f, u=None, rtol=1e-10, maxit=500, precond="fp64", stream=None,
+                 raise_on_noconv=True):
+    torch = _torch()
+    if u is None:
+        u = torch.zeros_like(f)
+    it, rr = ctypes.c_int(0), ctypes.c_double(0.0)
+    rc = lib().ts_pcg_solve(plan.handle, _dev(V2, plan, "V2"), _dev(f, plan, "f"), _dev(u, plan, "u"),
+                            float(rtol), int(maxit), _prec(precond), ctypes.byref(it), ctypes.byref(rr),
+                            _stream(stream))
+    if rc == TS_ERR_NOCONV and not raise_on_noconv:
+        return u, it.value, rr.value, rc
+    _check(rc, "ts_pcg_solve")
+    return u, it.value, rr.value, rc
+
+
+def ts_inverse_iteration(plan: Plan, V2, shift: float, u, steps=20, pcg_rtol=1e-10, maxit=500,
+                         precond="fp64", stream=None):
+    lam = np.zeros(steps + 1)
+    its = (ctypes.c_int * steps)()
+    rc = lib().ts_inverse_iteration(plan.handle, _dev(V2, plan, "V2"), float(shift), _dev(u, plan, "u"),
+                                    int(steps), float(pcg_rtol), int(maxit), _prec(precond), _dptr(lam),
+                                    its, _stream(stream))
+    _check(rc, "ts_inverse_iteration")
+    return u, lam, list(its)
+
+
+def ts_split_step(plan: Plan, V2, psi, dt: float, nsteps: int, scheme="strang_bab", prec="fp64",
+                  stream=None):
+    sch = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
+    _check(lib().ts_split_step(plan.handle, _dev(V2, plan, "V2"), _dev(psi, plan, "psi"), float(dt),
+                               int(nsteps), sch, _dtype_code(psi), _prec(prec), _stream(stream)),
+           "ts_split_step")
+    return psi
+
+
+def ts_operator_apply(plan: Plan, V2, s: float, u, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(u)
+    _check(lib().ts_operator_apply(plan.handle, _dev(V2, plan, "V2"), float(s), _dev(u, plan, "u"),
+                                   _dev(out, plan, "out"), _stream(stream)), "ts_operator_apply")
+    return out
+
+
+def ts_eigvals(plan: Plan, axis: int) -> np.ndarray:
+    out = np.empty(plan.shape[axis])
+    _check(lib().ts_eigvals(plan.handle, int(axis), _dptr(out)), "ts_eigvals")
+    return out
+
+
+def ts_eigvecs(plan: Plan, axis: int) -> np.ndarray:
+    n = plan.shape[axis]
+    out = np.empty((n, n))
+    _check(lib().ts_eigvecs(plan.handle, int(axis), _dptr(out)), "ts_eigvecs")
+    return out
+
+
+def ts_workspace_bytes(plan: Plan, dtype: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().ts_workspace_bytes(plan.handle, int(dtype), ctypes.byref(b)), "ts_workspace_bytes")
+    return b.value
+
+
+def ts_tridiag_eig(diag: np.ndarray, off: np.ndarray):
+    diag = np.ascontiguousarray(diag, dtype=np.float64)
+    off = np.ascontiguousarray(off, dtype=np.float64)
+    n = diag.size
+    lam = np.empty(n)
+    Q = np.empty((n, n))
+    offp = _dptr(off) if off.size else _dptr(np.zeros(1))
+    _check(lib().ts_tridiag_eig(n, _dptr(diag), offp, _dptr(lam), _dptr(Q)), "ts_tridiag_eig")
+    return lam, Q

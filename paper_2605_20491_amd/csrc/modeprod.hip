@@ -1,0 +1,394 @@
+// Mode-k contraction passes of the separable apply on CDNA4 (gfx950) MFMA.
+//
+// One pass computes, for a grid function X viewed as [P][n][R] (axis k has
+// extent n, P = product of the slower extents, R = product of the faster
+// extents times 2 for interleaved complex data):
+//     forward  (paper Sec. 2.1 step 2):  Y[p, j, r] = sum_i Q[i][j] X[p, i, r]
+//     backward (paper Sec. 2.1 step 4):  Y[p, j, r] = sum_i Q[j][i] X[p, i, r]
+// as a GEMM on the 16x16x4 FP64 / FP32 matrix cores:
+//   "column" passes (any axis but the fastest): for each p, C = A B with
+//       A = the n x n factor (resident, LDS-staged), B = X[p] (n x R, R contiguous)
+//   "row" passes (fastest axis, R == 1 or 2): C = A B with
+//       A = X viewed as (P or 2P) x n rows (streamed, transposed into LDS),
+//       B = the n x n factor.
+// The factor matrices are stored k-major and zero-padded by the plan, so their
+// tiles load without predicates; data tiles are predicated and zero-filled.
+// The last forward pass optionally scales each output in its epilogue:
+//     Inv: y / (lam_k[j] + Lp[p] + Lr[q] + shift)       (FP64 denominator)
+//     Exp: y * es[j] * Ep[p] * Er[q]                     (FP64 phase factors)
+// where q indexes the faster axes (r, or r/2 for complex data).
+#include "ts_internal.h"
+
+namespace ts {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 16, NT = 256;
+constexpr int LDS_LD = BM + 4;  // padded LDS row length (elements)
+
+template <typename T> struct AccT;
+template <> struct AccT<double> { using V = d4; };
+template <> struct AccT<float> { using V = f4; };
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Row (within a 16x16 output block) of accumulator element r held by lane l.
+// Measured on gfx950: the FP64 form interleaves rows across lane groups.
+template <typename T> __device__ __forceinline__ int out_row(int l, int r);
+template <> __device__ __forceinline__ int out_row<double>(int l, int r) { return (l >> 4) + 4 * r; }
+template <> __device__ __forceinline__ int out_row<float>(int l, int r) { return 4 * (l >> 4) + r; }
+
+// ---- element conversions ----
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+template <typename TIn, typename TC> __device__ __forceinline__ TC cvt_in(TIn x);
+template <> __device__ __forceinline__ double cvt_in<double, double>(double x) { return x; }
+template <> __device__ __forceinline__ float cvt_in<double, float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ float cvt_in<float, float>(float x) { return x; }
+template <> __device__ __forceinline__ double cvt_in<float, double>(float x) { return (double)x; }
+template <> __device__ __forceinline__ float cvt_in<uint16_t, float>(uint16_t x) { return bf16_to_f32(x); }
+
+template <typename TOut> __device__ __forceinline__ TOut cvt_out(double x);
+template <> __device__ __forceinline__ double cvt_out<double>(double x) { return x; }
+template <> __device__ __forceinline__ float cvt_out<float>(double x) { return (float)x; }
+template <> __device__ __forceinline__ uint16_t cvt_out<uint16_t>(double x) { return f32_to_bf16((float)x); }
+
+struct KArgs {
+  const void* X;
+  void* Y;
+  const void* S;      // resident factor, [kpad][ld], k-major
+  int64_t ld;
+  int64_t P, n, R;    // data view [P][n][R]
+  int64_t M, N;       // GEMM extents (K = n)
+  int64_t mt, nt;     // tiles along M and N
+  int64_t nblocks;
+  const double* lam;  // epilogue tables
+  const double* Lp;
+  const double* Lr;
+  double shift;
+  const double2* Ep;
+  const double2* Er;
+  const double2* es;
+  const int* skip;
+};
+
+// Map the hardware block id to a logical tile id so that consecutive logical
+// tiles (which share an operand panel) run on the same XCD: blocks are handed
+// to the 8 XCDs round-robin.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t bid, int64_t nblocks) {
+  int64_t q = nblocks / 8, rmd = nblocks % 8;
+  int64_t x = bid % 8, loc = bid / 8;
+  return x * q + (x < rmd ? x : rmd) + loc;
+}
+
+template <typename TC, typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI>
+__global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
+  if (a.skip && *a.skip) return;
+  __shared__ TC As[2][BK][LDS_LD];
+  __shared__ TC Bs[2][BK][LDS_LD];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  const int64_t lb = xcd_logical_block(blockIdx.x, a.nblocks);
+  int64_t p = 0, mtile, ntile;
+  if (ROWS) {
+    mtile = lb / a.nt;
+    ntile = lb % a.nt;
+  } else {
+    mtile = lb % a.mt;
+    int64_t rest = lb / a.mt;
+    ntile = rest % a.nt;
+    p = rest / a.nt;
+  }
+  const int64_t m0 = mtile * BM, n0 = ntile * BN;
+  const int64_t K = a.n;
+  const TIn* X = (const TIn*)a.X;
+  const TC* S = (const TC*)a.S;
+
+  TC rres[8];
+  TIn rdat[8];
+
+  // ---- global -> registers for k-tile kt ----
+  auto load_tile = [&](int64_t k0) {
+    // resident factor tile: rows k0..k0+BK-1, columns f0..f0+127 (always in bounds)
+    const int64_t f0 = ROWS ? n0 : m0;
+    const int c = t & 127, r0 = t >> 7;
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      int r = r0 + 2 * it;
+      rres[it] = S[(k0 + r) * a.ld + f0 + c];
+    }
+    if (!ROWS) {
+      // B = X[p] rows k, columns n0..n0+127
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        int r = r0 + 2 * it;
+        int64_t k = k0 + r, col = n0 + c;
+        rdat[it] = (k < K && col < a.R) ? X[(p * a.n + k) * a.R + col] : (TIn)0;
+      }
+    } else if (!CPLX) {
+      const int kk = t & 15, mr = t >> 4;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        int64_t m = m0 + mr + 16 * it, k = k0 + kk;
+        rdat[it] = (m < a.M && k < K) ? X[m * a.n + k] : (TIn)0;
+      }
+    } else {
+      const int kk = (t & 31) >> 1, cc = t & 1, pr = t >> 5;
+      const int64_t pb = m0 >> 1;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        int64_t pp = pb + pr + 8 * it, k = k0 + kk;
+        rdat[it] = (pp < a.P && k < K) ? X[((pp * a.n + k) << 1) + cc] : (TIn)0;
+      }
+    }
+  };
+  auto store_tile = [&](int buf) {
+    const int c = t & 127, r0 = t >> 7;
+    TC(*Res)[LDS_LD] = ROWS ? Bs[buf] : As[buf];
+#pragma unroll
+    for (int it = 0; it < 8; ++it) Res[r0 + 2 * it][c] = rres[it];
+    if (!ROWS) {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) Bs[buf][r0 + 2 * it][c] = cvt_in<TIn, TC>(rdat[it]);
+    } else if (!CPLX) {
+      const int kk = t & 15, mr = t >> 4;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) As[buf][kk][mr + 16 * it] = cvt_in<TIn, TC>(rdat[it]);
+    } else {
+      const int kk = (t & 31) >> 1, cc = t & 1, pr = t >> 5;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) As[buf][kk][2 * (pr + 8 * it) + cc] = cvt_in<TIn, TC>(rdat[it]);
+    }
+  };
+
+  using V = typename AccT<TC>::V;
+  V acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int krow = kk * 4 + lk;
+      TC av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = As[cur][krow][wm * 64 + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[cur][krow][wn * 64 + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue ----
+  TOut* Y = (TOut*)a.Y;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 64 + i * 16 + out_row<TC>(lane, r);
+        const int64_t col = n0 + wn * 64 + j * 16 + lr;
+        double v = (double)acc[i][j][r];
+        if (ROWS) {
+          if (m < a.M && col < a.n) {
+            if (!CPLX) Y[m * a.n + col] = cvt_out<TOut>(v);
+            else Y[(((m >> 1) * a.n + col) << 1) + (m & 1)] = cvt_out<TOut>(v);
+          }
+        } else {
+          if (EPI == (int)Epi::Exp) {
+            // (re, im) of one element sit in lanes 2u, 2u+1 (columns col, col^1)
+            double partner = __shfl_xor(v, 1);
+            if (m < a.n && col < a.R) {
+              double2 f1 = a.es[m], f2 = a.Ep[p], f3 = a.Er[col >> 1];
+              double fr = f1.x * f2.x - f1.y * f2.y, fi = f1.x * f2.y + f1.y * f2.x;
+              double gr = fr * f3.x - fi * f3.y, gi = fr * f3.y + fi * f3.x;
+              v = (col & 1) ? (gi * partner + gr * v) : (gr * v - gi * partner);
+            }
+          } else if (EPI == (int)Epi::Inv) {
+            if (m < a.n && col < a.R) {
+              const int64_t q = CPLX ? (col >> 1) : col;
+              double den = a.lam[m] + a.Lp[p] + a.Lr[q] + a.shift;
+              v = v / den;
+            }
+          }
+          if (m < a.n && col < a.R) Y[(p * a.n + m) * a.R + col] = cvt_out<TOut>(v);
+        }
+      }
+    }
+  }
+}
+
+template <typename TC, typename TIn, typename TOut>
+hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
+  KArgs a{};
+  a.X = pa.X;
+  a.Y = pa.Y;
+  const AxisFactor* F = pa.fac;
+  if (std::is_same<TC, double>::value) a.S = pa.forward ? (const void*)F->Q64 : (const void*)F->QT64;
+  else a.S = pa.forward ? (const void*)F->Q32 : (const void*)F->QT32;
+  a.ld = F->ld;
+  a.P = pa.P;
+  a.n = pa.n;
+  a.R = pa.R;
+  a.lam = F->lam;
+  a.Lp = pa.Lp;
+  a.Lr = pa.Lr;
+  a.shift = pa.shift;
+  a.Ep = pa.Ep;
+  a.Er = pa.Er;
+  a.es = pa.es;
+  a.skip = pa.skip;
+  const bool rows = (pa.R == 1 || (pa.cplx && pa.R == 2)) && pa.epi == Epi::None;
+  if (rows) {
+    a.M = pa.P * (pa.cplx ? 2 : 1);
+    a.N = pa.n;
+    a.mt = (a.M + BM - 1) / BM;
+    a.nt = (a.N + BN - 1) / BN;
+    a.nblocks = a.mt * a.nt;
+  } else {
+    a.M = pa.n;
+    a.N = pa.R;
+    a.mt = (a.M + BM - 1) / BM;
+    a.nt = (a.N + BN - 1) / BN;
+    a.nblocks = a.mt * a.nt * pa.P;
+  }
+  if (a.nblocks <= 0) return hipSuccess;
+  if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)a.nblocks), block(NT);
+  if (rows) {
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, true, 0>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, false, 0>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Exp) {
+    if (!pa.cplx) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Exp>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Inv) {
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Inv>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, (int)Epi::Inv>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, 0>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pass(const PassArgs& pa, hipStream_t st) {
+  if (pa.prec == 0) {
+    if (pa.tin != DT::F64 || pa.tout != DT::F64) return hipErrorInvalidValue;
+    return launch_typed<double, double, double>(pa, st);
+  }
+  if (pa.prec == 1) {
+    if (pa.tin == DT::F64 && pa.tout == DT::F64) return launch_typed<float, double, double>(pa, st);
+    if (pa.tin == DT::F64 && pa.tout == DT::F32) return launch_typed<float, double, float>(pa, st);
+    if (pa.tin == DT::F32 && pa.tout == DT::F32) return launch_typed<float, float, float>(pa, st);
+    if (pa.tin == DT::F32 && pa.tout == DT::F64) return launch_typed<float, float, double>(pa, st);
+    return hipErrorInvalidValue;
+  }
+  return hipErrorInvalidValue;  // bf16 passes live in modeprod_bf16.hip
+}
+
+// ---------------------------------------------------------------------------
+// Phase tables of the propagator (FP64): products of per-axis factors
+// e^{-i tau lam}.  Entry ranges: [0, P) -> Ep, [P, P+R) -> Er, then es.
+// ---------------------------------------------------------------------------
+__global__ void k_phase_tables(PhaseTableArgs a) {
+  const int64_t total = a.P + a.R + a.n[a.s];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double re = 1.0, im = 0.0;
+    int lo, hi;
+    int64_t idx;
+    double2* dst;
+    if (e < a.P) { lo = 0; hi = a.s; idx = e; dst = a.Ep + e; }
+    else if (e < a.P + a.R) { lo = a.s + 1; hi = a.d; idx = e - a.P; dst = a.Er + (e - a.P); }
+    else { lo = a.s; hi = a.s + 1; idx = e - a.P - a.R; dst = a.es + idx; }
+    for (int k = hi - 1; k >= lo; --k) {
+      int64_t j = idx % a.n[k];
+      idx /= a.n[k];
+      double sn, cs;
+      sincos(a.tau * a.lam[k][j], &sn, &cs);
+      // multiply by (cs - i sn)
+      double nr = re * cs + im * sn, ni = im * cs - re * sn;
+      re = nr;
+      im = ni;
+    }
+    *dst = make_double2(re, im);
+  }
+}
+
+hipError_t launch_phase_tables(const PhaseTableArgs& a, hipStream_t st) {
+  int64_t total = a.P + a.R + a.n[a.s];
+  int blocks = (int)std::min<int64_t>(4096, (total + 255) / 256);
+  hipLaunchKernelGGL(k_phase_tables, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+__global__ void k_cast_f32(const double* x, float* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void k_cast_bf16(const double* x, uint16_t* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    // round FP64 -> BF16 directly to nearest even (no intermediate FP32 rounding)
+    double v = x[i];
+    uint64_t u = __double_as_longlong(v);
+    uint64_t sign = u >> 63;
+    double av = fabs(v);
+    float f = (float)av;  // candidate; fix up by comparing the two bf16 neighbours in FP64
+    uint32_t fb = __float_as_uint(f) & 0xffff0000u;
+    float lo = __uint_as_float(fb), hi = __uint_as_float(fb + 0x10000u);
+    double dlo = av - (double)lo, dhi = (double)hi - av;
+    uint32_t pick;
+    if (dlo < dhi) pick = fb;
+    else if (dhi < dlo) pick = fb + 0x10000u;
+    else pick = ((fb >> 16) & 1u) ? fb + 0x10000u : fb;
+    if (av == 0.0) pick = 0;
+    y[i] = (uint16_t)((pick >> 16) | (sign << 15));
+  }
+}
+
+hipError_t launch_cast_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_f32, dim3(blocks), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+hipError_t launch_cast_f64_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_bf16, dim3(blocks), dim3(256), 0, st, x, y, n);
+  return hipGetLastError();
+}
+
+}  // namespace ts

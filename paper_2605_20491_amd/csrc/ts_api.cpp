@@ -1,0 +1,380 @@
+// C ABI of the separable tensor-product solver: plan setup (paper Sec. 2.1,
+// step 1), the inverse and propagator applies (steps 2-4, eq. (exact_prop)),
+// accessors and error plumbing.  Solvers built on the applies live in
+// solvers.cpp.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ts.h"
+#include "ts_internal.h"
+#include "ts_apply.h"
+
+namespace ts {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+AxisFactor::~AxisFactor() {
+  hipFree(lam);
+  hipFree(f);
+  hipFree(Q64);
+  hipFree(QT64);
+  hipFree(Q32);
+  hipFree(QT32);
+  hipFree(Q16);
+  hipFree(QT16);
+}
+
+// Build and upload the factors of H = h^-2 tridiag(-1,2,-1) + diag(f).
+static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<AxisFactor>& out) {
+  auto F = std::make_shared<AxisFactor>();
+  F->n = n;
+  F->L = L;
+  F->ld = round_up(n, kTileF);
+  F->kpad = round_up(n, kTileK);
+  const double h = 2.0 * L / (double)(n + 1);
+  const double ih2 = 1.0 / (h * h);
+  F->ih2 = ih2;
+  std::vector<double> dg(n), off(n > 1 ? n - 1 : 1, 0.0);
+  for (int64_t i = 0; i < n; ++i) dg[i] = 2.0 * ih2 + f[i];
+  for (int64_t i = 0; i + 1 < n; ++i) off[i] = -ih2;
+  F->lam_h.resize(n);
+  F->Q_h.resize((size_t)(n * n));
+  if (!tridiag_eig(n, dg.data(), off.data(), F->lam_h.data(), F->Q_h.data())) {
+    set_error("tridiagonal eigensolver did not converge");
+    return TS_ERR_INVALID;
+  }
+  const size_t padded = (size_t)(F->kpad * F->ld);
+  std::vector<double> Qp(padded, 0.0), QTp(padded, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      Qp[(size_t)(i * F->ld + j)] = F->Q_h[(size_t)(i * n + j)];
+      QTp[(size_t)(j * F->ld + i)] = F->Q_h[(size_t)(i * n + j)];
+    }
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&F->lam, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&F->f, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&F->Q64, sizeof(double) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F->QT64, sizeof(double) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F->Q32, sizeof(float) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F->QT32, sizeof(float) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F->Q16, sizeof(uint16_t) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F->QT16, sizeof(uint16_t) * padded);
+  if (e != hipSuccess) {
+    set_error(std::string("device allocation of factors failed: ") + hipGetErrorString(e));
+    return TS_ERR_NOMEM;
+  }
+  e = hipMemcpy(F->lam, F->lam_h.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(F->f, f, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(F->Q64, Qp.data(), sizeof(double) * padded, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(F->QT64, QTp.data(), sizeof(double) * padded, hipMemcpyHostToDevice);
+  // reduced-precision copies are cast on the device from the FP64 copy
+  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->Q64, F->Q32, (int64_t)padded, 0);
+  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->QT64, F->QT32, (int64_t)padded, 0);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->Q64, F->Q16, (int64_t)padded, 0);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->QT64, F->QT16, (int64_t)padded, 0);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    set_error(std::string("factor upload failed: ") + hipGetErrorString(e));
+    return TS_ERR_DEVICE;
+  }
+  out = F;
+  return TS_OK;
+}
+
+// Scratch of at least `bytes` owned by the plan (grown on demand).  Growing
+// synchronises the device so that no queued kernel still uses the old buffer.
+int plan_workspace(ts_plan* p, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> g(p->mu);
+  if (p->work_bytes < bytes) {
+    if (p->work) {
+      hipDeviceSynchronize();
+      hipFree(p->work);
+      p->work = nullptr;
+      p->work_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p->work, bytes);
+    if (e != hipSuccess) {
+      p->work = nullptr;
+      set_error("workspace allocation of " + std::to_string(bytes) + " bytes failed");
+      return TS_ERR_NOMEM;
+    }
+    p->work_bytes = bytes;
+  }
+  *out = p->work;
+  return TS_OK;
+}
+
+static DT dt_of(int dtype) { return (dtype == TS_F64 || dtype == TS_C128) ? DT::F64 : DT::F32; }
+
+// Run the 2d passes of one apply.  Intermediates have the precision's type.
+int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
+  const int d = p->d;
+  const bool cplx = ap.cplx;
+  const int ncomp = cplx ? 2 : 1;
+  DT inter = ap.prec == TS_PREC_FP64 ? DT::F64 : (ap.prec == TS_PREC_FP32 ? DT::F32 : DT::BF16);
+  // pass order: forward over every axis but s (fastest first), then s with the
+  // scaling epilogue; backward over s first, then the others.
+  std::vector<int> order;
+  for (int k = d - 1; k >= 0; --k)
+    if (k != p->s) order.push_back(k);
+  order.push_back(p->s);
+  const int T = 2 * d;
+  const void* src = ap.in;
+  DT src_t = ap.tin;
+  for (int t = 1; t <= T; ++t) {
+    const bool fwd = t <= d;
+    const int k = fwd ? order[t - 1] : (t == d + 1 ? p->s : order[t - d - 2]);
+    void* dst = ((T - t) % 2 == 0) ? ap.out : ap.work;
+    DT dst_t = (t == T) ? ap.tout : inter;
+    PassArgs pa;
+    pa.X = src;
+    pa.Y = dst;
+    pa.tin = src_t;
+    pa.tout = dst_t;
+    pa.prec = ap.prec;
+    pa.fac = p->ax[k].get();
+    pa.forward = fwd;
+    pa.n = p->n[k];
+    pa.P = 1;
+    for (int m = 0; m < k; ++m) pa.P *= p->n[m];
+    pa.R = (int64_t)ncomp;
+    for (int m = k + 1; m < d; ++m) pa.R *= p->n[m];
+    pa.cplx = cplx;
+    pa.skip = ap.skip;
+    if (fwd && t == d) {
+      pa.epi = ap.epi;
+      pa.Lp = p->Lp;
+      pa.Lr = p->Lr;
+      pa.shift = ap.shift;
+      pa.Ep = p->phase;
+      pa.Er = p->phase + p->Ps;
+      pa.es = p->phase + p->Ps + p->Rs;
+    }
+    hipError_t e = launch_pass(pa, st);
+    if (e != hipSuccess) {
+      set_error(std::string("mode pass launch failed: ") + hipGetErrorString(e));
+      return TS_ERR_DEVICE;
+    }
+    src = dst;
+    src_t = dst_t;
+  }
+  return TS_OK;
+}
+
+int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
+                       hipStream_t st, void* work, const int* skip) {
+  if (!p || !b || !u) { set_error("null argument"); return TS_ERR_INVALID; }
+  if (dtype != TS_F64 && dtype != TS_F32) { set_error("inverse apply needs TS_F64 or TS_F32 data"); return TS_ERR_INVALID; }
+  if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
+  if (prec == TS_PREC_FP64 && dtype != TS_F64) { set_error("FP64 transforms need TS_F64 data"); return TS_ERR_INVALID; }
+  if (!(p->lam_min + shift > 0.0)) {
+    set_error("H1 + sigma is not positive definite: lambda_min(H1) + sigma = " + std::to_string(p->lam_min + shift));
+    return TS_ERR_NOT_SPD;
+  }
+  if (!work) {
+    int rc = plan_workspace(p, (size_t)p->N * 8, &work);
+    if (rc) return rc;
+  }
+  ApplyParams ap;
+  ap.in = b;
+  ap.out = u;
+  ap.work = work;
+  ap.tin = ap.tout = dt_of(dtype);
+  ap.prec = prec;
+  ap.cplx = false;
+  ap.epi = Epi::Inv;
+  ap.shift = shift;
+  ap.skip = skip;
+  return run_apply(p, ap, st);
+}
+
+int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
+                   hipStream_t st, void* work) {
+  if (!p || !in || !out) { set_error("null argument"); return TS_ERR_INVALID; }
+  if (dtype != TS_C128 && dtype != TS_C64) { set_error("propagator needs TS_C128 or TS_C64 data"); return TS_ERR_INVALID; }
+  if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
+  if (prec == TS_PREC_FP64 && dtype != TS_C128) { set_error("FP64 transforms need TS_C128 data"); return TS_ERR_INVALID; }
+  if (!std::isfinite(tau)) { set_error("tau is not finite"); return TS_ERR_INVALID; }
+  if (!work) {
+    int rc = plan_workspace(p, (size_t)p->N * 16, &work);
+    if (rc) return rc;
+  }
+  PhaseTableArgs pt;
+  pt.d = p->d;
+  pt.s = p->s;
+  for (int k = 0; k < p->d; ++k) {
+    pt.n[k] = p->n[k];
+    pt.lam[k] = p->ax[k]->lam;
+  }
+  pt.tau = tau;
+  pt.Ep = p->phase;
+  pt.Er = p->phase + p->Ps;
+  pt.es = p->phase + p->Ps + p->Rs;
+  pt.P = p->Ps;
+  pt.R = p->Rs;
+  hipError_t e = launch_phase_tables(pt, st);
+  if (e != hipSuccess) { set_error("phase table launch failed"); return TS_ERR_DEVICE; }
+  ApplyParams ap;
+  ap.in = in;
+  ap.out = out;
+  ap.work = work;
+  ap.tin = ap.tout = dt_of(dtype);
+  ap.prec = prec;
+  ap.cplx = true;
+  ap.epi = Epi::Exp;
+  return run_apply(p, ap, st);
+}
+
+}  // namespace ts
+
+ts_plan::~ts_plan() {
+  hipFree(Lp);
+  hipFree(Lr);
+  hipFree(work);
+  hipFree(phase);
+}
+
+using namespace ts;
+
+extern "C" {
+
+const char* ts_last_error(void) { return g_err.c_str(); }
+
+int ts_setup(int d, const int64_t* n, double L, const double* const* f, double sigma, ts_plan** out) {
+  set_error("");
+  if (!out || !n || !f) { set_error("null argument"); return TS_ERR_INVALID; }
+  *out = nullptr;
+  if (d < 1 || d > TS_MAX_D) { set_error("d must be in [1, 12]"); return TS_ERR_INVALID; }
+  if (!(L > 0.0) || !std::isfinite(L)) { set_error("L must be positive"); return TS_ERR_INVALID; }
+  if (!std::isfinite(sigma)) { set_error("sigma must be finite"); return TS_ERR_INVALID; }
+  int64_t N = 1;
+  for (int k = 0; k < d; ++k) {
+    if (n[k] < 1 || n[k] > 16384) { set_error("n[k] must be in [1, 16384]"); return TS_ERR_INVALID; }
+    if (!f[k]) { set_error("f[k] is null"); return TS_ERR_INVALID; }
+    for (int64_t j = 0; j < n[k]; ++j)
+      if (!std::isfinite(f[k][j])) { set_error("f[k] has a non-finite sample"); return TS_ERR_NONFINITE; }
+    N *= n[k];
+    if (N >= (int64_t(1) << 40)) { set_error("grid too large"); return TS_ERR_INVALID; }
+  }
+  auto p = std::unique_ptr<ts_plan>(new ts_plan());
+  p->d = d;
+  p->N = N;
+  p->L = L;
+  p->sigma = sigma;
+  hipGetDevice(&p->device);
+  std::map<std::pair<int64_t, std::string>, std::shared_ptr<AxisFactor>> cache;
+  for (int k = 0; k < d; ++k) {
+    p->n[k] = n[k];
+    std::string key((const char*)f[k], sizeof(double) * (size_t)n[k]);
+    auto it = cache.find({n[k], key});
+    if (it != cache.end()) {
+      p->ax.push_back(it->second);
+      continue;
+    }
+    std::shared_ptr<AxisFactor> F;
+    int rc = build_axis(n[k], L, f[k], F);
+    if (rc) return rc;
+    cache[{n[k], key}] = F;
+    p->ax.push_back(F);
+  }
+  p->lam_min = 0.0;
+  for (int k = 0; k < d; ++k) p->lam_min += p->ax[k]->lam_h[0];
+  // scaling axis: a non-fastest axis balancing the two table lengths
+  p->s = 0;
+  if (d >= 2) {
+    int64_t best = -1;
+    for (int s = 0; s <= d - 2; ++s) {
+      int64_t P = 1, R = 1;
+      for (int m = 0; m < s; ++m) P *= n[m];
+      for (int m = s + 1; m < d; ++m) R *= n[m];
+      int64_t c = std::max(P, R);
+      if (best < 0 || c < best) { best = c; p->s = s; }
+    }
+  }
+  p->Ps = 1;
+  p->Rs = 1;
+  for (int m = 0; m < p->s; ++m) p->Ps *= n[m];
+  for (int m = p->s + 1; m < d; ++m) p->Rs *= n[m];
+  // eigenvalue-sum tables of the axes before / after s (FP64, host-built)
+  std::vector<double> Lp(p->Ps), Lr(p->Rs);
+  for (int64_t i = 0; i < p->Ps; ++i) {
+    int64_t idx = i;
+    double s = 0.0;
+    for (int m = p->s - 1; m >= 0; --m) { s += p->ax[m]->lam_h[idx % n[m]]; idx /= n[m]; }
+    Lp[i] = s;
+  }
+  for (int64_t i = 0; i < p->Rs; ++i) {
+    int64_t idx = i;
+    double s = 0.0;
+    for (int m = d - 1; m > p->s; --m) { s += p->ax[m]->lam_h[idx % n[m]]; idx /= n[m]; }
+    Lr[i] = s;
+  }
+  hipError_t e = hipMalloc(&p->Lp, sizeof(double) * p->Ps);
+  if (e == hipSuccess) e = hipMalloc(&p->Lr, sizeof(double) * p->Rs);
+  if (e == hipSuccess) e = hipMalloc(&p->phase, sizeof(double2) * (p->Ps + p->Rs + n[p->s]));
+  if (e != hipSuccess) { set_error("table allocation failed"); return TS_ERR_NOMEM; }
+  e = hipMemcpy(p->Lp, Lp.data(), sizeof(double) * p->Ps, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->Lr, Lr.data(), sizeof(double) * p->Rs, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { set_error("table upload failed"); return TS_ERR_DEVICE; }
+  *out = p.release();
+  return TS_OK;
+}
+
+int ts_destroy(ts_plan* plan) {
+  if (!plan) return TS_OK;
+  hipDeviceSynchronize();
+  delete plan;
+  return TS_OK;
+}
+
+int ts_apply_inverse(ts_plan* plan, const void* b, void* u, int dtype, int prec, void* hip_stream) {
+  if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
+  return apply_inverse_impl(plan, plan->sigma, b, u, dtype, prec, (hipStream_t)hip_stream, nullptr, nullptr);
+}
+
+int ts_apply_inverse_shift(ts_plan* plan, double s, const void* b, void* u, int dtype, int prec,
+                           void* hip_stream) {
+  if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
+  if (!std::isfinite(s)) { set_error("shift is not finite"); return TS_ERR_INVALID; }
+  return apply_inverse_impl(plan, s, b, u, dtype, prec, (hipStream_t)hip_stream, nullptr, nullptr);
+}
+
+int ts_apply_exp(ts_plan* plan, double tau, const void* psi_in, void* psi_out, int dtype, int prec,
+                 void* hip_stream) {
+  if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
+  return apply_exp_impl(plan, tau, psi_in, psi_out, dtype, prec, (hipStream_t)hip_stream, nullptr);
+}
+
+int ts_eigvals(const ts_plan* plan, int axis, double* out) {
+  if (!plan || !out || axis < 0 || axis >= plan->d) { set_error("bad argument"); return TS_ERR_INVALID; }
+  const auto& F = *plan->ax[axis];
+  std::memcpy(out, F.lam_h.data(), sizeof(double) * F.n);
+  return TS_OK;
+}
+
+int ts_eigvecs(const ts_plan* plan, int axis, double* out) {
+  if (!plan || !out || axis < 0 || axis >= plan->d) { set_error("bad argument"); return TS_ERR_INVALID; }
+  const auto& F = *plan->ax[axis];
+  std::memcpy(out, F.Q_h.data(), sizeof(double) * F.n * F.n);
+  return TS_OK;
+}
+
+int ts_tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q) {
+  if (n < 1 || !diag || !lam || !Q || (n > 1 && !off)) { set_error("bad argument"); return TS_ERR_INVALID; }
+  if (!tridiag_eig(n, diag, off, lam, Q)) { set_error("QL iteration limit reached"); return TS_ERR_NOCONV; }
+  return TS_OK;
+}
+
+int ts_workspace_bytes(const ts_plan* plan, int dtype, size_t* bytes) {
+  if (!plan || !bytes) { set_error("bad argument"); return TS_ERR_INVALID; }
+  size_t per = (dtype == TS_C128 || dtype == TS_C64) ? 16 : 8;
+  *bytes = per * (size_t)plan->N;
+  return TS_OK;
+}
+
+}  // extern "C"

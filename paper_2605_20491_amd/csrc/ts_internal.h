@@ -1,0 +1,118 @@
+// Internal declarations of the MI355X separable tensor-product solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#define TS_MAX_D 12
+
+namespace ts {
+
+// ---- host eigensolver (eig_tridiag.cpp) ----
+bool tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q);
+
+// ---- error plumbing (ts_api.cpp) ----
+void set_error(const std::string& msg);
+
+// Tile geometry shared by launchers and the plan's padded matrix storage.
+constexpr int kTileF = 128;   // free-index tile width of the MFMA kernels
+constexpr int kTileK = 32;    // K padding granularity (covers BK of every kernel)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Per-axis eigen-factors of one distinct (n, L, f_k) on the device.
+// Matrices are stored k-major and zero-padded to [kpad][ld]:
+//   Q  : Q[i][j]   = component i of eigenvector j      (used by forward passes)
+//   QT : QT[i][j]  = Q[j][i]                           (used by backward passes)
+// so an MFMA tile of either operand role reads whole padded rows.
+struct AxisFactor {
+  int64_t n = 0, ld = 0, kpad = 0;
+  double L = 0;
+  std::vector<double> lam_h;  // ascending
+  std::vector<double> Q_h;    // row-major n x n
+  double ih2 = 0;             // h^-2, h = 2L/(n+1)
+  double* lam = nullptr;      // device [n]
+  double* f = nullptr;        // device [n]: the samples f_k(x_j)
+  double* Q64 = nullptr;      // device [kpad][ld]
+  double* QT64 = nullptr;
+  float* Q32 = nullptr;
+  float* QT32 = nullptr;
+  uint16_t* Q16 = nullptr;    // bf16 bit patterns, same padded layout
+  uint16_t* QT16 = nullptr;
+  ~AxisFactor();
+};
+
+// Element types of the per-pass data.
+enum class DT : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+enum class Epi : int { None = 0, Inv = 1, Exp = 2 };
+
+// Arguments of one mode-k pass over X viewed as [P][n][R] (R real values per
+// (p, i), including the factor 2 of interleaved complex data).
+struct PassArgs {
+  const void* X = nullptr;
+  void* Y = nullptr;
+  DT tin = DT::F64, tout = DT::F64;
+  int prec = 0;                // 0 fp64, 1 fp32, 2 bf16 (MFMA arithmetic)
+  const AxisFactor* fac = nullptr;
+  bool forward = true;         // forward uses Q (y = Q^T x), backward uses Q^T
+  int64_t P = 1, n = 1, R = 1;
+  bool cplx = false;           // data are interleaved complex
+  Epi epi = Epi::None;
+  // epilogue tables (device, FP64), indexed by p, by r / (cplx ? 2 : 1), by j
+  const double* Lp = nullptr;  // Inv: sum of eigenvalues of the axes before
+  const double* Lr = nullptr;  //      and after the pass axis
+  double shift = 0.0;          // Inv: denominator = lam[j] + Lp[p] + Lr[q] + shift
+  const double2* Ep = nullptr; // Exp: factor = es[j] * Ep[p] * Er[q]
+  const double2* Er = nullptr;
+  const double2* es = nullptr;
+  const int* skip = nullptr;   // if non-null and *skip != 0 the kernel returns
+};
+
+hipError_t launch_pass(const PassArgs& a, hipStream_t st);
+
+// Phase tables for the propagator: es[j] = e^{-i tau lam_s[j]},
+// Ep[p] = prod_{m<s} e^{-i tau lam_m[j_m(p)]}, Er[q] = prod_{m>s} (...).
+struct PhaseTableArgs {
+  int d = 0, s = 0;
+  int64_t n[TS_MAX_D] = {};
+  const double* lam[TS_MAX_D] = {};
+  double tau = 0;
+  double2* Ep = nullptr;
+  double2* Er = nullptr;
+  double2* es = nullptr;
+  int64_t P = 1, R = 1;
+};
+hipError_t launch_phase_tables(const PhaseTableArgs& a, hipStream_t st);
+
+// Device-side casts for the plan's reduced-precision copies of Q.
+hipError_t launch_cast_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
+hipError_t launch_cast_f64_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st);
+
+}  // namespace ts
+
+// The opaque plan of the C ABI.
+struct ts_plan {
+  int d = 0;
+  int64_t n[TS_MAX_D] = {};
+  int64_t N = 0;
+  double L = 0, sigma = 0;
+  int device = 0;
+  std::vector<std::shared_ptr<ts::AxisFactor>> ax;
+  int s = 0;                   // axis whose forward pass carries the scaling
+  int64_t Ps = 1, Rs = 1;      // products of the extents before / after axis s
+  double* Lp = nullptr;        // device FP64 [Ps]
+  double* Lr = nullptr;        // device FP64 [Rs]
+  double lam_min = 0;          // lowest eigenvalue of H1
+  // lazily allocated scratch
+  std::mutex mu;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  double2* phase = nullptr;    // [Ps + Rs + n_s]
+  ~ts_plan();
+};
