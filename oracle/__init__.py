@@ -80,8 +80,15 @@ def lib():
         L.or_expm_apply.restype = ctypes.c_int64
         L.or_expm_apply.argtypes = [ctypes.c_int64, _dp, ctypes.c_double, ctypes.c_int, _dp, _dp]
         L.or_phase_apply.argtypes = [ctypes.c_int64, _dp, ctypes.c_double, _dp]
+        L.or_num_threads.restype = ctypes.c_int
+        L.or_num_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the C loops."""
+    return int(lib().or_num_threads())
 
 
 def _ptr(a: np.ndarray):

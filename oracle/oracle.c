@@ -424,3 +424,11 @@ void or_phase_apply(int64_t N, const double* V, double theta, double* psi) {
     psi[2 * i + 1] = s * re + c * im;
   }
 }
+
+/* Number of OpenMP threads the loops above use (reported by timing code). */
+#ifdef _OPENMP
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }
+#else
+int or_num_threads(void) { return 1; }
+#endif

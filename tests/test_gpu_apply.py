@@ -1,0 +1,138 @@
+"""Parity of the HIP separable apply (inverse and propagator) with the oracle.
+
+FP64 bar: ||x_gpu - x_oracle||_2 / ||x_oracle||_2 <= 1e-12 (the tolerance of
+the FP64 path); for the propagator at large tau ||H1|| the bar widens to the
+conditioning bound of ``gpu_common.exp_tol``.  Shapes span several 128-wide MFMA tiles with ragged tails,
+1 to 9 axes, extents of 1, and the 64^3 workload (L = 8, f = x^2, sigma = 1,
+N(0,1) right-hand side from seed 1, complex128 Gaussian wavepacket, tau = 0.01).
+FP32 results are compared at the FP32 rounding level (error reported).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_20491_amd as ts
+import workloads as W
+from gpu_common import announce, exp_tol, inv_tol, make_pair, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    (64, 64, 64),
+    (130, 70, 150),
+    (257, 129),
+    (1000,),
+    (20, 17, 24, 19),
+    (7, 6, 5, 8, 4, 6),
+    (1, 5, 1, 7),
+    (3, 3, 3, 3, 3, 3, 3, 3, 3),
+    (200, 144, 176),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_inverse_fp64_parity(shape):
+    announce("inverse fp64 %s" % (shape,))
+    plan, oplan, _ = make_pair(shape, 8.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 1)
+    u = to_host(ts.ts_apply_inverse(plan, to_dev(b)))
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    e = rel(u, ref)
+    announce("  rel err %.3e" % e)
+    assert e <= 1e-12
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("tau", [0.01, -0.3])
+def test_exp_fp64_parity(shape, tau):
+    announce("exp fp64 %s tau=%g" % (shape, tau))
+    plan, oplan, _ = make_pair(shape, 8.0, "cos", sigma=1.0)
+    psi = W.complex_normal(shape, 2)
+    out = to_host(ts.ts_apply_exp(plan, tau, to_dev(psi)))
+    ref = oracle.apply_exp(oplan, psi, tau)
+    e = rel(out, ref)
+    tol = exp_tol(oplan, tau)
+    announce("  rel err %.3e (tol %.1e)" % (e, tol))
+    assert e <= tol
+
+
+def test_config0_workload_inverse_and_exp():
+    """64^3 on [-8,8]^3, f = x^2, sigma = 1: N(0,1) RHS (seed 1) and wavepacket (tau = 0.01)."""
+    shape, L = (64, 64, 64), 8.0
+    plan, oplan, _ = make_pair(shape, L, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 1)
+    assert rel(to_host(ts.ts_apply_inverse(plan, to_dev(b))), oracle.apply_inverse(oplan, b, 1.0)) <= 1e-12
+    psi = W.gaussian_wavepacket(shape, L, 1)
+    out = to_host(ts.ts_apply_exp(plan, 0.01, to_dev(psi)))
+    assert rel(out, oracle.apply_exp(oplan, psi, 0.01)) <= 1e-12
+    assert abs(np.linalg.norm(out) - 1.0) <= 1e-13
+
+
+def test_in_place_and_tau_zero():
+    shape = (33, 65, 17)
+    plan, oplan, _ = make_pair(shape, 5.0, "rand", sigma=0.5, seed=3)
+    b = W.rhs_normal(shape, 4)
+    t = to_dev(b)
+    ts.ts_apply_inverse(plan, t, t)
+    assert rel(to_host(t), oracle.apply_inverse(oplan, b, 0.5)) <= 1e-12
+    psi = W.complex_normal(shape, 5)
+    tp = to_dev(psi)
+    ts.ts_apply_exp(plan, 0.0, tp, tp)
+    assert rel(to_host(tp), psi) <= 1e-13
+
+
+def test_shifted_inverse_and_not_spd():
+    shape = (40, 30, 20)
+    plan, oplan, _ = make_pair(shape, 6.0, "harm", sigma=1.0)
+    lam1 = sum(ts.ts_eigvals(plan, k)[0] for k in range(3))
+    s = -(lam1 - 1e-3)  # denominators as small as 1e-3: formed in FP64
+    b = W.rhs_normal(shape, 6)
+    u = to_host(ts.ts_apply_inverse_shift(plan, s, to_dev(b)))
+    e, tol = rel(u, oracle.apply_inverse(oplan, b, s)), inv_tol(oplan, s)
+    announce("shifted inverse rel err %.3e (tol %.1e)" % (e, tol))
+    assert e <= tol
+    with pytest.raises(ts.TSError) as e:
+        ts.ts_apply_inverse_shift(plan, -lam1 - 1.0, to_dev(b))
+    assert e.value.code == ts.TS_ERR_NOT_SPD
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (130, 70, 150), (20, 17, 24, 19)])
+def test_fp32_transforms(shape):
+    plan, oplan, _ = make_pair(shape, 8.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 7)
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    for dt in (torch.float64, torch.float32):
+        u = to_host(ts.ts_apply_inverse(plan, to_dev(b).to(dt), prec="fp32")).astype(np.float64)
+        e = rel(u, ref)
+        announce("fp32 inverse %s in=%s rel err %.3e" % (shape, dt, e))
+        assert e <= 2e-6
+    psi = W.complex_normal(shape, 8)
+    refp = oracle.apply_exp(oplan, psi, 0.01)
+    for dt in (torch.complex128, torch.complex64):
+        out = to_host(ts.ts_apply_exp(plan, 0.01, to_dev(psi).to(dt), prec="fp32")).astype(np.complex128)
+        e = rel(out, refp)
+        announce("fp32 exp %s in=%s rel err %.3e" % (shape, dt, e))
+        assert e <= 2e-6
+
+
+def test_operator_matches_oracle_stencil():
+    shape = (31, 40, 27)
+    plan, oplan, _ = make_pair(shape, 4.0, "rand", sigma=0.0, seed=9)
+    u = W.rhs_normal(shape, 10)
+    V2 = W.gaussian_bumps(shape, 4.0, 5, seed=11)
+    out = to_host(ts.ts_operator_apply(plan, to_dev(V2), 0.75, to_dev(u)))
+    ref = oracle.stencil_apply(oplan, u, V2, 0.75)
+    assert rel(out, ref) <= 1e-14
+    out0 = to_host(ts.ts_operator_apply(plan, None, 0.0, to_dev(u)))
+    assert rel(out0, oracle.stencil_apply(oplan, u, None, 0.0)) <= 1e-14
+
+
+def test_eigvals_match_oracle():
+    shape = (50, 37)
+    plan, oplan, _ = make_pair(shape, 8.0, "cos", sigma=1.0)
+    for k in range(2):
+        lam = ts.ts_eigvals(plan, k)
+        assert np.max(np.abs(lam - oplan.lam[k])) <= 1e-13 * np.abs(lam).max()
+        Q = ts.ts_eigvecs(plan, k)
+        assert np.max(np.abs(Q.T @ Q - np.eye(shape[k]))) <= 1e-13

@@ -1,0 +1,86 @@
+"""The 1e9-DoF workload (n = 1000 per axis, [-10,10]^3, f = x^2 + 0.5 cos 2x,
+sigma = 1) in the launch configuration the benchmark times, checked with what
+the oracle can compute at that size:
+
+* inverse: the true residual ||(H1 + sigma) u - b|| / ||b|| evaluated by the
+  oracle's stencil on the host (a property that holds at any size);
+* propagator: for a rank-one input g0 (x) g1 (x) g2 the exact result is the
+  outer product of the per-axis results exp(-i tau H_k) g_k, which the oracle
+  computes by dense Taylor series; compared on 10^6 sampled entries, plus norm
+  conservation over the whole grid.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_20491_amd as ts
+import workloads as W
+from gpu_common import DEV, EPS, announce
+
+pytestmark = pytest.mark.gpu
+
+N1, L1, SIG1, TAU1 = 1000, 10.0, 1.0, 0.01
+
+
+@pytest.fixture(scope="module")
+def plan1000():
+    f = [W.f_harmonic_cos(N1, L1) for _ in range(3)]
+    announce("setup n=1000")
+    p = ts.ts_setup((N1,) * 3, L1, f, SIG1)
+    yield p, f
+    p.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-4)])
+def test_inverse_residual_n1000(plan1000, prec, tol):
+    plan, f = plan1000
+    announce("inverse n=1000 %s" % prec)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(2)
+    b = torch.randn((N1,) * 3, dtype=torch.float64, device=DEV, generator=gen)
+    u = ts.ts_apply_inverse(plan, b, prec=prec)
+    torch.cuda.synchronize()
+    bh = b.cpu().numpy()
+    del b
+    uh = u.cpu().numpy()
+    del u
+    torch.cuda.empty_cache()
+    oplan = oracle.Plan(shape=(N1,) * 3, L=L1, f=f, h=[oracle.grid_spacing(N1, L1)] * 3)
+    r = oracle.stencil_apply(oplan, uh, None, SIG1)
+    r -= bh
+    rr = float(np.linalg.norm(r) / np.linalg.norm(bh))
+    announce("  relres %.3e" % rr)
+    assert rr <= tol
+
+
+def test_exp_rank_one_n1000(plan1000):
+    plan, f = plan1000
+    announce("exp n=1000 c128")
+    facs = W.wavepacket_factors((N1,) * 3, L1, 2)
+    H = oracle.fd_axis_matrix(N1, L1, f[0])
+    ref = [oracle.expm_apply(H, TAU1, g) for g in facs]
+    g = [torch.from_numpy(np.ascontiguousarray(x)).to(DEV) for x in facs]
+    psi = (g[0][:, None, None] * g[1][None, :, None]) * g[2][None, None, :]
+    out = ts.ts_apply_exp(plan, TAU1, psi)
+    del psi
+    nrm = float(torch.linalg.vector_norm(out))
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, N1, size=(3, 1_000_000))
+    lin = torch.from_numpy((idx[0] * N1 + idx[1]) * N1 + idx[2]).to(DEV)
+    got = out.reshape(-1)[lin].cpu().numpy()
+    want = ref[0][idx[0]] * ref[1][idx[1]] * ref[2][idx[2]]
+    e = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    normH = 3 * float(np.linalg.eigvalsh(H)[-1])
+    tol = max(1e-12, 50 * TAU1 * EPS * normH)
+    announce("  sampled rel err %.3e (tol %.1e), |norm-1| %.2e" % (e, tol, abs(nrm - 1)))
+    assert e <= tol
+    assert abs(nrm - 1.0) <= 1e-12
+    # complex64 data with FP32 transforms on the same input
+    psi64 = ((g[0][:, None, None] * g[1][None, :, None]) * g[2][None, None, :]).to(torch.complex64)
+    del out
+    out64 = ts.ts_apply_exp(plan, TAU1, psi64, prec="fp32")
+    got64 = out64.reshape(-1)[lin].cpu().numpy().astype(np.complex128)
+    e64 = float(np.linalg.norm(got64 - want) / np.linalg.norm(want))
+    announce("  complex64/fp32 sampled rel err %.3e" % e64)
+    assert e64 <= 1e-4
