@@ -233,6 +233,8 @@ int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype,
 }  // namespace ts
 
 ts_plan::~ts_plan() {
+  hipFree(solver);
+  if (solver_host) hipHostFree(solver_host);
   hipFree(Lp);
   hipFree(Lr);
   hipFree(work);

@@ -114,5 +114,8 @@ struct ts_plan {
   void* work = nullptr;
   size_t work_bytes = 0;
   double2* phase = nullptr;    // [Ps + Rs + n_s]
+  void* solver = nullptr;      // solver vectors, partial sums and scalars
+  size_t solver_bytes = 0;
+  void* solver_host = nullptr; // pinned host mirror of the solver scalars
   ~ts_plan();
 };

@@ -1,9 +1,17 @@
-// Launchers of the FP64 vector kernels (vec.hip).
+// Launchers of the FP64 vector kernels (vec.hip): the stencil operator of
+// eq. (general_system), deterministic reductions and the fused vector
+// updates of PCG / iterative refinement.
 #pragma once
 
 #include "ts_internal.h"
 
 namespace ts {
+
+constexpr int kRedBlocks = 1024;  // fixed grid of every reduction: results are bitwise reproducible
+
+// Output and reduction modes of the stencil kernel.
+enum class StOut : int { Ax = 0, FminusAx = 1 };
+enum class StDot : int { None = 0, UdotOut = 1, OutdotOut = 2 };
 
 struct StencilArgs {
   int d = 0;
@@ -15,9 +23,52 @@ struct StencilArgs {
   const double* V2 = nullptr;
   double s = 0.0;
   const double* u = nullptr;
+  const double* rhs = nullptr;     // StOut::FminusAx: out = rhs - A u
   double* out = nullptr;
+  StOut mode = StOut::Ax;
+  StDot dot = StDot::None;
+  double* partial = nullptr;       // [kRedBlocks] when dot != None
+  const int* skip = nullptr;
 };
 
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st);
+
+// Device scalar block used by the solvers (all FP64 except the int flags).
+struct SolverScalars {
+  double rz, rz_new, pq, zq, alpha, beta, rr, ff, tol2, rr_prev;
+  double aux[6];
+  int done, status, iters, pad;
+};
+
+// partial[b] = block b's share of sum x*y (and of sum x*w into partial2 if w).
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partial,
+                      const double* w, double* partial2, const int* skip, hipStream_t st);
+
+// x += alpha p; r -= alpha q; partial <- ||r||^2 shares.  alpha from sc.
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, int64_t n,
+                            const SolverScalars* sc, double* partial, const int* skip, hipStream_t st);
+
+// p = z + beta p (beta from sc).
+hipError_t launch_xpby(const double* z, double* p, int64_t n, const SolverScalars* sc, const int* skip,
+                       hipStream_t st);
+
+// x += y (iterative refinement correction).
+hipError_t launch_axpy1(double* x, const double* y, int64_t n, const int* skip, hipStream_t st);
+
+// y = x / sqrt(sc->aux[0]).
+hipError_t launch_scale_invnorm(const double* x, double* y, int64_t n, const SolverScalars* sc, hipStream_t st);
+
+// Scalar steps of PCG, one thread block each.  `what` selects the step.
+enum class ScalarStep : int {
+  InitRR = 0,      // rr <- sum(partial), ff <- sum(partial2) ; done if rr <= tol2 * ff
+  InitRZ = 1,      // rz <- sum(partial)
+  Alpha = 2,       // pq <- sum(partial); alpha = rz / pq (breakdown if pq <= 0)
+  RR = 3,          // rr <- sum(partial); iters++; done if rr <= tol2 * ff or iters >= maxit
+  Beta = 4,        // rz_new <- sum(partial), zq <- sum(partial2); beta (standard or flexible)
+  SetRR = 5,       // rr <- sum(partial) (no decision)
+  SetAux0 = 6,     // aux[0] <- sum(partial)
+};
+hipError_t launch_scalar(ScalarStep what, SolverScalars* sc, const double* partial, const double* partial2,
+                         int flexible, int maxit, hipStream_t st);
 
 }  // namespace ts

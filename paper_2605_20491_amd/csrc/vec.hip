@@ -1,39 +1,277 @@
 // HBM-bound FP64 kernels around the separable apply: the non-separable
-// operator by its stencil (paper eq. (general_system)), and the reductions
-// and vector updates of PCG and iterative refinement.
+// operator by its (2d+1)-point stencil (paper eq. (general_system)), and the
+// deterministic reductions and fused vector updates of PCG (Sec. 3.2) and
+// iterative refinement.
+//
+// Reductions are two-stage with a fixed grid (kRedBlocks blocks): each block
+// writes one partial sum, and a one-block "scalar" kernel adds the partials in
+// index order and takes the solver decision (alpha, beta, convergence) on the
+// device.  Results are bitwise reproducible from run to run.
 #include "ts_internal.h"
 #include "ts_vec.h"
 
 namespace ts {
 namespace {
 
-// out = (sum_k h_k^-2 (2u - u_{-e_k} - u_{+e_k}) + (sum_k f_k[j_k] + V2 + s) u), zero ghosts.
-__global__ __launch_bounds__(256) void k_stencil(StencilArgs a) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= a.N) return;
-  const double u0 = a.u[i];
-  double diag = a.s + (a.V2 ? a.V2[i] : 0.0);
-  double acc = 0.0;
-  int64_t rem = i;
-  for (int k = a.d - 1; k >= 0; --k) {
-    const int64_t nk = a.n[k];
-    const int64_t j = rem % nk;
-    rem /= nk;
-    diag += a.f[k][j];
-    const int64_t st = a.stride[k];
-    const double lo = (j > 0) ? a.u[i - st] : 0.0;
-    const double hi = (j + 1 < nk) ? a.u[i + st] : 0.0;
-    acc += a.ih2[k] * (2.0 * u0 - lo - hi);
-  }
-  a.out[i] = acc + diag * u0;
+constexpr int RT = 256;          // threads per block of the vector kernels
+constexpr int kMarch = 32;       // stencil: points per thread along axis 0
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  return v;
 }
+
+// Sum over the block; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sh[RT / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < RT / 64; ++i) s += sh[i];
+  return s;
+}
+
+// Stencil: each thread owns one index r of the faster axes (1..d-1) and a run
+// of kMarch consecutive points along axis 0, keeping the axis-0 neighbours in
+// registers.  Faster-axis neighbours come from L1/L2.
+template <int MODE, int DOT>
+__global__ __launch_bounds__(RT) void k_stencil(StencilArgs a) {
+  if (a.skip && *a.skip) {
+    if (DOT && threadIdx.x == 0 && blockIdx.x < kRedBlocks) a.partial[blockIdx.x] = 0.0;
+    return;
+  }
+  const int64_t n0 = a.n[0];
+  const int64_t rest = a.N / n0;  // = stride[0]
+  const int64_t chunks = (n0 + kMarch - 1) / kMarch;
+  const int64_t work = rest * chunks;
+  double dsum = 0.0;
+  for (int64_t w = blockIdx.x * (int64_t)RT + threadIdx.x; w < work; w += (int64_t)gridDim.x * RT) {
+    const int64_t r = w % rest;
+    const int64_t c = w / rest;
+    // decode r into the faster axes once: boundary flags and the f sum
+    double fsum = a.s;
+    unsigned lo_ok = 0, hi_ok = 0;  // bit k: the neighbour below / above exists on axis k
+    int64_t rem = r;
+    for (int k = a.d - 1; k >= 1; --k) {
+      const int64_t j = rem % a.n[k];
+      rem /= a.n[k];
+      fsum += a.f[k][j];
+      if (j > 0) lo_ok |= 1u << k;
+      if (j + 1 < a.n[k]) hi_ok |= 1u << k;
+    }
+    const int64_t i_beg = c * kMarch;
+    const int64_t i_end = i_beg + kMarch < n0 ? i_beg + kMarch : n0;
+    double um = i_beg > 0 ? a.u[(i_beg - 1) * rest + r] : 0.0;
+    double uc = a.u[i_beg * rest + r];
+    for (int64_t i = i_beg; i < i_end; ++i) {
+      const int64_t idx = i * rest + r;
+      const double up = (i + 1 < n0) ? a.u[idx + rest] : 0.0;
+      double acc = a.ih2[0] * (2.0 * uc - um - up);
+      for (int k = 1; k < a.d; ++k) {
+        const int64_t st = a.stride[k];
+        const double lo = ((lo_ok >> k) & 1u) ? a.u[idx - st] : 0.0;
+        const double hi = ((hi_ok >> k) & 1u) ? a.u[idx + st] : 0.0;
+        acc += a.ih2[k] * (2.0 * uc - lo - hi);
+      }
+      double diag = fsum + a.f[0][i] + (a.V2 ? a.V2[idx] : 0.0);
+      double v = acc + diag * uc;
+      if (MODE == (int)StOut::FminusAx) v = a.rhs[idx] - v;
+      a.out[idx] = v;
+      if (DOT == (int)StDot::UdotOut) dsum += uc * v;
+      if (DOT == (int)StDot::OutdotOut) dsum += v * v;
+      um = uc;
+      uc = up;
+    }
+  }
+  if (DOT) {
+    double s = block_sum(dsum);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(RT) void k_dot(const double* x, const double* y, int64_t n, double* partial,
+                                            const double* w, double* partial2, const int* skip) {
+  if (skip && *skip) {
+    if (threadIdx.x == 0) {
+      partial[blockIdx.x] = 0.0;
+      if (partial2) partial2[blockIdx.x] = 0.0;
+    }
+    return;
+  }
+  double s = 0.0, s2 = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    const double xi = x[i];
+    s += xi * y[i];
+    if (w) s2 += xi * w[i];
+  }
+  double t = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (w) {
+    double t2 = block_sum(s2);
+    if (threadIdx.x == 0) partial2[blockIdx.x] = t2;
+  }
+}
+
+__global__ __launch_bounds__(RT) void k_cg_update(double* x, double* r, const double* p, const double* q,
+                                                  int64_t n, const SolverScalars* sc, double* partial,
+                                                  const int* skip) {
+  if (skip && *skip) {
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0.0;
+    return;
+  }
+  const double alpha = sc->alpha;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  double t = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(RT) void k_xpby(const double* z, double* p, int64_t n, const SolverScalars* sc,
+                                             const int* skip) {
+  if (skip && *skip) return;
+  const double beta = sc->beta;
+  for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(RT) void k_axpy1(double* x, const double* y, int64_t n, const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) x[i] += y[i];
+}
+
+// y = x / sqrt(sc->aux[0])  (normalisation by a norm^2 reduced on the device)
+__global__ __launch_bounds__(RT) void k_scale_invnorm(const double* x, double* y, int64_t n,
+                                                      const SolverScalars* sc) {
+  const double inv = 1.0 / sqrt(sc->aux[0]);
+  for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) y[i] = x[i] * inv;
+}
+
+// Status codes written by the scalar kernel.
+enum { ST_RUN = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2, ST_MAXIT = 3 };
+
+__global__ __launch_bounds__(RT) void k_scalar(int what, SolverScalars* sc, const double* partial,
+                                               const double* partial2, int flexible, int maxit) {
+  // fixed-order sums of the partials: thread t adds t, t+RT, ...; then the block tree
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += RT) {
+    a += partial[i];
+    if (partial2) b += partial2[i];
+  }
+  a = block_sum(a);
+  if (partial2) b = block_sum(b);
+  if (threadIdx.x != 0) return;
+  if (sc->done && what != (int)ScalarStep::SetRR && what != (int)ScalarStep::SetAux0) return;
+  switch (what) {
+    case (int)ScalarStep::InitRR:
+      sc->rr = a;
+      sc->ff = b;
+      sc->iters = 0;
+      sc->status = ST_RUN;
+      if (!isfinite(a) || !isfinite(b)) { sc->status = ST_NONFINITE; sc->done = 1; }
+      else if (a <= sc->tol2 * b) sc->done = 1;
+      break;
+    case (int)ScalarStep::InitRZ:
+      sc->rz = a;
+      if (!isfinite(a)) { sc->status = ST_NONFINITE; sc->done = 1; }
+      break;
+    case (int)ScalarStep::Alpha:
+      sc->pq = a;
+      if (!isfinite(a)) { sc->status = ST_NONFINITE; sc->done = 1; }
+      else if (!(a > 0.0)) { sc->status = ST_BREAKDOWN; sc->done = 1; }
+      else sc->alpha = sc->rz / a;
+      break;
+    case (int)ScalarStep::RR:
+      sc->rr_prev = sc->rr;
+      sc->rr = a;
+      sc->iters += 1;
+      if (!isfinite(a)) { sc->status = ST_NONFINITE; sc->done = 1; }
+      else if (a <= sc->tol2 * sc->ff) sc->done = 1;
+      else if (sc->iters >= maxit) { sc->status = ST_MAXIT; sc->done = 1; }
+      break;
+    case (int)ScalarStep::Beta: {
+      // standard: beta = <z', r'> / <z, r>;  flexible (Polak-Ribiere):
+      // beta = <z', r' - r> / <z, r> = (<z', r'> - <z', r>) / <z, r>, and
+      // r' - r = -alpha q, so <z', r' - r> = -alpha <z', q>
+      const double rz_new = a;
+      double beta = flexible ? (-sc->alpha * b) / sc->rz : rz_new / sc->rz;
+      if (!isfinite(beta)) { sc->status = ST_NONFINITE; sc->done = 1; }
+      sc->rz_new = rz_new;
+      sc->zq = b;
+      sc->beta = beta;
+      sc->rz = rz_new;
+      break;
+    }
+    case (int)ScalarStep::SetRR:
+      sc->rr = a;
+      break;
+    case (int)ScalarStep::SetAux0:
+      sc->aux[0] = a;
+      break;
+  }
+}
+
+inline int red_grid(int64_t n) { (void)n; return kRedBlocks; }
 
 }  // namespace
 
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
-  int64_t blocks = (a.N + 255) / 256;
-  hipLaunchKernelGGL(k_stencil, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  const int64_t work = (a.N / a.n[0]) * ((a.n[0] + kMarch - 1) / kMarch);
+  unsigned grid;
+  if (a.dot != StDot::None) grid = kRedBlocks;
+  else grid = (unsigned)std::min<int64_t>((work + RT - 1) / RT, 1 << 20);
+  const int m = (int)a.mode, dt = (int)a.dot;
+#define TS_ST(M, D) \
+  if (m == M && dt == D) { hipLaunchKernelGGL((k_stencil<M, D>), dim3(grid), dim3(RT), 0, st, a); return hipGetLastError(); }
+  TS_ST(0, 0) TS_ST(0, 1) TS_ST(0, 2) TS_ST(1, 0) TS_ST(1, 1) TS_ST(1, 2)
+#undef TS_ST
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partial, const double* w,
+                      double* partial2, const int* skip, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot, dim3(red_grid(n)), dim3(RT), 0, st, x, y, n, partial, w, partial2, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, int64_t n,
+                            const SolverScalars* sc, double* partial, const int* skip, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(red_grid(n)), dim3(RT), 0, st, x, r, p, q, n, sc, partial, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpby(const double* z, double* p, int64_t n, const SolverScalars* sc, const int* skip,
+                       hipStream_t st) {
+  unsigned grid = (unsigned)std::min<int64_t>((n + RT - 1) / RT, 4096);
+  hipLaunchKernelGGL(k_xpby, dim3(grid), dim3(RT), 0, st, z, p, n, sc, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy1(double* x, const double* y, int64_t n, const int* skip, hipStream_t st) {
+  unsigned grid = (unsigned)std::min<int64_t>((n + RT - 1) / RT, 4096);
+  hipLaunchKernelGGL(k_axpy1, dim3(grid), dim3(RT), 0, st, x, y, n, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_invnorm(const double* x, double* y, int64_t n, const SolverScalars* sc, hipStream_t st) {
+  unsigned grid = (unsigned)std::min<int64_t>((n + RT - 1) / RT, 4096);
+  hipLaunchKernelGGL(k_scale_invnorm, dim3(grid), dim3(RT), 0, st, x, y, n, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar(ScalarStep what, SolverScalars* sc, const double* partial, const double* partial2,
+                         int flexible, int maxit, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(RT), 0, st, (int)what, sc, partial, partial2, flexible, maxit);
   return hipGetLastError();
 }
 
