@@ -51,6 +51,82 @@ def timed(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def bumps_on_device(W, torch, dev, shape, L, nbumps, seed):
+    """The Gaussian-bump V2 of the workload recipe, evaluated on the device."""
+    axes = [torch.from_numpy(W.grid_nodes(n, L)).to(dev) for n in shape]
+    V = torch.zeros(shape, dtype=torch.float64, device=dev)
+    for a, w, c in W.bump_params(len(shape), nbumps, seed):
+        g = [torch.exp(-(axes[k] - c[k]) ** 2 / (2.0 * w * w)) for k in range(len(shape))]
+        t = g[0]
+        for k in range(1, len(shape)):
+            t = t.unsqueeze(-1) * g[k]
+        V += a * t
+    return V
+
+
+def pcg_section(ts, W, torch, dev, n, precs):
+    """Non-separable PCG workload: 3D n^3 on [-8,8]^3, V1 = sum x^2, 16 bumps (seed 3),
+    f ~ N(0,1) (seed 3), preconditioner (H1 + sigma)^-1 in each precision, rtol 1e-10."""
+    L = 8.0
+    shape = (n, n, n)
+    f_list = [W.f_harmonic(n, L) for _ in range(3)]
+    V2 = bumps_on_device(W, torch, dev, shape, L, 16, 3)
+    plan = ts.ts_setup(shape, L, f_list, 1.0)
+    lam_min = sum(float(ts.ts_eigvals(plan, k)[0]) for k in range(3))
+    sigma = max(1.0, 0.5 - lam_min - float(V2.min()))
+    if sigma != 1.0:
+        plan = ts.ts_setup(shape, L, f_list, sigma)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    f = torch.randn(shape, dtype=torch.float64, device=dev, generator=gen)
+    out = {"n": n, "sigma": sigma}
+    for prec in precs:
+        try:
+            u = torch.zeros_like(f)
+            ts.ts_pcg_solve(plan, V2, f, u, rtol=1e-10, precond=prec)   # warm-up
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, it, rr, _ = ts.ts_pcg_solve(plan, V2, f, u, rtol=1e-10, precond=prec)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            out[prec] = {"solve_ms": ms, "iters": it, "relres": rr}
+            log("pcg n=%d %s: %.1f ms, %d iters, relres %.2e" % (n, prec, ms, it, rr))
+        except ts.TSError as e:
+            out[prec] = "unavailable: %s" % e.status
+    if isinstance(out.get("fp64"), dict):
+        for prec in precs[1:]:
+            if isinstance(out.get(prec), dict):
+                out["speedup_%s_vs_fp64" % prec] = out["fp64"]["solve_ms"] / out[prec]["solve_ms"]
+    return out
+
+
+def invit_section(ts, W, torch, dev, n, precs, steps=20):
+    """20 steps of shifted inverse iteration on the same workload (shift per the recipe)."""
+    L = 8.0
+    shape = (n, n, n)
+    f_list = [W.f_harmonic(n, L) for _ in range(3)]
+    V2 = bumps_on_device(W, torch, dev, shape, L, 16, 3)
+    plan = ts.ts_setup(shape, L, f_list, 1.0)
+    lam1 = sum(float(ts.ts_eigvals(plan, k)[0]) for k in range(3))
+    shift = lam1 + min(0.0, float(V2.min())) - 1e-4
+    Q = [torch.from_numpy(ts.ts_eigvecs(plan, k)[:, 0].copy()).to(dev) for k in range(3)]
+    out = {"n": n, "shift": shift, "steps": steps}
+    for prec in precs:
+        try:
+            u = ((Q[0][:, None, None] * Q[1][None, :, None]) * Q[2][None, None, :]).contiguous()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, lam, its = ts.ts_inverse_iteration(plan, V2, shift, u, steps=steps, pcg_rtol=1e-10, precond=prec)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            out[prec] = {"ms": ms, "lambda": float(lam[-1]), "pcg_iters_total": int(sum(its))}
+            log("inverse iteration n=%d %s: %.1f ms, lambda %.10f, %d PCG iters" % (n, prec, ms, lam[-1], sum(its)))
+        except ts.TSError as e:
+            out[prec] = "unavailable: %s" % e.status
+    return out
+
+
 def cpu_baseline(n, depth):
     """The oracle's six mode products on slabs holding `depth` x n full fibres per axis."""
     import numpy as np
@@ -81,7 +157,8 @@ def main():
     ap.add_argument("--n", type=int, default=1000, help="points per axis (1000 is the headline workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-depth", type=int, default=24)
+    ap.add_argument("--cpu-depth", type=int, default=96)
+    ap.add_argument("--no-pcg", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
@@ -156,6 +233,12 @@ def main():
         extra["exp_c64_fp32_ms"] = msx
         log("c64 exp %.2f ms/apply" % msx)
         del psi64, out64
+    if not args.no_pcg:
+        precs = ["fp64", "fp32", "bf16"]
+        extra["pcg_n256"] = pcg_section(ts, W, torch, dev, 256, precs)
+        extra["pcg_n512"] = pcg_section(ts, W, torch, dev, 512, precs)
+        extra["inverse_iteration_n256"] = invit_section(ts, W, torch, dev, 256, precs)
+        torch.cuda.empty_cache()
     extra["paper_context"] = ("FP64 direct inverse, 1099^3 (Q^1 = FD), NVIDIA GH200: 0.508 s = 2.61e9 DoF/s "
                               "(Table tab:accuracy_gh200); not the same workload or hardware")
     torch.cuda.synchronize()

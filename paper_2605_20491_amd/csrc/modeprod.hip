@@ -18,81 +18,16 @@
 //     Exp: y * es[j] * Ep[p] * Er[q]                     (FP64 phase factors)
 // where q indexes the faster axes (r, or r/2 for complex data).
 #include "ts_internal.h"
+#include "modeprod_common.h"
 
 namespace ts {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
+using namespace mp;
 
 constexpr int BM = 128, BN = 128, BK = 16, NT = 256;
 constexpr int LDS_LD = BM + 4;  // padded LDS row length (elements)
 
-template <typename T> struct AccT;
-template <> struct AccT<double> { using V = d4; };
-template <> struct AccT<float> { using V = f4; };
-
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Row (within a 16x16 output block) of accumulator element r held by lane l.
-// Measured on gfx950: the FP64 form interleaves rows across lane groups.
-template <typename T> __device__ __forceinline__ int out_row(int l, int r);
-template <> __device__ __forceinline__ int out_row<double>(int l, int r) { return (l >> 4) + 4 * r; }
-template <> __device__ __forceinline__ int out_row<float>(int l, int r) { return 4 * (l >> 4) + r; }
-
-// ---- element conversions ----
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
-}
-
-template <typename TIn, typename TC> __device__ __forceinline__ TC cvt_in(TIn x);
-template <> __device__ __forceinline__ double cvt_in<double, double>(double x) { return x; }
-template <> __device__ __forceinline__ float cvt_in<double, float>(double x) { return (float)x; }
-template <> __device__ __forceinline__ float cvt_in<float, float>(float x) { return x; }
-template <> __device__ __forceinline__ double cvt_in<float, double>(float x) { return (double)x; }
-template <> __device__ __forceinline__ float cvt_in<uint16_t, float>(uint16_t x) { return bf16_to_f32(x); }
-
-template <typename TOut> __device__ __forceinline__ TOut cvt_out(double x);
-template <> __device__ __forceinline__ double cvt_out<double>(double x) { return x; }
-template <> __device__ __forceinline__ float cvt_out<float>(double x) { return (float)x; }
-template <> __device__ __forceinline__ uint16_t cvt_out<uint16_t>(double x) { return f32_to_bf16((float)x); }
-
-struct KArgs {
-  const void* X;
-  void* Y;
-  const void* S;      // resident factor, [kpad][ld], k-major
-  int64_t ld;
-  int64_t P, n, R;    // data view [P][n][R]
-  int64_t M, N;       // GEMM extents (K = n)
-  int64_t mt, nt;     // tiles along M and N
-  int64_t nblocks;
-  const double* lam;  // epilogue tables
-  const double* Lp;
-  const double* Lr;
-  double shift;
-  const double2* Ep;
-  const double2* Er;
-  const double2* es;
-  const int* skip;
-};
-
-// Map the hardware block id to a logical tile id so that consecutive logical
-// tiles (which share an operand panel) run on the same XCD: blocks are handed
-// to the 8 XCDs round-robin.
-__device__ __forceinline__ int64_t xcd_logical_block(int64_t bid, int64_t nblocks) {
-  int64_t q = nblocks / 8, rmd = nblocks % 8;
-  int64_t x = bid % 8, loc = bid / 8;
-  return x * q + (x < rmd ? x : rmd) + loc;
-}
 
 template <typename TC, typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI>
 __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
@@ -212,77 +147,31 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   // ---- epilogue ----
   TOut* Y = (TOut*)a.Y;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + wm * 64 + i * 16 + out_row<TC>(lane, r);
         const int64_t col = n0 + wn * 64 + j * 16 + lr;
         double v = (double)acc[i][j][r];
-        if (ROWS) {
-          if (m < a.M && col < a.n) {
-            if (!CPLX) Y[m * a.n + col] = cvt_out<TOut>(v);
-            else Y[(((m >> 1) * a.n + col) << 1) + (m & 1)] = cvt_out<TOut>(v);
-          }
-        } else {
-          if (EPI == (int)Epi::Exp) {
-            // (re, im) of one element sit in lanes 2u, 2u+1 (columns col, col^1)
-            double partner = __shfl_xor(v, 1);
-            if (m < a.n && col < a.R) {
-              double2 f1 = a.es[m], f2 = a.Ep[p], f3 = a.Er[col >> 1];
-              double fr = f1.x * f2.x - f1.y * f2.y, fi = f1.x * f2.y + f1.y * f2.x;
-              double gr = fr * f3.x - fi * f3.y, gi = fr * f3.y + fi * f3.x;
-              v = (col & 1) ? (gi * partner + gr * v) : (gr * v - gi * partner);
-            }
-          } else if (EPI == (int)Epi::Inv) {
-            if (m < a.n && col < a.R) {
-              const int64_t q = CPLX ? (col >> 1) : col;
-              double den = a.lam[m] + a.Lp[p] + a.Lr[q] + a.shift;
-              v = v / den;
-            }
-          }
-          if (m < a.n && col < a.R) Y[(p * a.n + m) * a.R + col] = cvt_out<TOut>(v);
-        }
+        double partner = 0.0;
+        // (re, im) of one element sit in lanes 2u, 2u+1 (columns col, col^1)
+        if (EPI == (int)Epi::Exp) partner = __shfl_xor(v, 1);
+        if (ROWS) store_rows<TOut, CPLX>(a, Y, m, col, v);
+        else store_cols<TOut, CPLX, EPI>(a, Y, p, m, col, v, partner);
       }
-    }
-  }
 }
 
 template <typename TC, typename TIn, typename TOut>
 hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   KArgs a{};
-  a.X = pa.X;
-  a.Y = pa.Y;
   const AxisFactor* F = pa.fac;
-  if (std::is_same<TC, double>::value) a.S = pa.forward ? (const void*)F->Q64 : (const void*)F->QT64;
-  else a.S = pa.forward ? (const void*)F->Q32 : (const void*)F->QT32;
-  a.ld = F->ld;
-  a.P = pa.P;
-  a.n = pa.n;
-  a.R = pa.R;
-  a.lam = F->lam;
-  a.Lp = pa.Lp;
-  a.Lr = pa.Lr;
-  a.shift = pa.shift;
-  a.Ep = pa.Ep;
-  a.Er = pa.Er;
-  a.es = pa.es;
-  a.skip = pa.skip;
-  const bool rows = (pa.R == 1 || (pa.cplx && pa.R == 2)) && pa.epi == Epi::None;
-  if (rows) {
-    a.M = pa.P * (pa.cplx ? 2 : 1);
-    a.N = pa.n;
-    a.mt = (a.M + BM - 1) / BM;
-    a.nt = (a.N + BN - 1) / BN;
-    a.nblocks = a.mt * a.nt;
-  } else {
-    a.M = pa.n;
-    a.N = pa.R;
-    a.mt = (a.M + BM - 1) / BM;
-    a.nt = (a.N + BN - 1) / BN;
-    a.nblocks = a.mt * a.nt * pa.P;
-  }
+  const void* S;
+  if (std::is_same<TC, double>::value) S = pa.forward ? (const void*)F->Q64 : (const void*)F->QT64;
+  else S = pa.forward ? (const void*)F->Q32 : (const void*)F->QT32;
+  fill_kargs(pa, a, S, BM, BN);
+  const bool rows = a.rows;
   if (a.nblocks <= 0) return hipSuccess;
   if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)a.nblocks), block(NT);
@@ -315,7 +204,8 @@ hipError_t launch_pass(const PassArgs& pa, hipStream_t st) {
     if (pa.tin == DT::F32 && pa.tout == DT::F64) return launch_typed<float, float, double>(pa, st);
     return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;  // bf16 passes live in modeprod_bf16.hip
+  if (pa.prec == 2) return launch_pass_bf16(pa, st);
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,278 @@
+// BF16 mode-product passes: BF16 operands on the 16x16x32 matrix cores of
+// gfx950 with FP32 accumulation (the reduced-precision transforms used inside
+// PCG and refinement; paper Sec. 2.2 runs the same apply in BF16).
+//
+// Same pass structure as modeprod.hip (column passes: factor x X[p]; row
+// passes on the fastest axis: X rows x factor), but both LDS operands are
+// stored "free index major, K contiguous" because one MFMA lane consumes 8
+// consecutive K values of one row (A) or one column (B): each fragment is a
+// single 128-bit LDS read.  The factor tiles therefore come from the
+// transposed copy of the role the FP64 kernel uses (forward: Q^T, backward:
+// Q), stored in HBM as BF16 with the same zero padding.  Data tiles are
+// converted to BF16 on the way into LDS (FP64 -> FP32 -> BF16, each round to
+// nearest even); the column operand is transposed there.
+#include "modeprod_common.h"
+#include "ts_internal.h"
+
+namespace ts {
+namespace {
+
+using namespace mp;
+
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+constexpr int BM = 128, BN = 128, BK = 64, NT = 256;
+constexpr int LDK = BK + 8;  // padded row: 144 B, fragment reads are bank-conflict free
+
+__device__ __forceinline__ uint16_t to_bf16(double x) { return f32_to_bf16((float)x); }
+__device__ __forceinline__ uint16_t to_bf16(float x) { return f32_to_bf16(x); }
+__device__ __forceinline__ uint16_t to_bf16(uint16_t x) { return x; }
+
+// 8 consecutive elements by 16-byte loads (the caller guarantees alignment).
+__device__ __forceinline__ void load_vec8(const double* src, double* dst) {
+  const double2* s2 = (const double2*)src;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double2 v = s2[i];
+    dst[2 * i] = v.x;
+    dst[2 * i + 1] = v.y;
+  }
+}
+__device__ __forceinline__ void load_vec8(const float* src, float* dst) {
+  const float4* s4 = (const float4*)src;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    float4 v = s4[i];
+    dst[4 * i] = v.x;
+    dst[4 * i + 1] = v.y;
+    dst[4 * i + 2] = v.z;
+    dst[4 * i + 3] = v.w;
+  }
+}
+__device__ __forceinline__ void load_vec8(const uint16_t* src, uint16_t* dst) {
+  uint4 v = *(const uint4*)src;
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    dst[2 * i] = (uint16_t)(w[i] & 0xffffu);
+    dst[2 * i + 1] = (uint16_t)(w[i] >> 16);
+  }
+}
+
+template <typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI>
+__global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
+  if (a.skip && *a.skip) return;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][LDK];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  const int64_t lb = xcd_logical_block(blockIdx.x, a.nblocks);
+  int64_t p = 0, mtile, ntile;
+  if (ROWS) {
+    mtile = lb / a.nt;
+    ntile = lb % a.nt;
+  } else {
+    mtile = lb % a.mt;
+    int64_t rest = lb / a.mt;
+    ntile = rest % a.nt;
+    p = rest / a.nt;
+  }
+  const int64_t m0 = mtile * BM, n0 = ntile * BN;
+  const int64_t K = a.n;
+  const TIn* X = (const TIn*)a.X;
+  const uint16_t* S = (const uint16_t*)a.S;
+
+  // resident factor tile: 128 rows (free index) x 64 k; 4 x 16 bytes per thread
+  uint4 rres0, rres1, rres2, rres3;
+  // data: 32 elements per thread
+  TIn rdat[32];
+
+  const int64_t f0 = ROWS ? n0 : m0;
+  const bool base_aligned = (((uintptr_t)a.X) & 15) == 0;
+  auto load_tile = [&](int64_t k0) {
+    {
+      const int row = t >> 1, half = t & 1;  // 32 k per thread
+      const uint4* src = (const uint4*)(S + (f0 + row) * a.ld + k0 + 32 * half);
+      rres0 = src[0];
+      rres1 = src[1];
+      rres2 = src[2];
+      rres3 = src[3];
+    }
+    if (!ROWS) {
+      // X[p] rows k0 + 4*kq .. +3, columns n0 + 8*oc .. +7
+      const int oc = t & 15, kq = t >> 4;
+      const int64_t col0 = n0 + 8 * oc;
+      const bool vec = base_aligned && (a.R % 8 == 0) && (col0 + 8 <= a.R);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int64_t k = k0 + 4 * kq + rr;
+        const TIn* src = X + (p * a.n + k) * a.R + col0;
+        if (k < K && vec) {
+          load_vec8(src, &rdat[rr * 8]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) rdat[rr * 8 + c] = (k < K && col0 + c < a.R) ? src[c] : (TIn)0;
+        }
+      }
+    } else if (!CPLX) {
+      const int row = t >> 1, half = t & 1;
+      const int64_t m = m0 + row;
+      const int64_t kb = k0 + 32 * half;
+      const TIn* src = X + m * a.n + kb;
+      if (base_aligned && m < a.M && kb + 32 <= K && (a.n % 8) == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) load_vec8(src + 8 * c, &rdat[8 * c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) rdat[c] = (m < a.M && kb + c < K) ? src[c] : (TIn)0;
+      }
+    } else {
+      // rows 2p (re) and 2p+1 (im): p = pl, 16 consecutive k, both components
+      const int pl = t >> 2, quarter = t & 3;
+      const int64_t pp = (m0 >> 1) + pl;
+      const int64_t kb = k0 + 16 * quarter;
+      const TIn* src = X + ((pp * a.n + kb) << 1);
+      if (base_aligned && pp < a.P && kb + 16 <= K && (a.n % 8) == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) load_vec8(src + 8 * c, &rdat[8 * c]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) rdat[c] = (pp < a.P && kb + (c >> 1) < K) ? src[c] : (TIn)0;
+      }
+    }
+  };
+  auto store_tile = [&](int buf) {
+    uint16_t(*Res)[LDK] = ROWS ? Bs[buf] : As[buf];
+    {
+      const int row = t >> 1, half = t & 1;
+      uint4* dst = (uint4*)&Res[row][32 * half];
+      dst[0] = rres0;
+      dst[1] = rres1;
+      dst[2] = rres2;
+      dst[3] = rres3;
+    }
+    if (!ROWS) {
+      // transpose: Bs[col][4 kq .. 4 kq + 3] for each of 8 columns
+      const int oc = t & 15, kq = t >> 4;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        uint32_t lo = (uint32_t)to_bf16(rdat[0 * 8 + c]) | ((uint32_t)to_bf16(rdat[1 * 8 + c]) << 16);
+        uint32_t hi = (uint32_t)to_bf16(rdat[2 * 8 + c]) | ((uint32_t)to_bf16(rdat[3 * 8 + c]) << 16);
+        *(uint2*)&Bs[buf][8 * oc + c][4 * kq] = make_uint2(lo, hi);
+      }
+    } else if (!CPLX) {
+      const int row = t >> 1, half = t & 1;
+      uint32_t w[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        w[c] = (uint32_t)to_bf16(rdat[2 * c]) | ((uint32_t)to_bf16(rdat[2 * c + 1]) << 16);
+      uint4* dst = (uint4*)&As[buf][row][32 * half];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dst[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+    } else {
+      const int pl = t >> 2, quarter = t & 3;
+      uint32_t wr[8], wi[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        // rdat holds (re, im) pairs for k = 2c and 2c + 1
+        wr[c] = (uint32_t)to_bf16(rdat[4 * c]) | ((uint32_t)to_bf16(rdat[4 * c + 2]) << 16);
+        wi[c] = (uint32_t)to_bf16(rdat[4 * c + 1]) | ((uint32_t)to_bf16(rdat[4 * c + 3]) << 16);
+      }
+      uint4* dr = (uint4*)&As[buf][2 * pl][16 * quarter];
+      uint4* di = (uint4*)&As[buf][2 * pl + 1][16 * quarter];
+      dr[0] = make_uint4(wr[0], wr[1], wr[2], wr[3]);
+      dr[1] = make_uint4(wr[4], wr[5], wr[6], wr[7]);
+      di[0] = make_uint4(wi[0], wi[1], wi[2], wi[3]);
+      di[1] = make_uint4(wi[4], wi[5], wi[6], wi[7]);
+    }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 32; ++ks) {
+      s8 av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = *(const s8*)&As[cur][wm * 64 + i * 16 + lr][ks * 32 + 8 * lg];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = *(const s8*)&Bs[cur][wn * 64 + j * 16 + lr][ks * 32 + 8 * lg];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+
+  TOut* Y = (TOut*)a.Y;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 64 + i * 16 + out_row<float>(lane, r);
+        const int64_t col = n0 + wn * 64 + j * 16 + lr;
+        double v = (double)acc[i][j][r];
+        double partner = 0.0;
+        if (EPI == (int)Epi::Exp) partner = __shfl_xor(v, 1);
+        if (ROWS) store_rows<TOut, CPLX>(a, Y, m, col, v);
+        else store_cols<TOut, CPLX, EPI>(a, Y, p, m, col, v, partner);
+      }
+}
+
+template <typename TIn, typename TOut>
+hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
+  KArgs a{};
+  fill_kargs(pa, a, pa.forward ? (const void*)pa.fac->QT16 : (const void*)pa.fac->Q16, BM, BN);
+  if (a.nblocks <= 0) return hipSuccess;
+  if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)a.nblocks), block(NT);
+  const bool rows = a.rows;
+  if (rows) {
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, true, 0>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, false, 0>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Exp) {
+    if (!pa.cplx) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Exp>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Inv) {
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Inv>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, (int)Epi::Inv>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, 0>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_pass_bf16(const PassArgs& pa, hipStream_t st) {
+  // intermediates are BF16; the first pass may read FP64/FP32 and the last write FP64/FP32
+  const DT i = pa.tin, o = pa.tout;
+  if (i == DT::F64 && o == DT::BF16) return launch_bf16_typed<double, uint16_t>(pa, st);
+  if (i == DT::F32 && o == DT::BF16) return launch_bf16_typed<float, uint16_t>(pa, st);
+  if (i == DT::BF16 && o == DT::BF16) return launch_bf16_typed<uint16_t, uint16_t>(pa, st);
+  if (i == DT::BF16 && o == DT::F64) return launch_bf16_typed<uint16_t, double>(pa, st);
+  if (i == DT::BF16 && o == DT::F32) return launch_bf16_typed<uint16_t, float>(pa, st);
+  if (i == DT::F64 && o == DT::F64) return launch_bf16_typed<double, double>(pa, st);
+  if (i == DT::F32 && o == DT::F32) return launch_bf16_typed<float, float>(pa, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ts

@@ -35,7 +35,7 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
   F->n = n;
   F->L = L;
   F->ld = round_up(n, kTileF);
-  F->kpad = round_up(n, kTileK);
+  F->kpad = F->ld;  // square padding: every kernel's tiles stay inside
   const double h = 2.0 * L / (double)(n + 1);
   const double ih2 = 1.0 / (h * h);
   F->ih2 = ih2;

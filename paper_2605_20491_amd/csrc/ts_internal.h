@@ -75,6 +75,7 @@ struct PassArgs {
 };
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);
+hipError_t launch_pass_bf16(const PassArgs& a, hipStream_t st);
 
 // Phase tables for the propagator: es[j] = e^{-i tau lam_s[j]},
 // Ep[p] = prod_{m<s} e^{-i tau lam_m[j_m(p)]}, Er[q] = prod_{m>s} (...).

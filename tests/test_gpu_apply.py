@@ -136,3 +136,25 @@ def test_eigvals_match_oracle():
         assert np.max(np.abs(lam - oplan.lam[k])) <= 1e-13 * np.abs(lam).max()
         Q = ts.ts_eigvecs(plan, k)
         assert np.max(np.abs(Q.T @ Q - np.eye(shape[k]))) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (130, 70, 150), (20, 17, 24, 19), (257, 129), (96, 64, 128)])
+def test_bf16_transforms_error_reported(shape):
+    """BF16 operands, FP32 accumulation: no exact value exists (parity unpinned);
+    the error against the FP64 oracle is reported and must sit at the BF16
+    rounding level (the paper's BF16 rows show 1.6e-2)."""
+    plan, oplan, _ = make_pair(shape, 8.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 7)
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    for dt in (torch.float64, torch.float32):
+        u = to_host(ts.ts_apply_inverse(plan, to_dev(b).to(dt), prec="bf16")).astype(np.float64)
+        e = rel(u, ref)
+        announce("bf16 inverse %s in=%s rel err %.3e" % (shape, dt, e))
+        assert 1e-5 < e <= 4e-2
+    psi = W.complex_normal(shape, 8)
+    refp = oracle.apply_exp(oplan, psi, 0.01)
+    for dt in (torch.complex128, torch.complex64):
+        out = to_host(ts.ts_apply_exp(plan, 0.01, to_dev(psi).to(dt), prec="bf16")).astype(np.complex128)
+        e = rel(out, refp)
+        announce("bf16 exp %s in=%s rel err %.3e" % (shape, dt, e))
+        assert 1e-5 < e <= 4e-2

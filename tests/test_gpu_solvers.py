@@ -150,3 +150,25 @@ def test_error_paths_forced_from_host():
     with pytest.raises(ts.TSError) as e:
         ts.ts_inverse_iteration(plan, None, 1e4, to_dev(f), steps=1)
     assert e.value.code == ts.TS_ERR_NOT_SPD
+
+
+def test_mixed_bf16_solvers_reach_fp64_tolerance():
+    """BF16 transforms inside refinement / flexible PCG still reach 1e-10 in FP64."""
+    shape, L = (64, 72, 80), 8.0
+    f_list = [W.f_harmonic(n, L) for n in shape]
+    plan = ts.ts_setup(shape, L, f_list, 1.0)
+    oplan = oracle.make_plan(shape, L, f_list)
+    f = W.rhs_normal(shape, 9)
+    u, it, rr = ts.ts_solve_refined(plan, to_dev(f), inner="bf16", rtol=1e-10, maxit=60)
+    uh = to_host(u)
+    true = np.linalg.norm(f - oracle.stencil_apply(oplan, uh, None, 1.0)) / np.linalg.norm(f)
+    announce("refined bf16: %d iterations, relres %.2e (oracle-stencil %.2e)" % (it, rr, true))
+    assert true <= 1.05e-10
+    V2 = W.gaussian_bumps(shape, L, 16, seed=3)
+    sigma = max(1.0, 0.5 - sum(l[0] for l in oplan.lam) - V2.min())
+    plan2 = ts.ts_setup(shape, L, f_list, sigma)
+    u, it, rr, _ = ts.ts_pcg_solve(plan2, to_dev(V2), to_dev(f), rtol=1e-10, precond="bf16")
+    uh = to_host(u)
+    true = np.linalg.norm(f - oracle.stencil_apply(oplan, uh, V2, sigma)) / np.linalg.norm(f)
+    announce("pcg bf16 preconditioner: %d iterations, relres %.2e (oracle-stencil %.2e)" % (it, rr, true))
+    assert true <= 1.05e-10
