@@ -1,0 +1,257 @@
+// Small-extent mode products (n_k <= 32 on every axis: the 6D / 9D grids of
+// the splitting workloads and small serving requests), HBM-bound.
+//
+// Consecutive axes are grouped so that a tile [PB][G][RT] of the tensor
+// viewed as [P][G][R] (G = product of the group's extents, R = faster
+// extents x components) fits in LDS.  One pass loads a tile, applies the
+// group's mode products one axis after the other inside LDS (one fibre per
+// thread in registers, the n x n factor staged in LDS and read as a broadcast),
+// and stores the tile back to the same place (passes run in place).  The
+// slowest group's pass also carries the diagonal scaling between its forward
+// and backward products (paper Sec. 2.1 steps 2-4, eq. (exact_prop)), so an
+// apply with g groups makes 2g - 1 round trips through HBM instead of 2d.
+// The pointwise potential factor e^{-i theta V2} of the splitting schemes
+// (Sec. 5.1) can be fused into the first load and the last store.
+#include "modeprod_common.h"
+#include "ts_internal.h"
+#include "ts_small.h"
+
+namespace ts {
+namespace {
+
+using namespace mp;
+
+constexpr int GT = 256;  // threads per block
+
+template <typename T> __device__ __forceinline__ void sincos_t(T x, T* s, T* c);
+template <> __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) { sincos(x, s, c); }
+template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+
+template <typename TIO, typename TC, int NMAX, bool CPLX>
+__global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
+  if (a.skip && *a.skip) return;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  TC* tile = (TC*)smem;
+  TC* Qs = tile + a.tile_elems;  // NMAX x NMAX
+
+  const int t = threadIdx.x;
+  const int64_t lb = xcd_logical_block(blockIdx.x, a.nblocks);
+  const int64_t ptile = lb / a.rtiles, rtile = lb % a.rtiles;
+  const int64_t p0 = ptile * a.PB, r0 = rtile * a.RT;
+  const int pb = (int)(a.P - p0 < a.PB ? a.P - p0 : a.PB);
+  const int rt = (int)(a.R - r0 < a.RT ? a.R - r0 : a.RT);
+  const int G = a.G, RT = a.RT;
+  const int elems = a.PB * G * RT;
+  const TIO* Xin = (const TIO*)a.Xin;
+  TIO* Xout = (TIO*)a.Xout;
+  const TIO* V2 = (const TIO*)a.V2;
+
+  // ---- load (optionally multiplied by e^{-i th_pre V2}) ----
+  if (CPLX) {
+    for (int e = 2 * t; e < elems; e += 2 * GT) {
+      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
+      TC re = 0, im = 0;
+      if (pl < pb && rl < rt) {
+        const int64_t gi = ((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl;
+        re = (TC)Xin[gi];
+        im = (TC)Xin[gi + 1];
+        if (a.pre) {
+          TC sn, cs;
+          sincos_t<TC>((TC)(-a.th_pre) * (TC)V2[gi >> 1], &sn, &cs);
+          const TC nr = cs * re - sn * im, ni = sn * re + cs * im;
+          re = nr;
+          im = ni;
+        }
+      }
+      tile[e] = re;
+      tile[e + 1] = im;
+    }
+  } else {
+    for (int e = t; e < elems; e += GT) {
+      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
+      TC v = 0;
+      if (pl < pb && rl < rt) v = (TC)Xin[((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl];
+      tile[e] = v;
+    }
+  }
+  __syncthreads();
+
+  for (int s = 0; s < a.nsteps; ++s) {
+    const GroupStep S = a.step[s];
+    const int n = S.n, st = S.stride;
+    const TC* Qg = (const TC*)S.Q;
+    for (int e = t; e < NMAX * NMAX; e += GT) {
+      const int i = e / NMAX, j = e % NMAX;
+      Qs[e] = (i < n && j < n) ? Qg[(int64_t)i * S.ld + j] : (TC)0;
+    }
+    __syncthreads();
+    const int outer = G / (n * st);
+    const int fibres = a.PB * outer * st * RT;
+    const int estep = st * RT;
+    for (int f = t; f < fibres; f += GT) {
+      const int rl = f % RT;
+      int rest = f / RT;
+      const int gin = rest % st;
+      rest /= st;
+      const int gout = rest % outer, pl = rest / outer;
+      const int base = (pl * G + gout * n * st + gin) * RT + rl;
+      TC x[NMAX], y[NMAX];
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) x[i] = (i < n) ? tile[base + i * estep] : (TC)0;
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j) y[j] = 0;
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        if (i < n) {
+          const TC xi = x[i];
+#pragma unroll
+          for (int j = 0; j < NMAX; ++j) y[j] += Qs[i * NMAX + j] * xi;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j)
+        if (j < n) tile[base + j * estep] = y[j];
+    }
+    __syncthreads();
+    if (s == a.scale_after) {
+      // diagonal of the slowest group's pass: element (g, q) with q = (r0 + rl) / ncomp
+      if (CPLX) {
+        for (int e = 2 * t; e < elems; e += 2 * GT) {
+          const int rl = e % RT, g = (e / RT) % G;
+          const int64_t q = (r0 + rl) >> 1;
+          if (rl < rt) {
+            const double2 f1 = a.Eg[g], f2 = a.Er[q];
+            const double fr = f1.x * f2.x - f1.y * f2.y, fi = f1.x * f2.y + f1.y * f2.x;
+            const double re = tile[e], im = tile[e + 1];
+            tile[e] = (TC)(fr * re - fi * im);
+            tile[e + 1] = (TC)(fi * re + fr * im);
+          }
+        }
+      } else {
+        for (int e = t; e < elems; e += GT) {
+          const int rl = e % RT, g = (e / RT) % G;
+          if (rl < rt) tile[e] = (TC)((double)tile[e] / (a.Lg[g] + a.Lr[r0 + rl] + a.shift));
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- store (optionally multiplied by e^{-i th_post V2}) ----
+  if (CPLX) {
+    for (int e = 2 * t; e < elems; e += 2 * GT) {
+      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
+      if (pl < pb && rl < rt) {
+        const int64_t gi = ((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl;
+        TC re = tile[e], im = tile[e + 1];
+        if (a.post) {
+          TC sn, cs;
+          sincos_t<TC>((TC)(-a.th_post) * (TC)V2[gi >> 1], &sn, &cs);
+          const TC nr = cs * re - sn * im, ni = sn * re + cs * im;
+          re = nr;
+          im = ni;
+        }
+        Xout[gi] = (TIO)re;
+        Xout[gi + 1] = (TIO)im;
+      }
+    }
+  } else {
+    for (int e = t; e < elems; e += GT) {
+      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
+      if (pl < pb && rl < rt) Xout[((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl] = (TIO)tile[e];
+    }
+  }
+}
+
+template <typename TIO, typename TC, bool CPLX>
+hipError_t launch_nmax(const GroupArgs& a, int nmax, hipStream_t st) {
+  const size_t lds = sizeof(TC) * ((size_t)a.tile_elems + (size_t)nmax * nmax);
+  dim3 grid((unsigned)a.nblocks), block(GT);
+  switch (nmax) {
+    case 8: hipLaunchKernelGGL((k_group<TIO, TC, 8, CPLX>), grid, block, lds, st, a); break;
+    case 16: hipLaunchKernelGGL((k_group<TIO, TC, 16, CPLX>), grid, block, lds, st, a); break;
+    case 24: hipLaunchKernelGGL((k_group<TIO, TC, 24, CPLX>), grid, block, lds, st, a); break;
+    case 32: hipLaunchKernelGGL((k_group<TIO, TC, 32, CPLX>), grid, block, lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int small_nmax(int64_t n) {
+  if (n <= 8) return 8;
+  if (n <= 16) return 16;
+  if (n <= 24) return 24;
+  if (n <= 32) return 32;
+  return 0;
+}
+
+hipError_t launch_group(const GroupArgs& a, DT tio, bool fp64_compute, bool cplx, int nmax, hipStream_t st) {
+  if (a.nblocks <= 0) return hipSuccess;
+  if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  if (tio == DT::F64 && fp64_compute)
+    return cplx ? launch_nmax<double, double, true>(a, nmax, st) : launch_nmax<double, double, false>(a, nmax, st);
+  if (tio == DT::F64 && !fp64_compute)
+    return cplx ? launch_nmax<double, float, true>(a, nmax, st) : launch_nmax<double, float, false>(a, nmax, st);
+  if (tio == DT::F32 && !fp64_compute)
+    return cplx ? launch_nmax<float, float, true>(a, nmax, st) : launch_nmax<float, float, false>(a, nmax, st);
+  return hipErrorInvalidValue;
+}
+
+// ---- pointwise e^{-i theta V2} on interleaved complex data (generic path) ----
+template <typename T>
+__global__ __launch_bounds__(256) void k_phase(T* psi, const T* V2, double theta, int64_t N) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    T sn, cs;
+    sincos_t<T>((T)(-theta) * V2[i], &sn, &cs);
+    const T re = psi[2 * i], im = psi[2 * i + 1];
+    psi[2 * i] = cs * re - sn * im;
+    psi[2 * i + 1] = sn * re + cs * im;
+  }
+}
+
+hipError_t launch_phase(void* psi, const void* V2, double theta, int64_t N, bool fp64, hipStream_t st) {
+  const unsigned grid = (unsigned)std::min<int64_t>((N + 255) / 256, 8192);
+  if (grid == 0) return hipSuccess;
+  if (fp64) hipLaunchKernelGGL(k_phase<double>, dim3(grid), dim3(256), 0, st, (double*)psi, (const double*)V2, theta, N);
+  else hipLaunchKernelGGL(k_phase<float>, dim3(grid), dim3(256), 0, st, (float*)psi, (const float*)V2, theta, N);
+  return hipGetLastError();
+}
+
+// ---- FP64 tables over two axis ranges [0, split) and [split, d) ----
+// mode 0: sums of eigenvalues (Lg, Lr); mode 1: products of e^{-i tau lam} (Eg, Er).
+__global__ void k_range_tables(RangeTableArgs a) {
+  const int64_t total = a.n_lo + a.n_hi;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const bool lo = e < a.n_lo;
+    int64_t idx = lo ? e : e - a.n_lo;
+    const int kb = lo ? 0 : a.split, ke = lo ? a.split : a.d;
+    double sum = 0.0, re = 1.0, im = 0.0;
+    for (int k = ke - 1; k >= kb; --k) {
+      const int64_t j = idx % a.n[k];
+      idx /= a.n[k];
+      const double l = a.lam[k][j];
+      if (a.mode == 0) {
+        sum += l;
+      } else {
+        double sn, cs;
+        sincos(a.tau * l, &sn, &cs);
+        const double nr = re * cs + im * sn, ni = im * cs - re * sn;  // times (cs - i sn)
+        re = nr;
+        im = ni;
+      }
+    }
+    if (a.mode == 0) (lo ? a.L_lo : a.L_hi)[lo ? e : e - a.n_lo] = sum;
+    else (lo ? a.E_lo : a.E_hi)[lo ? e : e - a.n_lo] = make_double2(re, im);
+  }
+}
+
+hipError_t launch_range_tables(const RangeTableArgs& a, hipStream_t st) {
+  const int64_t total = a.n_lo + a.n_hi;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_range_tables, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace ts

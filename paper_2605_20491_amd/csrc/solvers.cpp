@@ -351,9 +351,4 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
   return TS_OK;
 }
 
-int ts_split_step(ts_plan*, const void*, void*, double, int, int, int, int, void*) {
-  set_error("ts_split_step: not available in this build");
-  return TS_ERR_INVALID;
-}
-
 }  // extern "C"

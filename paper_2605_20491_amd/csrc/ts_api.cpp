@@ -12,6 +12,7 @@
 #include "../../include/ts.h"
 #include "ts_internal.h"
 #include "ts_apply.h"
+#include "ts_small.h"
 
 namespace ts {
 
@@ -176,6 +177,18 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
     set_error("H1 + sigma is not positive definite: lambda_min(H1) + sigma = " + std::to_string(p->lam_min + shift));
     return TS_ERR_NOT_SPD;
   }
+  if (plan_is_small(p)) {
+    SmallApply sa;
+    sa.in = b;
+    sa.out = u;
+    sa.tio = dt_of(dtype);
+    sa.fp64 = prec == TS_PREC_FP64;
+    sa.cplx = false;
+    sa.epi = Epi::Inv;
+    sa.shift = shift;
+    sa.skip = skip;
+    return run_small_apply(p, sa, st);
+  }
   if (!work) {
     int rc = plan_workspace(p, (size_t)p->N * 8, &work);
     if (rc) return rc;
@@ -193,13 +206,18 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
   return run_apply(p, ap, st);
 }
 
-int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
-                   hipStream_t st, void* work) {
+static int check_exp_args(ts_plan* p, double tau, const void* in, const void* out, int dtype, int prec) {
   if (!p || !in || !out) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_C128 && dtype != TS_C64) { set_error("propagator needs TS_C128 or TS_C64 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
   if (prec == TS_PREC_FP64 && dtype != TS_C128) { set_error("FP64 transforms need TS_C128 data"); return TS_ERR_INVALID; }
   if (!std::isfinite(tau)) { set_error("tau is not finite"); return TS_ERR_INVALID; }
+  return TS_OK;
+}
+
+// The MFMA-path propagator: phase tables for the scaling axis, then 2d passes.
+static int exp_mfma(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec, hipStream_t st,
+                    void* work) {
   if (!work) {
     int rc = plan_workspace(p, (size_t)p->N * 16, &work);
     if (rc) return rc;
@@ -230,9 +248,63 @@ int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype,
   return run_apply(p, ap, st);
 }
 
+int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
+                   hipStream_t st, void* work) {
+  int rc = check_exp_args(p, tau, in, out, dtype, prec);
+  if (rc) return rc;
+  if (plan_is_small(p)) {
+    SmallApply sa;
+    sa.in = in;
+    sa.out = out;
+    sa.tio = dt_of(dtype);
+    sa.fp64 = prec == TS_PREC_FP64;
+    sa.cplx = true;
+    sa.epi = Epi::Exp;
+    sa.tau = tau;
+    return run_small_apply(p, sa, st);
+  }
+  return exp_mfma(p, tau, in, out, dtype, prec, st, work);
+}
+
+int apply_exp_phased(ts_plan* p, double tau, void* psi, int dtype, int prec, const Phases& ph,
+                     hipStream_t st, void* work) {
+  int rc = check_exp_args(p, tau, psi, psi, dtype, prec);
+  if (rc) return rc;
+  const bool fp64_data = dtype == TS_C128;
+  if (plan_is_small(p)) {
+    SmallApply sa;
+    sa.in = psi;
+    sa.out = psi;
+    sa.tio = dt_of(dtype);
+    sa.fp64 = prec == TS_PREC_FP64;
+    sa.cplx = true;
+    sa.epi = Epi::Exp;
+    sa.tau = tau;
+    sa.V2 = ph.V2;
+    sa.pre = ph.pre;
+    sa.post = ph.post;
+    sa.th_pre = ph.th_pre;
+    sa.th_post = ph.th_post;
+    return run_small_apply(p, sa, st);
+  }
+  hipError_t e;
+  if (ph.pre) {
+    e = launch_phase(psi, ph.V2, ph.th_pre, p->N, fp64_data, st);
+    if (e != hipSuccess) { set_error("phase launch failed"); return TS_ERR_DEVICE; }
+  }
+  rc = exp_mfma(p, tau, psi, psi, dtype, prec, st, work);
+  if (rc) return rc;
+  if (ph.post) {
+    e = launch_phase(psi, ph.V2, ph.th_post, p->N, fp64_data, st);
+    if (e != hipSuccess) { set_error("phase launch failed"); return TS_ERR_DEVICE; }
+  }
+  return TS_OK;
+}
+
 }  // namespace ts
 
 ts_plan::~ts_plan() {
+  hipFree(small_tab);
   hipFree(solver);
   if (solver_host) hipHostFree(solver_host);
   hipFree(Lp);

@@ -28,4 +28,14 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
 int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
                    hipStream_t st, void* work);
 
+// Optional pointwise potential factors around one propagator apply (in place,
+// psi_in == psi_out): psi <- e^{-i th_post V2} e^{-i tau H1} e^{-i th_pre V2} psi.
+struct Phases {
+  const void* V2 = nullptr;
+  bool pre = false, post = false;
+  double th_pre = 0.0, th_post = 0.0;
+};
+int apply_exp_phased(ts_plan* p, double tau, void* psi, int dtype, int prec, const Phases& ph,
+                     hipStream_t st, void* work);
+
 }  // namespace ts

@@ -118,5 +118,7 @@ struct ts_plan {
   void* solver = nullptr;      // solver vectors, partial sums and scalars
   size_t solver_bytes = 0;
   void* solver_host = nullptr; // pinned host mirror of the solver scalars
+  void* small_tab = nullptr;   // diagonal tables of the grouped small-extent path
+  size_t small_tab_bytes = 0;
   ~ts_plan();
 };

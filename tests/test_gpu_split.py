@@ -1,0 +1,132 @@
+"""Small-extent grouped apply and the splitting schemes (Sec. 5.1) on the GPU.
+
+* grouped passes (every n_k <= 32): inverse and propagator parity with the
+  oracle on 1D-9D grids, FP64 bar 1e-12, FP32 at the FP32 rounding level;
+* ts_split_step against the oracle's literal (unmerged) product of factors for
+  Strang (BAB, ABA) and Yoshida, complex128 after 100 steps;
+* V2 = 0 reproduces the exact propagator; constant V2 is a global phase;
+* the splitting workload at full size (6D n = 24, 9D n = 8, 100 steps,
+  dt = 1e-3, pairwise V2 on [-6,6]^d, superposition of the 4 lowest separable
+  eigenfunctions): with V2 = 0 the result is the closed form
+  sum_m c_m e^{-i Lambda_m T} Phi_m; with V2 the complex64 run is compared with
+  the complex128 run and the norm drift is reported.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_20491_amd as ts
+import workloads as W
+from gpu_common import DEV, announce, exp_tol, make_pair, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(30,), (31, 32), (32, 17, 29), (16, 16, 16), (12, 10, 11, 9, 8, 7), (5, 4, 5, 4, 3, 4, 3, 4, 5),
+         (1, 7, 1, 3)]
+
+
+@pytest.mark.parametrize("shape", SMALL)
+def test_grouped_apply_fp64_parity(shape):
+    plan, oplan, _ = make_pair(shape, 6.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 1)
+    e1 = rel(to_host(ts.ts_apply_inverse(plan, to_dev(b))), oracle.apply_inverse(oplan, b, 1.0))
+    psi = W.complex_normal(shape, 2)
+    e2 = rel(to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi))), oracle.apply_exp(oplan, psi, 0.05))
+    announce("grouped %s: inverse %.2e exp %.2e" % (shape, e1, e2))
+    assert e1 <= 1e-12 and e2 <= exp_tol(oplan, 0.05)
+
+
+@pytest.mark.parametrize("shape", [(32, 17, 29), (12, 10, 11, 9, 8, 7)])
+def test_grouped_apply_fp32(shape):
+    plan, oplan, _ = make_pair(shape, 6.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 1)
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    for dt, prec in ((torch.float32, "fp32"), (torch.float64, "fp32"), (torch.float32, "bf16")):
+        u = to_host(ts.ts_apply_inverse(plan, to_dev(b).to(dt), prec=prec)).astype(np.float64)
+        assert rel(u, ref) <= 2e-6
+    psi = W.complex_normal(shape, 2)
+    out = to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi).to(torch.complex64), prec="fp32"))
+    assert rel(out.astype(np.complex128), oracle.apply_exp(oplan, psi, 0.05)) <= 2e-6
+
+
+SCHEMES = ["strang_bab", "strang_aba", "yoshida_bab", "yoshida_aba"]
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("shape,L", [((5, 5, 5, 5, 5, 5), 6.0), ((3,) * 9, 6.0), ((33, 40), 6.0)])
+def test_split_matches_oracle_product(scheme, shape, L):
+    """complex128, 100 steps of dt = 1e-3; the (33, 40) grid takes the MFMA path."""
+    plan, oplan, _ = make_pair(shape, L, "harm", sigma=1.0)
+    V2 = W.pairwise_v2(shape, L)
+    psi0 = W.complex_normal(shape, 3)
+    psi0 /= np.linalg.norm(psi0)
+    t = to_dev(psi0)
+    ts.ts_split_step(plan, to_dev(V2), t, 1e-3, 100, scheme)
+    got = to_host(t)
+    ref = oracle.split_propagate(oplan, V2, psi0, 1e-3, 100, scheme)
+    e = rel(got, ref)
+    announce("split %s %s: rel err vs literal product %.2e, |norm-1| %.1e"
+             % (scheme, shape, e, abs(np.linalg.norm(got) - 1)))
+    assert e <= 1e-12
+    # 100 steps of ~2d rounded passes each: drift of a few 1e-13
+    assert abs(np.linalg.norm(got) - 1) <= 1e-12
+    # complex64 with FP32 transforms on the same input
+    t64 = to_dev(psi0).to(torch.complex64)
+    ts.ts_split_step(plan, to_dev(V2).to(torch.float32), t64, 1e-3, 100, scheme, prec="fp32")
+    e64 = rel(to_host(t64).astype(np.complex128), ref)
+    announce("  complex64: rel err %.2e" % e64)
+    assert e64 <= 2e-5
+
+
+def test_split_exactness_cases():
+    shape, L = (6, 5, 7, 4), 4.0
+    plan, oplan, _ = make_pair(shape, L, "harm", sigma=1.0)
+    psi0 = W.complex_normal(shape, 4)
+    ref = oracle.apply_exp(oplan, psi0, 0.05)
+    for scheme in SCHEMES:
+        t = to_dev(psi0)
+        ts.ts_split_step(plan, to_dev(np.zeros(shape)), t, 1e-3, 50, scheme)
+        assert rel(to_host(t), ref) <= 1e-12
+        t = to_dev(psi0)
+        ts.ts_split_step(plan, to_dev(np.full(shape, 2.5)), t, 1e-3, 50, scheme)
+        assert rel(to_host(t), np.exp(-1j * 2.5 * 0.05) * ref) <= 1e-12
+    t = to_dev(psi0)
+    ts.ts_split_step(plan, to_dev(np.zeros(shape)), t, 1e-3, 0, "strang_bab")
+    assert rel(to_host(t), psi0) == 0.0
+
+
+@pytest.mark.parametrize("d,n", [(6, 24), (9, 8)])
+def test_split_workload_full_size(d, n):
+    L, dt, steps = 6.0, 1e-3, 100
+    shape = (n,) * d
+    f = [W.f_harmonic(n, L) for _ in range(d)]
+    plan = ts.ts_setup(shape, L, f, 1.0)
+    w, Q = oracle.jacobi_eigh(oracle.fd_axis_matrix(n, L, f[0]))
+    terms = W.superposition_terms([Q] * d, [w] * d, 4, seed=4)
+    psi0 = W.superposition_grid([Q] * d, terms)
+    T = dt * steps
+    exact = sum(cm * np.exp(-1j * T * sum(w[j] for j in idx)) * W.outer([Q[:, j] for j in idx])
+                for cm, idx in terms)
+    announce("split workload %dD n=%d: V2 = 0 closed form" % (d, n))
+    t = to_dev(psi0)
+    ts.ts_split_step(plan, torch.zeros(shape, dtype=torch.float64, device=DEV), t, dt, steps, "strang_bab")
+    e0 = rel(to_host(t), exact)
+    announce("  V2=0 complex128 Strang vs closed form: %.2e" % e0)
+    assert e0 <= 1e-12
+    V2 = W.pairwise_v2(shape, L)
+    res = {}
+    for scheme in ("strang_bab", "yoshida_bab"):
+        t = to_dev(psi0)
+        ts.ts_split_step(plan, to_dev(V2), t, dt, steps, scheme)
+        t64 = to_dev(psi0).to(torch.complex64)
+        ts.ts_split_step(plan, to_dev(V2).to(torch.float32), t64, dt, steps, scheme, prec="fp32")
+        a, b = to_host(t), to_host(t64).astype(np.complex128)
+        drift128 = abs(np.linalg.norm(a) - 1)
+        drift64 = abs(np.linalg.norm(b) - 1)
+        e = rel(b, a)
+        announce("  %s: norm drift c128 %.1e c64 %.1e; c64 vs c128 %.2e" % (scheme, drift128, drift64, e))
+        assert drift128 <= 1e-12 and drift64 <= 1e-5 and e <= 5e-5
+        res[scheme] = a
+    # Strang and Yoshida agree to the splitting error (order dt^2 T ||[A,B]||, small here)
+    assert rel(res["strang_bab"], res["yoshida_bab"]) <= 1e-4

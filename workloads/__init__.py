@@ -135,3 +135,44 @@ def complex_normal(shape, seed: int) -> np.ndarray:
 
 
 __all__ = [n for n in dir() if not n.startswith("_") and n not in ("math", "np", "annotations")]
+
+
+def lowest_separable_modes(lams, count: int):
+    """Multi-indices of the `count` lowest separable eigenfunctions.
+
+    Sorted by (eigenvalue sum rounded to 1e-9 relative, multi-index in
+    lexicographic order), which breaks the degeneracies of identical axes
+    deterministically.  lams[k]: ascending eigenvalues of axis k.
+    """
+    import itertools
+    d = len(lams)
+    cand = []
+    depth = 3
+    for idx in itertools.product(*[range(min(depth, len(l))) for l in lams]):
+        s = sum(float(lams[k][idx[k]]) for k in range(d))
+        cand.append((s, idx))
+    top = max(abs(c[0]) for c in cand) or 1.0
+    cand.sort(key=lambda c: (round(c[0] / (1e-9 * top)), c[1]))
+    return [c[1] for c in cand[:count]]
+
+
+def superposition_terms(Qs, lams, count: int, seed: int):
+    """Seeded superposition of the `count` lowest separable eigenfunctions.
+
+    Returns [(c_m, multi_index_m)] with c_m ~ CN(0,1) normalised so that
+    sum |c_m|^2 = 1 (the eigenfunctions are orthonormal); Qs[k][:, j] is the
+    j-th eigenvector of axis k.
+    """
+    modes = lowest_separable_modes(lams, count)
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(count) + 1j * rng.standard_normal(count)
+    c /= np.linalg.norm(c)
+    return list(zip(c, modes))
+
+
+def superposition_grid(Qs, terms) -> np.ndarray:
+    out = None
+    for cm, idx in terms:
+        t = cm * outer([Qs[k][:, j] for k, j in enumerate(idx)])
+        out = t if out is None else out + t
+    return out
