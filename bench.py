@@ -127,6 +127,172 @@ def invit_section(ts, W, torch, dev, n, precs, steps=20):
     return out
 
 
+def pairwise_on_device(W, torch, dev, shape, L, dtype):
+    """V2 = sum_{i<j} 0.5 / (1 + (x_i - x_j)^2), evaluated on the device."""
+    d = len(shape)
+    ax = [torch.from_numpy(W.grid_nodes(n, L)).to(dev) for n in shape]
+    V = torch.zeros(shape, dtype=torch.float64, device=dev)
+    for i in range(d):
+        for j in range(i + 1, d):
+            vi = ax[i].reshape([-1 if k == i else 1 for k in range(d)])
+            vj = ax[j].reshape([-1 if k == j else 1 for k in range(d)])
+            V += 0.5 / (1.0 + (vi - vj) ** 2)
+    return V.to(dtype)
+
+
+def split_section(ts, W, torch, dev, d, n, steps=100, dt=1e-3):
+    """Splitting workload: V1 = sum x^2 on [-6,6]^d, pairwise V2, psi0 = seeded
+    superposition of the 4 lowest separable eigenfunctions, 100 steps of 1e-3."""
+    import numpy as np
+    L = 6.0
+    shape = (n,) * d
+    N = n ** d
+    f = [W.f_harmonic(n, L) for _ in range(d)]
+    plan = ts.ts_setup(shape, L, f, 1.0)
+    Q = ts.ts_eigvecs(plan, 0)
+    w = ts.ts_eigvals(plan, 0)
+    terms = W.superposition_terms([Q] * d, [w] * d, 4, seed=4)
+    out = {"d": d, "n": n, "dofs": N, "steps": steps, "dt": dt}
+    for dtype, prec in ((torch.complex64, "fp32"), (torch.complex128, "fp64")):
+        V2 = pairwise_on_device(W, torch, dev, shape, L, torch.float32 if dtype == torch.complex64 else torch.float64)
+        psi0 = torch.zeros(shape, dtype=dtype, device=dev)
+        for cm, idx in terms:
+            t = torch.ones((), dtype=dtype, device=dev)
+            for k, j in enumerate(idx):
+                t = t.unsqueeze(-1) * torch.from_numpy(Q[:, j].copy()).to(dev).to(dtype)
+            psi0 += complex(cm) * t
+        for scheme in ("strang_bab", "yoshida_bab"):
+            psi = psi0.clone()
+            ts.ts_split_step(plan, V2, psi, dt, 2, scheme, prec=prec)   # warm-up
+            psi = psi0.clone()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ts.ts_split_step(plan, V2, psi, dt, steps, scheme, prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            n_apply = steps + 1 if scheme == "strang_bab" else 3 * steps + 1
+            drift = abs(float(torch.linalg.vector_norm(psi)) / float(torch.linalg.vector_norm(psi0)) - 1.0)
+            key = "%s_%s" % (scheme, "c64" if dtype == torch.complex64 else "c128")
+            out[key] = {"ms_per_step": ms / steps, "ms_per_apply": ms / n_apply, "norm_drift": drift,
+                        "dof_s_per_apply": N / (ms / n_apply * 1e-3)}
+            log("split %dD n=%d %s: %.2f ms/step, drift %.1e" % (d, n, key, ms / steps, drift))
+        del V2, psi0, psi
+        torch.cuda.empty_cache()
+    return out
+
+
+SERVE_SHAPES = [(2048, 2048), (128, 128, 128), (256, 256, 256), (512, 512, 512), (64,) * 4, (16,) * 6]
+SERVE_KINDS = ["inverse_fp64", "inverse_mixed", "exp_c64"]
+
+
+def serve_stream(seed, count, rate):
+    """Seeded Poisson arrivals; each request draws a shape, a kind, V2 present with
+    probability 1/2 and tau ~ U[1e-3, 1e-1]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        reqs.append({"t": t, "shape": SERVE_SHAPES[rng.integers(len(SERVE_SHAPES))],
+                     "kind": SERVE_KINDS[rng.integers(len(SERVE_KINDS))], "v2": bool(rng.integers(2)),
+                     "tau": float(rng.uniform(1e-3, 1e-1))})
+    return reqs
+
+
+def serve_run(ts, W, torch, dev, reqs, mode, inputs):
+    """Replay the stream against a server.  mode: 'batch' (4 streams, no cap),
+    'fp64' (same, every request in plain FP64), 'fifo' (1 stream, 1 request)."""
+    import numpy as np
+    n_streams, max_active = (1, 1) if mode == "fifo" else (4, 0)
+    srv = ts.Server(64 << 30, n_streams, max_active)
+    L = 8.0
+
+    def submit(r, tag):
+        shape = r["shape"]
+        f = inputs["f"][shape]
+        V2 = inputs["v2"][shape] if r["v2"] else None
+        if r["kind"].startswith("inverse"):
+            x = inputs["rhs"][shape]
+            prec = "fp64" if (mode == "fp64" or r["kind"] == "inverse_fp64") else "bf16"
+            out = torch.empty_like(x)
+            return srv.submit(ts.TS_REQ_INVERSE, shape, L, f, inputs["sigma"][shape], x, out, prec=prec, V2=V2,
+                              rtol=1e-10, maxit=500 if V2 is not None else 60, tag=tag)
+        c128 = mode == "fp64"
+        x = inputs["psi128" if c128 else "psi64"][shape]
+        V2 = None if V2 is None else (V2 if c128 else inputs["v2f"][shape])
+        out = torch.empty_like(x)
+        return srv.submit(ts.TS_REQ_EXP, shape, L, f, 1.0, x, out, prec="fp64" if c128 else "fp32", V2=V2,
+                          tau=r["tau"], dt=1e-2, tag=tag)
+
+    # warm the plan cache and the kernels with one request per (shape, kind, V2)
+    seen = set()
+    for r in reqs:
+        k = (r["shape"], r["kind"], r["v2"])
+        if k not in seen:
+            seen.add(k)
+            submit(r, 0)
+    srv.drain()
+    torch.cuda.synchronize()
+    t0 = srv.clock()
+    tickets = {}
+    pending = list(enumerate(reqs))
+    results = {}
+    while pending or tickets:
+        now = srv.clock() - t0
+        while pending and pending[0][1]["t"] <= now:
+            i, r = pending.pop(0)
+            tickets[i] = submit(r, i)
+        for i in list(tickets):
+            res = srv.poll(tickets[i])
+            if res is not None:
+                results[i] = (res, t0 + reqs[i]["t"])
+                del tickets[i]
+        time.sleep(0.0005)
+    makespan = max(res.t_done for res, _ in results.values()) - t0
+    lat = np.array([res.t_done - arr for res, arr in results.values()])
+    ok = sum(1 for res, _ in results.values() if res.status == 0)
+    dofs = sum(int(np.prod(r["shape"])) for r in reqs)
+    srv.close()
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "makespan_s": makespan, "dof_s": dofs / makespan, "ok": ok, "requests": len(reqs)}
+
+
+def serve_section(ts, W, torch, dev, count, rate=200.0):
+    """Serving mix: Poisson 200 req/s over {2D 2048; 3D 128/256/512; 4D 64; 6D 16}
+    x {inverse FP64, inverse mixed (BF16 + refinement / BF16-preconditioned PCG),
+    exp complex64 tau ~ U[1e-3, 1e-1]}, V2 zero or 8 seeded bumps."""
+    L = 8.0
+    reqs = serve_stream(5, count, rate)
+    inputs = {"f": {}, "v2": {}, "v2f": {}, "rhs": {}, "psi64": {}, "psi128": {}, "sigma": {}}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    for shape in SERVE_SHAPES:
+        inputs["f"][shape] = [W.f_harmonic(n, L) for n in shape]
+        V2 = bumps_on_device(W, torch, dev, shape, L, 8, 5)
+        inputs["v2"][shape] = V2
+        inputs["v2f"][shape] = V2.to(torch.float32)
+        inputs["rhs"][shape] = torch.randn(shape, dtype=torch.float64, device=dev, generator=gen)
+        facs = W.wavepacket_factors(shape, L, 5)
+        psi = torch.ones((), dtype=torch.complex128, device=dev)
+        for g in facs:
+            psi = psi.unsqueeze(-1) * torch.from_numpy(g).to(dev)
+        inputs["psi128"][shape] = psi.contiguous()
+        inputs["psi64"][shape] = psi.to(torch.complex64)
+        # sigma: 1, raised so that H1 + V2 + sigma >= 0.5 (lambda_min(H1) >= sum of min f_k)
+        lam_lb = sum(float(min(f)) for f in inputs["f"][shape])
+        inputs["sigma"][shape] = max(1.0, 0.5 - lam_lb - float(V2.min()))
+    out = {"requests": count, "rate_per_s": rate}
+    for mode in ("batch", "fp64", "fifo"):
+        out[mode] = serve_run(ts, W, torch, dev, reqs, mode, inputs)
+        log("serve %s: p50 %.1f ms p99 %.1f ms, %.3e DoF/s, %d/%d ok" % (
+            mode, out[mode]["p50_ms"], out[mode]["p99_ms"], out[mode]["dof_s"], out[mode]["ok"], count))
+    return out
+
+
 def cpu_baseline(n, depth):
     """The oracle's six mode products on slabs holding `depth` x n full fibres per axis."""
     import numpy as np
@@ -159,6 +325,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-depth", type=int, default=96)
     ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
@@ -238,6 +406,12 @@ def main():
         extra["pcg_n256"] = pcg_section(ts, W, torch, dev, 256, precs)
         extra["pcg_n512"] = pcg_section(ts, W, torch, dev, 512, precs)
         extra["inverse_iteration_n256"] = invit_section(ts, W, torch, dev, 256, precs)
+        torch.cuda.empty_cache()
+    if not args.no_split:
+        extra["split_6d_n24"] = split_section(ts, W, torch, dev, 6, 24)
+        extra["split_9d_n8"] = split_section(ts, W, torch, dev, 9, 8)
+    if args.serve_requests > 0:
+        extra["serving"] = serve_section(ts, W, torch, dev, args.serve_requests)
         torch.cuda.empty_cache()
     extra["paper_context"] = ("FP64 direct inverse, 1099^3 (Q^1 = FD), NVIDIA GH200: 0.508 s = 2.61e9 DoF/s "
                               "(Table tab:accuracy_gh200); not the same workload or hardware")

@@ -220,6 +220,76 @@ int ts_tridiag_eig(int64_t n, const double* diag, const double* off, double* lam
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* ts_last_error(void);
 
+/* ------------------------------------------------------------- serving -- */
+/* A request loop over the applies and solvers above (not part of the paper):
+ * requests of different d, n and kind are admitted as device memory frees
+ * up, run concurrently on a pool of HIP streams, and keep their operator
+ * factors resident in a plan cache.  Each admitted request advances in small
+ * units (one apply, one refinement sweep, a few PCG iterations, a few split
+ * steps), so requests that arrive while others run join between units.
+ * Results do not depend on what else runs: every kernel is deterministic and
+ * a request's arithmetic does not depend on the schedule. */
+typedef struct ts_server ts_server;
+
+typedef enum {
+  TS_REQ_INVERSE = 0, /* solve: V2 == NULL and prec FP64 -> one direct apply;
+                         V2 == NULL, prec FP32/BF16 -> refinement to rtol;
+                         V2 != NULL -> PCG to rtol with a prec preconditioner */
+  TS_REQ_EXP = 1      /* propagate: V2 == NULL -> exact e^{-i tau H1};
+                         V2 != NULL -> Strang (BAB) steps of dt covering tau */
+} ts_req_kind;
+
+typedef struct {
+  int kind;               /* ts_req_kind */
+  int d;                  /* grid: as ts_setup (f[k] are HOST pointers, read at submit) */
+  int64_t n[12];
+  double L;
+  const double* f[12];
+  double sigma;
+  int dtype;              /* TS_F64 for INVERSE; TS_C128 / TS_C64 for EXP */
+  int prec;               /* ts_prec of the transforms */
+  const void* in;         /* DEVICE, caller-owned, valid and unchanged until done */
+  void* out;              /* DEVICE, caller-owned (may equal in) */
+  const void* V2;         /* DEVICE or NULL: FP64 (INVERSE, C128) or FP32 (C64) */
+  double tau;             /* EXP: total time */
+  double dt;              /* EXP with V2: step (nsteps = ceil(|tau| / dt)) */
+  double rtol;            /* INVERSE iterative forms */
+  int maxit;
+  uint64_t tag;           /* echoed in the result */
+} ts_request;
+
+typedef struct {
+  int status;             /* ts_status of the request */
+  int iters;              /* sweeps / PCG iterations / split steps */
+  double relres;          /* true relative residual of iterative solves, else 0 */
+  double t_submit, t_admit, t_done;  /* seconds on the server's clock */
+  uint64_t tag;
+} ts_result;
+
+/* Create a server on the current device.  hbm_budget_bytes is the arena
+ * from which every admitted request's scratch is carved (allocated once,
+ * here; resident factors of the plan cache are allocated outside it);
+ * n_streams >= 1 non-blocking HIP streams of default priority; max_active
+ * caps the requests in flight (0 = no cap; 1 with one stream = plain FIFO). */
+int ts_serve_create(size_t hbm_budget_bytes, int n_streams, int max_active, ts_server** out);
+
+/* Queue a request; it is admitted when its scratch fits.  Returns a ticket.
+ * TS_ERR_NOMEM if the request could never fit the budget, TS_ERR_INVALID for
+ * a malformed request. */
+int ts_serve_submit(ts_server* s, const ts_request* req, uint64_t* ticket);
+
+/* Non-blocking: *done = 1 and *res filled once the request has finished. */
+int ts_serve_poll(ts_server* s, uint64_t ticket, int* done, ts_result* res);
+
+/* Block until every submitted request has finished. */
+int ts_serve_drain(ts_server* s);
+
+/* Seconds on the server's clock (for arrival timestamps). */
+double ts_serve_clock(ts_server* s);
+
+/* Stop the scheduler (after draining), release the arena, plans and streams. */
+int ts_serve_destroy(ts_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -291,3 +291,107 @@ def ts_tridiag_eig(diag: np.ndarray, off: np.ndarray):
     offp = _dptr(off) if off.size else _dptr(np.zeros(1))
     _check(lib().ts_tridiag_eig(n, _dptr(diag), offp, _dptr(lam), _dptr(Q)), "ts_tridiag_eig")
     return lam, Q
+
+
+# ------------------------------------------------------------------ serving --
+
+TS_REQ_INVERSE, TS_REQ_EXP = 0, 1
+
+
+class TsRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("d", ctypes.c_int), ("n", ctypes.c_int64 * 12), ("L", ctypes.c_double),
+                ("f", ctypes.c_void_p * 12), ("sigma", ctypes.c_double), ("dtype", ctypes.c_int),
+                ("prec", ctypes.c_int), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("V2", ctypes.c_void_p), ("tau", ctypes.c_double), ("dt", ctypes.c_double),
+                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("tag", ctypes.c_uint64)]
+
+
+class TsResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("relres", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("tag", ctypes.c_uint64)]
+
+
+def _serve_lib():
+    L = lib()
+    if not hasattr(L, "_serve_ready"):
+        L.ts_serve_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]
+        L.ts_serve_submit.argtypes = [_vp, ctypes.POINTER(TsRequest), ctypes.POINTER(ctypes.c_uint64)]
+        L.ts_serve_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(TsResult)]
+        L.ts_serve_drain.argtypes = [_vp]
+        L.ts_serve_destroy.argtypes = [_vp]
+        L.ts_serve_clock.argtypes = [_vp]
+        L.ts_serve_clock.restype = ctypes.c_double
+        for name in ("ts_serve_create", "ts_serve_submit", "ts_serve_poll", "ts_serve_drain", "ts_serve_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        L._serve_ready = True
+    return L
+
+
+class Server:
+    """ts_serve_*: requests are admitted by memory and run concurrently.
+
+    Device tensors passed to submit() are kept referenced here until the
+    request has finished (the library reads and writes them asynchronously).
+    """
+
+    def __init__(self, budget_bytes: int, n_streams: int = 4, max_active: int = 0):
+        L = _serve_lib()
+        h = _vp()
+        _check(L.ts_serve_create(int(budget_bytes), int(n_streams), int(max_active), ctypes.byref(h)),
+               "ts_serve_create")
+        self._h = h
+        self._keep = {}
+
+    def clock(self) -> float:
+        return _serve_lib().ts_serve_clock(self._h)
+
+    def submit(self, kind, shape, L, f_list, sigma, inp, out, prec="fp64", V2=None, tau=0.0, dt=0.0,
+               rtol=1e-10, maxit=500, tag=0) -> int:
+        r = TsRequest()
+        r.kind = int(kind)
+        r.d = len(shape)
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in f_list]
+        for k, nk in enumerate(shape):
+            r.n[k] = int(nk)
+            r.f[k] = fs[k].ctypes.data
+        r.L, r.sigma = float(L), float(sigma)
+        r.dtype = _dtype_code(inp)
+        r.prec = _prec(prec)
+        r.in_ = inp.data_ptr()
+        r.out = out.data_ptr()
+        r.V2 = V2.data_ptr() if V2 is not None else None
+        r.tau, r.dt, r.rtol, r.maxit, r.tag = float(tau), float(dt), float(rtol), int(maxit), int(tag)
+        t = ctypes.c_uint64(0)
+        _check(_serve_lib().ts_serve_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "ts_serve_submit")
+        self._keep[t.value] = (inp, out, V2)
+        return t.value
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int(0)
+        res = TsResult()
+        _check(_serve_lib().ts_serve_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(res)),
+               "ts_serve_poll")
+        if done.value:
+            self._keep.pop(ticket, None)
+            return res
+        return None
+
+    def drain(self):
+        _check(_serve_lib().ts_serve_drain(self._h), "ts_serve_drain")
+
+    def close(self):
+        if self._h is not None:
+            _serve_lib().ts_serve_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ts_serve_create(budget_bytes, n_streams=4, max_active=0) -> Server:
+    return Server(budget_bytes, n_streams, max_active)

@@ -46,29 +46,21 @@ std::vector<Group> make_groups(const ts_plan* p, int ncomp, int64_t budget, int6
   return gs;
 }
 
-int table_buffer(ts_plan* p, size_t bytes, void** out) {
-  std::lock_guard<std::mutex> g(p->mu);
-  if (p->small_tab_bytes < bytes) {
-    if (p->small_tab) {
-      hipDeviceSynchronize();
-      hipFree(p->small_tab);
-      p->small_tab = nullptr;
-      p->small_tab_bytes = 0;
-    }
-    if (hipMalloc(&p->small_tab, bytes) != hipSuccess) {
-      p->small_tab = nullptr;
-      set_error("table allocation failed");
-      return TS_ERR_NOMEM;
-    }
-    p->small_tab_bytes = bytes;
-  }
-  *out = p->small_tab;
-  return TS_OK;
-}
-
 }  // namespace
 
-int run_small_apply(ts_plan* p, const SmallApply& s, hipStream_t st) {
+size_t small_table_bytes(const ts_plan* p, bool cplx, bool fp64, bool exp) {
+  (void)fp64;
+  // size for either compute precision (their groupings differ)
+  size_t worst = 0;
+  for (int64_t eb : {4, 8}) {
+    std::vector<Group> gs = make_groups(p, cplx ? 2 : 1, kSmallTileBytes / eb, 64 / eb);
+    const int64_t G = gs[0].G;
+    worst = std::max(worst, (size_t)(G + p->N / G));
+  }
+  return worst * (exp ? sizeof(double2) : sizeof(double)) + 256;
+}
+
+int run_small_apply(ts_plan* p, const SmallApply& s, hipStream_t st, ExecCtx& c) {
   const int d = p->d;
   const int ncomp = s.cplx ? 2 : 1;
   const size_t eb = s.fp64 ? 8 : 4;
@@ -82,7 +74,7 @@ int run_small_apply(ts_plan* p, const SmallApply& s, hipStream_t st) {
   const int64_t nlo = g0.G, nhi = p->N / g0.G;
   void* tab = nullptr;
   const size_t tb = (size_t)(nlo + nhi) * (s.epi == Epi::Exp ? sizeof(double2) : sizeof(double));
-  int rc = table_buffer(p, tb, &tab);
+  int rc = ctx_get(c, kSlotTab, tb, &tab);
   if (rc) return rc;
   RangeTableArgs ra;
   ra.d = d;

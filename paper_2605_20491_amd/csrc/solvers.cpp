@@ -4,10 +4,10 @@
 // inverse iteration (Sec. 4.1, Sec. 5.3.1).
 //
 // All vectors, inner products and the scalars alpha, beta of PCG stay on the
-// device in FP64.  The host enqueues iterations in chunks and polls a pinned
-// copy of the scalar block one chunk behind; once the device sets its `done`
-// flag every later kernel of the chunk returns at once, so the iterate is the
-// one that met the tolerance.
+// device in FP64.  PCG and refinement are written as tasks (ts_tasks.h): the
+// host enqueues a few iterations, then reads a pinned copy of the scalar
+// block; once the device sets its `done` flag every later kernel returns at
+// once, so the iterate is the one that met the tolerance.
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -15,6 +15,7 @@
 #include "../../include/ts.h"
 #include "ts_apply.h"
 #include "ts_internal.h"
+#include "ts_tasks.h"
 #include "ts_vec.h"
 
 namespace ts {
@@ -40,52 +41,6 @@ StencilArgs stencil_args(const ts_plan* p, const double* V2, double s, const dou
 
 namespace {
 
-// Layout of the plan's solver buffer: a fixed header (two partial arrays and
-// the scalar block) followed by nvec FP64 vectors of N; callers asking for
-// different nvec see the same header.
-struct SolverBufs {
-  double* vec[5] = {};
-  double* partial = nullptr;
-  double* partial2 = nullptr;
-  SolverScalars* sc = nullptr;
-  SolverScalars* host = nullptr;  // pinned
-};
-
-int solver_buffers(ts_plan* p, int nvec, SolverBufs& b) {
-  std::lock_guard<std::mutex> g(p->mu);
-  const size_t vbytes = round_up((int64_t)(sizeof(double) * p->N), 256);
-  const size_t header = round_up((int64_t)(2 * sizeof(double) * kRedBlocks + sizeof(SolverScalars)), 256);
-  const size_t need = header + vbytes * nvec;
-  if (p->solver_bytes < need) {
-    if (p->solver) {
-      hipDeviceSynchronize();
-      hipFree(p->solver);
-      p->solver = nullptr;
-      p->solver_bytes = 0;
-    }
-    if (hipMalloc(&p->solver, need) != hipSuccess) {
-      p->solver = nullptr;
-      set_error("solver buffer allocation of " + std::to_string(need) + " bytes failed");
-      return TS_ERR_NOMEM;
-    }
-    p->solver_bytes = need;
-  }
-  if (!p->solver_host) {
-    if (hipHostMalloc(&p->solver_host, sizeof(SolverScalars), hipHostMallocDefault) != hipSuccess) {
-      p->solver_host = nullptr;
-      set_error("pinned host allocation failed");
-      return TS_ERR_NOMEM;
-    }
-  }
-  char* base = (char*)p->solver;
-  b.partial = (double*)base;
-  b.partial2 = b.partial + kRedBlocks;
-  b.sc = (SolverScalars*)(b.partial2 + kRedBlocks);
-  for (int i = 0; i < nvec; ++i) b.vec[i] = (double*)(base + header + vbytes * i);
-  b.host = (SolverScalars*)p->solver_host;
-  return TS_OK;
-}
-
 #define TS_TRY(expr)                                                                  \
   do {                                                                                \
     hipError_t _e = (expr);                                                           \
@@ -101,20 +56,37 @@ int solver_buffers(ts_plan* p, int nvec, SolverBufs& b) {
     if (_rc) return _rc;     \
   } while (0)
 
-// Reset the scalar block from the pinned host mirror.
-hipError_t reset_scalars(const SolverBufs& b, double tol2, hipStream_t st) {
-  hipError_t e = hipStreamSynchronize(st);  // the host mirror may still be the target of a copy
-  if (e != hipSuccess) return e;
-  std::memset(b.host, 0, sizeof(SolverScalars));
-  b.host->tol2 = tol2;
-  return hipMemcpyAsync(b.sc, b.host, sizeof(SolverScalars), hipMemcpyHostToDevice, st);
+// Layout of a context's solver slot: a fixed header (two partial arrays and
+// the scalar block) followed by nvec FP64 vectors of N.
+struct SolverBufs {
+  double* vec[6] = {};
+  double* partial = nullptr;
+  double* partial2 = nullptr;
+  SolverScalars* sc = nullptr;
+  SolverScalars* host = nullptr;  // pinned mirror
+};
+
+size_t solver_header() {
+  return round_up((int64_t)(2 * sizeof(double) * kRedBlocks + sizeof(SolverScalars)), 256);
+}
+size_t solver_vbytes(const ts_plan* p) { return round_up((int64_t)(sizeof(double) * p->N), 256); }
+
+int solver_buffers(ExecCtx& c, const ts_plan* p, int nvec, SolverBufs& b) {
+  void* base = nullptr;
+  TS_RC(ctx_get(c, kSlotSolver, solver_header() + solver_vbytes(p) * nvec, &base));
+  void* host = nullptr;
+  TS_RC(ctx_host(c, &host));
+  char* cb = (char*)base;
+  b.partial = (double*)cb;
+  b.partial2 = b.partial + kRedBlocks;
+  b.sc = (SolverScalars*)(b.partial2 + kRedBlocks);
+  for (int i = 0; i < nvec; ++i) b.vec[i] = (double*)(cb + solver_header() + solver_vbytes(p) * i);
+  b.host = (SolverScalars*)host;
+  return TS_OK;
 }
 
-hipError_t read_scalars(const SolverBufs& b, SolverScalars* out, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(b.host, b.sc, sizeof(SolverScalars), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess) std::memcpy(out, b.host, sizeof(SolverScalars));
-  return e;
+hipError_t snapshot(const SolverBufs& b, hipStream_t st) {
+  return hipMemcpyAsync(b.host, b.sc, sizeof(SolverScalars), hipMemcpyDeviceToHost, st);
 }
 
 int status_code(const SolverScalars& s) {
@@ -126,90 +98,275 @@ int status_code(const SolverScalars& s) {
   }
 }
 
+// ------------------------------------------------------------------ PCG --
+class PcgTask : public Task {
+ public:
+  PcgTask(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x, double rtol,
+          int maxit, int prec, ExecCtx& c)
+      : p_(p), V2_(V2), s_op_(s_op), s_pc_(s_pc), f_(f), x_(x), rtol_(rtol), maxit_(maxit), prec_(prec), c_(c) {}
+
+  int start(hipStream_t st) override {
+    TS_RC(solver_buffers(c_, p_, 4, b_));
+    r_ = b_.vec[0];
+    z_ = b_.vec[1];
+    pp_ = b_.vec[2];
+    q_ = b_.vec[3];
+    N_ = p_->N;
+    flexible_ = prec_ != TS_PREC_FP64;
+    done_ = &b_.sc->done;
+    chunk_ = N_ >= (int64_t(1) << 24) ? 2 : (N_ >= (int64_t(1) << 20) ? 4 : 8);
+    TS_TRY(launch_init_scalars(b_.sc, rtol_ * rtol_, st));
+    // r = f - A x ; ||r||^2 and ||f||^2
+    sa_ = stencil_args(p_, V2_, s_op_, x_, r_);
+    sa_.mode = StOut::FminusAx;
+    sa_.rhs = f_;
+    sa_.dot = StDot::OutdotOut;
+    sa_.partial = b_.partial;
+    TS_TRY(launch_stencil(sa_, st));
+    TS_TRY(launch_dot(f_, f_, N_, b_.partial2, nullptr, nullptr, nullptr, st));
+    TS_TRY(launch_scalar(ScalarStep::InitRR, b_.sc, b_.partial, b_.partial2, flexible_, maxit_, st));
+    // z = M^{-1} r ; <r, z> ; p = z
+    TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_));
+    TS_TRY(launch_dot(r_, z_, N_, b_.partial, nullptr, nullptr, done_, st));
+    TS_TRY(launch_scalar(ScalarStep::InitRZ, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
+    TS_TRY(hipMemcpyAsync(pp_, z_, sizeof(double) * N_, hipMemcpyDeviceToDevice, st));
+    sq_ = stencil_args(p_, V2_, s_op_, pp_, q_);
+    sq_.dot = StDot::UdotOut;
+    sq_.partial = b_.partial;
+    sq_.skip = done_;
+    TS_RC(enqueue_chunk(st));
+    TS_TRY(snapshot(b_, st));
+    return TS_OK;
+  }
+
+  int advance(hipStream_t st, bool* done) override {
+    SolverScalars s;
+    std::memcpy(&s, b_.host, sizeof(s));
+    if (!final_) {
+      if (!s.done && enq_ < maxit_) {
+        TS_RC(enqueue_chunk(st));
+        TS_TRY(snapshot(b_, st));
+        *done = false;
+        return TS_OK;
+      }
+      // recompute the true residual ||f - A x|| / ||f||
+      final_ = true;
+      TS_TRY(launch_stencil(sa_, st));
+      TS_TRY(launch_scalar(ScalarStep::SetRR, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
+      TS_TRY(snapshot(b_, st));
+      *done = false;
+      return TS_OK;
+    }
+    iters = s.iters;
+    relres = s.ff > 0 ? std::sqrt(s.rr / s.ff) : 0.0;
+    if (!s.done) {
+      set_error("iteration limit reached");
+      status = TS_ERR_NOCONV;
+    } else {
+      status = status_code(s);
+    }
+    *done = true;
+    return TS_OK;
+  }
+
+ private:
+  int enqueue_chunk(hipStream_t st) {
+    for (int ci = 0; ci < chunk_ && enq_ < maxit_; ++ci, ++enq_) {
+      TS_TRY(launch_stencil(sq_, st));
+      TS_TRY(launch_scalar(ScalarStep::Alpha, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
+      TS_TRY(launch_cg_update(x_, r_, pp_, q_, N_, b_.sc, b_.partial, done_, st));
+      TS_TRY(launch_scalar(ScalarStep::RR, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
+      TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_));
+      TS_TRY(launch_dot(z_, r_, N_, b_.partial, flexible_ ? q_ : nullptr, flexible_ ? b_.partial2 : nullptr,
+                        done_, st));
+      TS_TRY(launch_scalar(ScalarStep::Beta, b_.sc, b_.partial, flexible_ ? b_.partial2 : nullptr, flexible_,
+                           maxit_, st));
+      TS_TRY(launch_xpby(z_, pp_, N_, b_.sc, done_, st));
+    }
+    return TS_OK;
+  }
+
+  ts_plan* p_;
+  const double* V2_;
+  double s_op_, s_pc_;
+  const double* f_;
+  double* x_;
+  double rtol_;
+  int maxit_, prec_;
+  ExecCtx& c_;
+  SolverBufs b_;
+  double *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr, *q_ = nullptr;
+  int64_t N_ = 0;
+  int flexible_ = 0;
+  const int* done_ = nullptr;
+  int chunk_ = 4, enq_ = 0;
+  bool final_ = false;
+  StencilArgs sa_, sq_;
+};
+
+// ------------------------------------------------------- refinement --
+// u <- u + M^{-1}(f - (H1 + sigma) u), M^{-1} the apply in `inner` precision,
+// residual in FP64 with the stencil; if a sweep contracts the residual by less
+// than 0.9 twice, the rest is flexible CG warm-started from u.
+class RefineTask : public Task {
+ public:
+  RefineTask(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, ExecCtx& c)
+      : p_(p), f_(f), u_(u), inner_(inner), rtol_(rtol), maxit_(maxit), c_(c) {}
+
+  int start(hipStream_t st) override {
+    TS_RC(solver_buffers(c_, p_, 2, b_));
+    r_ = b_.vec[0];
+    dlt_ = b_.vec[1];
+    N_ = p_->N;
+    TS_TRY(launch_init_scalars(b_.sc, rtol_ * rtol_, st));
+    TS_TRY(launch_dot(f_, f_, N_, b_.partial, nullptr, nullptr, nullptr, st));
+    TS_TRY(launch_scalar(ScalarStep::SetAux0, b_.sc, b_.partial, nullptr, 0, maxit_, st));
+    // first sweep from u = 0: u = M^{-1} f, then its residual
+    TS_RC(apply_inverse_impl(p_, p_->sigma, f_, u_, TS_F64, inner_, st, c_, nullptr));
+    sa_ = stencil_args(p_, nullptr, p_->sigma, u_, r_);
+    sa_.mode = StOut::FminusAx;
+    sa_.rhs = f_;
+    sa_.dot = StDot::OutdotOut;
+    sa_.partial = b_.partial;
+    TS_TRY(launch_stencil(sa_, st));
+    TS_TRY(launch_scalar(ScalarStep::SetRR, b_.sc, b_.partial, nullptr, 0, maxit_, st));
+    TS_TRY(snapshot(b_, st));
+    sweeps_ = 1;
+    return TS_OK;
+  }
+
+  int advance(hipStream_t st, bool* done) override {
+    if (cg_) {
+      TS_RC(cg_->advance(st, done));
+      if (*done) {
+        iters = sweeps_ + cg_->iters;
+        relres = cg_->relres;
+        status = cg_->status;
+      }
+      return TS_OK;
+    }
+    SolverScalars s;
+    std::memcpy(&s, b_.host, sizeof(s));
+    const double ff = s.aux[0], rr = s.rr;
+    *done = true;
+    iters = sweeps_;
+    if (ff == 0.0) {  // f = 0: u = M^{-1} 0 = 0 already
+      relres = 0.0;
+      return TS_OK;
+    }
+    relres = std::sqrt(rr / ff);
+    if (!std::isfinite(rr)) { set_error("non-finite residual"); status = TS_ERR_NONFINITE; return TS_OK; }
+    if (rr <= rtol_ * rtol_ * ff) return TS_OK;
+    if (sweeps_ > 1 && rr > 0.81 * prev_) ++slow_;  // contraction factor above 0.9
+    prev_ = rr;
+    if (sweeps_ >= maxit_) { set_error("refinement did not reach rtol"); status = TS_ERR_NOCONV; return TS_OK; }
+    *done = false;
+    if (slow_ >= 2) {
+      cg_ = make_pcg_task(p_, nullptr, p_->sigma, p_->sigma, f_, u_, rtol_, maxit_ - sweeps_, inner_, c_);
+      return cg_->start(st);
+    }
+    TS_RC(apply_inverse_impl(p_, p_->sigma, r_, dlt_, TS_F64, inner_, st, c_, nullptr));
+    TS_TRY(launch_axpy1(u_, dlt_, N_, nullptr, st));
+    TS_TRY(launch_stencil(sa_, st));
+    TS_TRY(launch_scalar(ScalarStep::SetRR, b_.sc, b_.partial, nullptr, 0, maxit_, st));
+    TS_TRY(snapshot(b_, st));
+    ++sweeps_;
+    return TS_OK;
+  }
+
+ private:
+  ts_plan* p_;
+  const double* f_;
+  double* u_;
+  int inner_;
+  double rtol_;
+  int maxit_;
+  ExecCtx& c_;
+  SolverBufs b_;
+  double *r_ = nullptr, *dlt_ = nullptr;
+  int64_t N_ = 0;
+  StencilArgs sa_;
+  int sweeps_ = 0, slow_ = 0;
+  double prev_ = 0.0;
+  std::unique_ptr<Task> cg_;
+};
+
+// ------------------------------------------------- single applies --
+class ApplyTask : public Task {
+ public:
+  ApplyTask(bool inverse, ts_plan* p, double param, const void* in, void* out, int dtype, int prec, ExecCtx& c)
+      : inverse_(inverse), p_(p), param_(param), in_(in), out_(out), dtype_(dtype), prec_(prec), c_(c) {}
+  int start(hipStream_t st) override {
+    return inverse_ ? apply_inverse_impl(p_, param_, in_, out_, dtype_, prec_, st, c_, nullptr)
+                    : apply_exp_impl(p_, param_, in_, out_, dtype_, prec_, st, c_);
+  }
+  int advance(hipStream_t, bool* done) override {
+    *done = true;
+    return TS_OK;
+  }
+
+ private:
+  bool inverse_;
+  ts_plan* p_;
+  double param_;
+  const void* in_;
+  void* out_;
+  int dtype_, prec_;
+  ExecCtx& c_;
+};
+
 }  // namespace
 
-// PCG for (H1 + V2 + s_op) x = f with preconditioner (H1 + s_pc)^{-1} in `prec`.
-// x: in initial guess, out solution.  b: solver buffers with 4 vectors.
-int pcg_run(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x,
-            double rtol, int maxit, int prec, int* iters, double* relres, hipStream_t st) {
-  SolverBufs b;
-  TS_RC(solver_buffers(p, 4, b));
-  double *r = b.vec[0], *z = b.vec[1], *pp = b.vec[2], *q = b.vec[3];
-  const int64_t N = p->N;
-  const int flexible = prec != TS_PREC_FP64;
-  const int* done = &b.sc->done;
-  TS_TRY(reset_scalars(b, rtol * rtol, st));
-  // r = f - A x ; ||r||^2, ||f||^2
-  StencilArgs sa = stencil_args(p, V2, s_op, x, r);
-  sa.mode = StOut::FminusAx;
-  sa.rhs = f;
-  sa.dot = StDot::OutdotOut;
-  sa.partial = b.partial;
-  TS_TRY(launch_stencil(sa, st));
-  TS_TRY(launch_dot(f, f, N, b.partial2, nullptr, nullptr, nullptr, st));
-  TS_TRY(launch_scalar(ScalarStep::InitRR, b.sc, b.partial, b.partial2, flexible, maxit, st));
-  // z = M^{-1} r ; rz ; p = z
-  TS_RC(apply_inverse_impl(p, s_pc, r, z, TS_F64, prec, st, nullptr, done));
-  TS_TRY(launch_dot(r, z, N, b.partial, nullptr, nullptr, done, st));
-  TS_TRY(launch_scalar(ScalarStep::InitRZ, b.sc, b.partial, nullptr, flexible, maxit, st));
-  TS_TRY(hipMemcpyAsync(pp, z, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-
-  StencilArgs sq = stencil_args(p, V2, s_op, pp, q);
-  sq.dot = StDot::UdotOut;
-  sq.partial = b.partial;
-  sq.skip = done;
-  const int chunk = N >= (int64_t(1) << 24) ? 2 : 8;
+int run_blocking(Task& t, hipStream_t st) {
   hipEvent_t ev = nullptr;
   TS_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-  SolverScalars snap{};
-  int enq = 0;
-  bool pending = false, finished = false;
-  while (!finished) {
-    if (enq < maxit) {
-      for (int c = 0; c < chunk && enq < maxit; ++c, ++enq) {
-        TS_TRY(launch_stencil(sq, st));
-        TS_TRY(launch_scalar(ScalarStep::Alpha, b.sc, b.partial, nullptr, flexible, maxit, st));
-        TS_TRY(launch_cg_update(x, r, pp, q, N, b.sc, b.partial, done, st));
-        TS_TRY(launch_scalar(ScalarStep::RR, b.sc, b.partial, nullptr, flexible, maxit, st));
-        TS_RC(apply_inverse_impl(p, s_pc, r, z, TS_F64, prec, st, nullptr, done));
-        TS_TRY(launch_dot(z, r, N, b.partial, flexible ? q : nullptr, flexible ? b.partial2 : nullptr, done, st));
-        TS_TRY(launch_scalar(ScalarStep::Beta, b.sc, b.partial, flexible ? b.partial2 : nullptr, flexible,
-                             maxit, st));
-        TS_TRY(launch_xpby(z, pp, N, b.sc, done, st));
-      }
-    }
-    // poll the previous chunk's snapshot while this chunk runs
-    if (pending) {
-      TS_TRY(hipEventSynchronize(ev));
-      std::memcpy(&snap, b.host, sizeof(snap));
-      if (snap.done) finished = true;
-    }
-    if (!finished) {
-      if (enq >= maxit && pending) {
-        // every iteration is queued and the device has decided: read the final state below
-        finished = true;
-      } else {
-        TS_TRY(hipMemcpyAsync(b.host, b.sc, sizeof(SolverScalars), hipMemcpyDeviceToHost, st));
-        TS_TRY(hipEventRecord(ev, st));
-        pending = true;
-      }
-    }
+  struct Guard { hipEvent_t e; ~Guard() { hipEventDestroy(e); } } guard{ev};
+  TS_RC(t.start(st));
+  for (;;) {
+    TS_TRY(hipEventRecord(ev, st));
+    TS_TRY(hipEventSynchronize(ev));
+    bool done = false;
+    TS_RC(t.advance(st, &done));
+    if (done) break;
   }
-  hipEventDestroy(ev);
-  SolverScalars fin{};
-  TS_TRY(read_scalars(b, &fin, st));
-  // true residual ||f - A x|| / ||f||
-  TS_TRY(launch_stencil(sa, st));
-  TS_TRY(launch_scalar(ScalarStep::SetRR, b.sc, b.partial, nullptr, flexible, maxit, st));
-  SolverScalars tr{};
-  TS_TRY(read_scalars(b, &tr, st));
-  if (iters) *iters = fin.iters;
-  if (relres) *relres = fin.ff > 0 ? std::sqrt(tr.rr / fin.ff) : 0.0;
-  if (!fin.done) {
-    set_error("iteration limit reached");
-    return TS_ERR_NOCONV;
-  }
-  return status_code(fin);
+  return t.status;
+}
+
+std::unique_ptr<Task> make_pcg_task(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f,
+                                    double* x, double rtol, int maxit, int prec, ExecCtx& c) {
+  return std::unique_ptr<Task>(new PcgTask(p, V2, s_op, s_pc, f, x, rtol, maxit, prec, c));
+}
+std::unique_ptr<Task> make_refine_task(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit,
+                                       ExecCtx& c) {
+  return std::unique_ptr<Task>(new RefineTask(p, f, u, inner, rtol, maxit, c));
+}
+std::unique_ptr<Task> make_inverse_task(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
+                                        ExecCtx& c) {
+  return std::unique_ptr<Task>(new ApplyTask(true, p, shift, b, u, dtype, prec, c));
+}
+std::unique_ptr<Task> make_exp_task(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
+                                    ExecCtx& c) {
+  return std::unique_ptr<Task>(new ApplyTask(false, p, tau, in, out, dtype, prec, c));
+}
+
+size_t need_solver(const ts_plan* p, int nvec) { return solver_header() + solver_vbytes(p) * nvec; }
+
+int pcg_run(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x, double rtol,
+            int maxit, int prec, int* iters, double* relres, hipStream_t st, ExecCtx& c) {
+  PcgTask t(p, V2, s_op, s_pc, f, x, rtol, maxit, prec, c);
+  int rc = run_blocking(t, st);
+  if (iters) *iters = t.iters;
+  if (relres) *relres = t.relres;
+  return rc;
+}
+
+int refine_run(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, int* iters,
+               double* relres, hipStream_t st, ExecCtx& c) {
+  RefineTask t(p, f, u, inner, rtol, maxit, c);
+  int rc = run_blocking(t, st);
+  if (iters) *iters = t.iters;
+  if (relres) *relres = t.relres;
+  return rc;
 }
 
 }  // namespace ts
@@ -233,7 +390,7 @@ int ts_pcg_solve(ts_plan* plan, const double* V2, const double* f, double* u, do
   if (!(rtol > 0.0) || maxit < 1) { set_error("rtol must be > 0 and maxit >= 1"); return TS_ERR_INVALID; }
   if (precond < TS_PREC_FP64 || precond > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
   return pcg_run(plan, V2, plan->sigma, plan->sigma, f, u, rtol, maxit, precond, iters, relres,
-                 (hipStream_t)hip_stream);
+                 (hipStream_t)hip_stream, plan->ctx);
 }
 
 int ts_solve_refined(ts_plan* plan, const double* f, double* u, int inner, double rtol, int maxit,
@@ -241,62 +398,7 @@ int ts_solve_refined(ts_plan* plan, const double* f, double* u, int inner, doubl
   if (!plan || !f || !u) { set_error("null argument"); return TS_ERR_INVALID; }
   if (!(rtol > 0.0) || maxit < 1) { set_error("rtol must be > 0 and maxit >= 1"); return TS_ERR_INVALID; }
   if (inner < TS_PREC_FP64 || inner > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
-  hipStream_t st = (hipStream_t)hip_stream;
-  SolverBufs b;
-  TS_RC(solver_buffers(plan, 2, b));
-  double *r = b.vec[0], *dlt = b.vec[1];
-  const int64_t N = plan->N;
-  TS_TRY(reset_scalars(b, rtol * rtol, st));
-  // ||f||^2 into ff via InitRR with r = f
-  TS_TRY(hipMemcpyAsync(r, f, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-  TS_TRY(launch_dot(f, f, N, b.partial, nullptr, nullptr, nullptr, st));
-  TS_TRY(launch_scalar(ScalarStep::InitRR, b.sc, b.partial, b.partial, 0, maxit, st));
-  SolverScalars s0{};
-  TS_TRY(read_scalars(b, &s0, st));
-  const double ff = s0.ff;
-  if (ff == 0.0) {
-    TS_TRY(hipMemsetAsync(u, 0, sizeof(double) * N, st));
-    if (iters) *iters = 0;
-    if (relres) *relres = 0.0;
-    return TS_OK;
-  }
-  StencilArgs sa = stencil_args(plan, nullptr, plan->sigma, u, r);
-  sa.mode = StOut::FminusAx;
-  sa.rhs = f;
-  sa.dot = StDot::OutdotOut;
-  sa.partial = b.partial;
-  double prev = ff, rr = ff;
-  int slow = 0, it = 0;
-  // first sweep from u = 0: u = M^{-1} f
-  TS_RC(apply_inverse_impl(plan, plan->sigma, f, u, TS_F64, inner, st, nullptr, nullptr));
-  for (it = 1;; ++it) {
-    TS_TRY(launch_stencil(sa, st));
-    TS_TRY(launch_scalar(ScalarStep::SetRR, b.sc, b.partial, nullptr, 0, maxit, st));
-    SolverScalars s{};
-    TS_TRY(read_scalars(b, &s, st));
-    rr = s.rr;
-    if (!std::isfinite(rr)) { set_error("non-finite residual"); return TS_ERR_NONFINITE; }
-    if (rr <= rtol * rtol * ff) break;
-    if (rr > 0.81 * prev) ++slow;  // contraction factor above 0.9
-    prev = rr;
-    if (it >= maxit) break;
-    if (slow >= 2) {
-      // Richardson stalls: finish with flexible CG on the same operator,
-      // warm-started from the current u
-      int cg_it = 0;
-      double cg_res = 0.0;
-      int rc = pcg_run(plan, nullptr, plan->sigma, plan->sigma, f, u, rtol, maxit - it, inner, &cg_it, &cg_res, st);
-      if (iters) *iters = it + cg_it;
-      if (relres) *relres = cg_res;
-      return rc;
-    }
-    TS_RC(apply_inverse_impl(plan, plan->sigma, r, dlt, TS_F64, inner, st, nullptr, nullptr));
-    TS_TRY(launch_axpy1(u, dlt, N, nullptr, st));
-  }
-  if (iters) *iters = it;
-  if (relres) *relres = std::sqrt(rr / ff);
-  if (rr > rtol * rtol * ff) { set_error("refinement did not reach rtol"); return TS_ERR_NOCONV; }
-  return TS_OK;
+  return refine_run(plan, f, u, inner, rtol, maxit, iters, relres, (hipStream_t)hip_stream, plan->ctx);
 }
 
 int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* u, int steps,
@@ -304,22 +406,22 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
                          void* hip_stream) {
   if (!plan || !u || steps < 0) { set_error("bad argument"); return TS_ERR_INVALID; }
   if (!std::isfinite(shift) || !(pcg_rtol > 0.0) || maxit < 1) { set_error("bad argument"); return TS_ERR_INVALID; }
+  if (precond < TS_PREC_FP64 || precond > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
   if (!(plan->lam_min - shift > 0.0)) {
     set_error("shift must lie below lambda_min(H1) for the preconditioner (H1 - shift)^{-1}");
     return TS_ERR_NOT_SPD;
   }
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t N = plan->N;
-  // w (the PCG iterate, warm start) lives in its own buffer; PCG uses 4 more
-  double* w = nullptr;
-  if (hipMalloc(&w, sizeof(double) * N) != hipSuccess) { set_error("allocation failed"); return TS_ERR_NOMEM; }
-  struct Free { double* p; ~Free() { hipFree(p); } } guard{w};
+  ExecCtx& c = plan->ctx;
+  // PCG uses vectors 0..3; H u and the warm-started iterate w take 4 and 5
   SolverBufs b;
-  TS_RC(solver_buffers(plan, 5, b));
+  TS_RC(solver_buffers(c, plan, 6, b));
   double* Hu = b.vec[4];
+  double* w = b.vec[5];
   auto rayleigh = [&](double* lam) -> int {
     // ||u||^2 -> aux0, u <- u / ||u||, lambda = u^T H u (s = 0)
-    TS_TRY(reset_scalars(b, 0.0, st));
+    TS_TRY(launch_init_scalars(b.sc, 0.0, st));
     TS_TRY(launch_dot(u, u, N, b.partial, nullptr, nullptr, nullptr, st));
     TS_TRY(launch_scalar(ScalarStep::SetAux0, b.sc, b.partial, nullptr, 0, 1, st));
     TS_TRY(launch_scale_invnorm(u, u, N, b.sc, st));
@@ -328,9 +430,9 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
     s.partial = b.partial;
     TS_TRY(launch_stencil(s, st));
     TS_TRY(launch_scalar(ScalarStep::SetAux0, b.sc, b.partial, nullptr, 0, 1, st));
-    SolverScalars sv{};
-    TS_TRY(read_scalars(b, &sv, st));
-    *lam = sv.aux[0];
+    TS_TRY(snapshot(b, st));
+    TS_TRY(hipStreamSynchronize(st));
+    *lam = b.host->aux[0];
     return TS_OK;
   };
   double lam = 0.0;
@@ -340,7 +442,7 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
   for (int k = 0; k < steps; ++k) {
     int it = 0;
     double rr = 0.0;
-    int rc = pcg_run(plan, V2, -shift, -shift, u, w, pcg_rtol, maxit, precond, &it, &rr, st);
+    int rc = pcg_run(plan, V2, -shift, -shift, u, w, pcg_rtol, maxit, precond, &it, &rr, st, c);
     if (pcg_iters) pcg_iters[k] = it;
     if (rc) return rc;
     TS_TRY(hipMemcpyAsync(u, w, sizeof(double) * N, hipMemcpyDeviceToDevice, st));

@@ -16,16 +16,17 @@
 #include "ts_apply.h"
 #include "ts_internal.h"
 #include "ts_small.h"
+#include "ts_tasks.h"
 
 namespace ts {
 
-// Factor list of nsteps steps; 'A' = propagator of H1, 'B' = potential factor.
+// Factor list of nsteps steps, in the order the factors act on psi;
+// 'A' = propagator of H1, 'B' = potential factor.
 std::vector<std::pair<char, double>> split_factors(int scheme, double dt, int nsteps) {
   std::vector<std::pair<char, double>> ops;
   const double c = std::cbrt(2.0);
   const double g1 = 1.0 / (2.0 - c), g2 = -c / (2.0 - c);
   auto strang = [&](double h, bool bab) {
-    // listed in the order the factors act on psi
     if (bab) {
       ops.push_back({'B', h / 2});
       ops.push_back({'A', h});
@@ -52,47 +53,105 @@ std::vector<std::pair<char, double>> split_factors(int scheme, double dt, int ns
   return merged;
 }
 
-}  // namespace ts
+namespace {
 
-using namespace ts;
-
-extern "C" int ts_split_step(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme,
-                             int dtype, int prec, void* hip_stream) {
+int check_split(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec) {
   if (!plan || !V2 || !psi) { set_error("null argument"); return TS_ERR_INVALID; }
   if (nsteps < 0 || !std::isfinite(dt)) { set_error("bad dt or nsteps"); return TS_ERR_INVALID; }
   if (scheme < TS_STRANG_BAB || scheme > TS_YOSHIDA_ABA) { set_error("unknown scheme"); return TS_ERR_INVALID; }
   if (dtype != TS_C128 && dtype != TS_C64) { set_error("splitting needs TS_C128 or TS_C64 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
   if (prec == TS_PREC_FP64 && dtype != TS_C128) { set_error("FP64 transforms need TS_C128 data"); return TS_ERR_INVALID; }
-  hipStream_t st = (hipStream_t)hip_stream;
-  auto ops = split_factors(scheme, dt, nsteps);
-  int lastA = -1;
-  for (int i = 0; i < (int)ops.size(); ++i)
-    if (ops[i].first == 'A') lastA = i;
-  const bool fp64_data = dtype == TS_C128;
-  if (lastA < 0) {
-    for (auto& o : ops) {
-      hipError_t e = launch_phase(psi, V2, o.second, plan->N, fp64_data, st);
-      if (e != hipSuccess) { set_error("phase launch failed"); return TS_ERR_DEVICE; }
+  return TS_OK;
+}
+
+// Runs the merged factor list a few A factors per unit.
+class SplitTask : public Task {
+ public:
+  SplitTask(ts_plan* p, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec,
+            ExecCtx& c)
+      : p_(p), V2_(V2), psi_(psi), dtype_(dtype), prec_(prec), c_(c) {
+    ops_ = split_factors(scheme, dt, nsteps);
+    for (int i = 0; i < (int)ops_.size(); ++i)
+      if (ops_[i].first == 'A') lastA_ = i;
+    iters = nsteps;
+  }
+  int start(hipStream_t st) override {
+    if (lastA_ < 0) {  // nsteps = 0 or only potential factors
+      for (auto& o : ops_) {
+        hipError_t e = launch_phase(psi_, V2_, o.second, p_->N, dtype_ == TS_C128, st);
+        if (e != hipSuccess) { set_error("phase launch failed"); return TS_ERR_DEVICE; }
+      }
+      pos_ = (int)ops_.size();
+      return TS_OK;
+    }
+    return unit(st);
+  }
+  int advance(hipStream_t st, bool* done) override {
+    *done = pos_ > lastA_;
+    if (*done) return TS_OK;
+    return unit(st);
+  }
+
+ private:
+  int unit(hipStream_t st) {
+    int applied = 0;
+    Phases ph;
+    ph.V2 = V2_;
+    while (pos_ <= lastA_ && applied < kPerUnit) {
+      const auto& o = ops_[pos_];
+      if (o.first == 'B') {
+        ph.pre = true;
+        ph.th_pre = o.second;
+        ++pos_;
+        continue;
+      }
+      if (pos_ == lastA_ && pos_ + 1 < (int)ops_.size()) {  // trailing potential factor
+        ph.post = true;
+        ph.th_post = ops_[pos_ + 1].second;
+      }
+      int rc = apply_exp_phased(p_, o.second, psi_, dtype_, prec_, ph, st, c_);
+      if (rc) return rc;
+      ph.pre = ph.post = false;
+      ++pos_;
+      ++applied;
     }
     return TS_OK;
   }
-  Phases ph;
-  ph.V2 = V2;
-  for (int i = 0; i < (int)ops.size(); ++i) {
-    if (ops[i].first == 'B') {
-      if (i > lastA) break;  // trailing factor: fused into the last A below
-      ph.pre = true;
-      ph.th_pre = ops[i].second;
-      continue;
-    }
-    if (i == lastA && i + 1 < (int)ops.size()) {
-      ph.post = true;
-      ph.th_post = ops[i + 1].second;
-    }
-    int rc = apply_exp_phased(plan, ops[i].second, psi, dtype, prec, ph, st, nullptr);
-    if (rc) return rc;
-    ph.pre = ph.post = false;
-  }
-  return TS_OK;
+
+  static constexpr int kPerUnit = 4;
+  ts_plan* p_;
+  const void* V2_;
+  void* psi_;
+  int dtype_, prec_;
+  ExecCtx& c_;
+  std::vector<std::pair<char, double>> ops_;
+  int lastA_ = -1, pos_ = 0;
+};
+
+}  // namespace
+
+std::unique_ptr<Task> make_split_task(ts_plan* p, const void* V2, void* psi, double dt, int nsteps, int scheme,
+                                      int dtype, int prec, ExecCtx& c) {
+  return std::unique_ptr<Task>(new SplitTask(p, V2, psi, dt, nsteps, scheme, dtype, prec, c));
+}
+
+int split_run(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec,
+              hipStream_t st, ExecCtx& c) {
+  int rc = check_split(plan, V2, psi, dt, nsteps, scheme, dtype, prec);
+  if (rc) return rc;
+  SplitTask t(plan, V2, psi, dt, nsteps, scheme, dtype, prec, c);
+  return run_blocking(t, st);
+}
+
+int split_check(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec) {
+  return check_split(plan, V2, psi, dt, nsteps, scheme, dtype, prec);
+}
+
+}  // namespace ts
+
+extern "C" int ts_split_step(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme,
+                             int dtype, int prec, void* hip_stream) {
+  if (!plan) { ts::set_error("null plan"); return TS_ERR_INVALID; }
+  return ts::split_run(plan, V2, psi, dt, nsteps, scheme, dtype, prec, (hipStream_t)hip_stream, plan->ctx);
 }

@@ -69,16 +69,20 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
     set_error(std::string("device allocation of factors failed: ") + hipGetErrorString(e));
     return TS_ERR_NOMEM;
   }
-  e = hipMemcpy(F->lam, F->lam_h.data(), sizeof(double) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(F->f, f, sizeof(double) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(F->Q64, Qp.data(), sizeof(double) * padded, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(F->QT64, QTp.data(), sizeof(double) * padded, hipMemcpyHostToDevice);
+  // upload on a private non-blocking stream: setup never waits for other work
+  hipStream_t st = nullptr;
+  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMemcpyAsync(F->lam, F->lam_h.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F->f, f, sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F->Q64, Qp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F->QT64, QTp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
   // reduced-precision copies are cast on the device from the FP64 copy
-  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->Q64, F->Q32, (int64_t)padded, 0);
-  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->QT64, F->QT32, (int64_t)padded, 0);
-  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->Q64, F->Q16, (int64_t)padded, 0);
-  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->QT64, F->QT16, (int64_t)padded, 0);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->Q64, F->Q32, (int64_t)padded, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->QT64, F->QT32, (int64_t)padded, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->Q64, F->Q16, (int64_t)padded, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->QT64, F->QT16, (int64_t)padded, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (st) hipStreamDestroy(st);
   if (e != hipSuccess) {
     set_error(std::string("factor upload failed: ") + hipGetErrorString(e));
     return TS_ERR_DEVICE;
@@ -87,27 +91,62 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
   return TS_OK;
 }
 
-// Scratch of at least `bytes` owned by the plan (grown on demand).  Growing
-// synchronises the device so that no queued kernel still uses the old buffer.
-int plan_workspace(ts_plan* p, size_t bytes, void** out) {
-  std::lock_guard<std::mutex> g(p->mu);
-  if (p->work_bytes < bytes) {
-    if (p->work) {
-      hipDeviceSynchronize();
-      hipFree(p->work);
-      p->work = nullptr;
-      p->work_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&p->work, bytes);
-    if (e != hipSuccess) {
-      p->work = nullptr;
-      set_error("workspace allocation of " + std::to_string(bytes) + " bytes failed");
+ExecCtx::~ExecCtx() {
+  if (!growable) return;
+  for (int i = 0; i < kSlots; ++i) hipFree(buf[i]);
+  if (host) hipHostFree(host);
+}
+
+// Growing a slot synchronises the device so that no queued kernel still uses
+// the old buffer.
+int ctx_get(ExecCtx& c, int slot, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> g(c.mu);
+  if (bytes == 0) bytes = 256;
+  if (c.bytes[slot] < bytes) {
+    if (!c.growable) {
+      set_error("request scratch too small (" + std::to_string(c.bytes[slot]) + " < " + std::to_string(bytes) + " bytes)");
       return TS_ERR_NOMEM;
     }
-    p->work_bytes = bytes;
+    if (c.buf[slot]) {
+      hipDeviceSynchronize();
+      hipFree(c.buf[slot]);
+      c.buf[slot] = nullptr;
+      c.bytes[slot] = 0;
+    }
+    if (hipMalloc(&c.buf[slot], bytes) != hipSuccess) {
+      c.buf[slot] = nullptr;
+      set_error("scratch allocation of " + std::to_string(bytes) + " bytes failed");
+      return TS_ERR_NOMEM;
+    }
+    c.bytes[slot] = bytes;
   }
-  *out = p->work;
+  *out = c.buf[slot];
   return TS_OK;
+}
+
+int ctx_host(ExecCtx& c, void** out) {
+  std::lock_guard<std::mutex> g(c.mu);
+  if (!c.host) {
+    if (!c.growable || hipHostMalloc(&c.host, 256, hipHostMallocDefault) != hipSuccess) {
+      c.host = nullptr;
+      set_error("pinned host allocation failed");
+      return TS_ERR_NOMEM;
+    }
+  }
+  *out = c.host;
+  return TS_OK;
+}
+
+size_t need_inverse(const ts_plan* p, int slot) {
+  if (plan_is_small(p)) return slot == kSlotTab ? small_table_bytes(p, false, true, false) : 0;
+  return slot == kSlotWork ? (size_t)p->N * 8 : 0;
+}
+
+size_t need_exp(const ts_plan* p, int slot) {
+  if (plan_is_small(p)) return slot == kSlotTab ? small_table_bytes(p, true, false, true) : 0;
+  if (slot == kSlotWork) return (size_t)p->N * 16;
+  if (slot == kSlotPhase) return sizeof(double2) * (size_t)(p->Ps + p->Rs + p->n[p->s]);
+  return 0;
 }
 
 static DT dt_of(int dtype) { return (dtype == TS_F64 || dtype == TS_C128) ? DT::F64 : DT::F32; }
@@ -152,9 +191,9 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
       pa.Lp = p->Lp;
       pa.Lr = p->Lr;
       pa.shift = ap.shift;
-      pa.Ep = p->phase;
-      pa.Er = p->phase + p->Ps;
-      pa.es = p->phase + p->Ps + p->Rs;
+      pa.Ep = ap.phase;
+      pa.Er = ap.phase ? ap.phase + p->Ps : nullptr;
+      pa.es = ap.phase ? ap.phase + p->Ps + p->Rs : nullptr;
     }
     hipError_t e = launch_pass(pa, st);
     if (e != hipSuccess) {
@@ -168,7 +207,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
 }
 
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, void* work, const int* skip) {
+                       hipStream_t st, ExecCtx& c, const int* skip) {
   if (!p || !b || !u) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_F64 && dtype != TS_F32) { set_error("inverse apply needs TS_F64 or TS_F32 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
@@ -187,12 +226,11 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
     sa.epi = Epi::Inv;
     sa.shift = shift;
     sa.skip = skip;
-    return run_small_apply(p, sa, st);
+    return run_small_apply(p, sa, st, c);
   }
-  if (!work) {
-    int rc = plan_workspace(p, (size_t)p->N * 8, &work);
-    if (rc) return rc;
-  }
+  void* work = nullptr;
+  int rc = ctx_get(c, kSlotWork, need_inverse(p, kSlotWork), &work);
+  if (rc) return rc;
   ApplyParams ap;
   ap.in = b;
   ap.out = u;
@@ -217,11 +255,13 @@ static int check_exp_args(ts_plan* p, double tau, const void* in, const void* ou
 
 // The MFMA-path propagator: phase tables for the scaling axis, then 2d passes.
 static int exp_mfma(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec, hipStream_t st,
-                    void* work) {
-  if (!work) {
-    int rc = plan_workspace(p, (size_t)p->N * 16, &work);
-    if (rc) return rc;
-  }
+                    ExecCtx& c) {
+  void *work = nullptr, *tabs = nullptr;
+  int rc = ctx_get(c, kSlotWork, need_exp(p, kSlotWork), &work);
+  if (rc) return rc;
+  rc = ctx_get(c, kSlotPhase, need_exp(p, kSlotPhase), &tabs);
+  if (rc) return rc;
+  double2* phase = (double2*)tabs;
   PhaseTableArgs pt;
   pt.d = p->d;
   pt.s = p->s;
@@ -230,9 +270,9 @@ static int exp_mfma(ts_plan* p, double tau, const void* in, void* out, int dtype
     pt.lam[k] = p->ax[k]->lam;
   }
   pt.tau = tau;
-  pt.Ep = p->phase;
-  pt.Er = p->phase + p->Ps;
-  pt.es = p->phase + p->Ps + p->Rs;
+  pt.Ep = phase;
+  pt.Er = phase + p->Ps;
+  pt.es = phase + p->Ps + p->Rs;
   pt.P = p->Ps;
   pt.R = p->Rs;
   hipError_t e = launch_phase_tables(pt, st);
@@ -245,11 +285,12 @@ static int exp_mfma(ts_plan* p, double tau, const void* in, void* out, int dtype
   ap.prec = prec;
   ap.cplx = true;
   ap.epi = Epi::Exp;
+  ap.phase = phase;
   return run_apply(p, ap, st);
 }
 
 int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
-                   hipStream_t st, void* work) {
+                   hipStream_t st, ExecCtx& c) {
   int rc = check_exp_args(p, tau, in, out, dtype, prec);
   if (rc) return rc;
   if (plan_is_small(p)) {
@@ -261,13 +302,13 @@ int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype,
     sa.cplx = true;
     sa.epi = Epi::Exp;
     sa.tau = tau;
-    return run_small_apply(p, sa, st);
+    return run_small_apply(p, sa, st, c);
   }
-  return exp_mfma(p, tau, in, out, dtype, prec, st, work);
+  return exp_mfma(p, tau, in, out, dtype, prec, st, c);
 }
 
 int apply_exp_phased(ts_plan* p, double tau, void* psi, int dtype, int prec, const Phases& ph,
-                     hipStream_t st, void* work) {
+                     hipStream_t st, ExecCtx& c) {
   int rc = check_exp_args(p, tau, psi, psi, dtype, prec);
   if (rc) return rc;
   const bool fp64_data = dtype == TS_C128;
@@ -285,14 +326,14 @@ int apply_exp_phased(ts_plan* p, double tau, void* psi, int dtype, int prec, con
     sa.post = ph.post;
     sa.th_pre = ph.th_pre;
     sa.th_post = ph.th_post;
-    return run_small_apply(p, sa, st);
+    return run_small_apply(p, sa, st, c);
   }
   hipError_t e;
   if (ph.pre) {
     e = launch_phase(psi, ph.V2, ph.th_pre, p->N, fp64_data, st);
     if (e != hipSuccess) { set_error("phase launch failed"); return TS_ERR_DEVICE; }
   }
-  rc = exp_mfma(p, tau, psi, psi, dtype, prec, st, work);
+  rc = exp_mfma(p, tau, psi, psi, dtype, prec, st, c);
   if (rc) return rc;
   if (ph.post) {
     e = launch_phase(psi, ph.V2, ph.th_post, p->N, fp64_data, st);
@@ -304,13 +345,8 @@ int apply_exp_phased(ts_plan* p, double tau, void* psi, int dtype, int prec, con
 }  // namespace ts
 
 ts_plan::~ts_plan() {
-  hipFree(small_tab);
-  hipFree(solver);
-  if (solver_host) hipHostFree(solver_host);
   hipFree(Lp);
   hipFree(Lr);
-  hipFree(work);
-  hipFree(phase);
 }
 
 using namespace ts;
@@ -390,7 +426,6 @@ int ts_setup(int d, const int64_t* n, double L, const double* const* f, double s
   }
   hipError_t e = hipMalloc(&p->Lp, sizeof(double) * p->Ps);
   if (e == hipSuccess) e = hipMalloc(&p->Lr, sizeof(double) * p->Rs);
-  if (e == hipSuccess) e = hipMalloc(&p->phase, sizeof(double2) * (p->Ps + p->Rs + n[p->s]));
   if (e != hipSuccess) { set_error("table allocation failed"); return TS_ERR_NOMEM; }
   e = hipMemcpy(p->Lp, Lp.data(), sizeof(double) * p->Ps, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->Lr, Lr.data(), sizeof(double) * p->Rs, hipMemcpyHostToDevice);
@@ -408,20 +443,20 @@ int ts_destroy(ts_plan* plan) {
 
 int ts_apply_inverse(ts_plan* plan, const void* b, void* u, int dtype, int prec, void* hip_stream) {
   if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
-  return apply_inverse_impl(plan, plan->sigma, b, u, dtype, prec, (hipStream_t)hip_stream, nullptr, nullptr);
+  return apply_inverse_impl(plan, plan->sigma, b, u, dtype, prec, (hipStream_t)hip_stream, plan->ctx, nullptr);
 }
 
 int ts_apply_inverse_shift(ts_plan* plan, double s, const void* b, void* u, int dtype, int prec,
                            void* hip_stream) {
   if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
   if (!std::isfinite(s)) { set_error("shift is not finite"); return TS_ERR_INVALID; }
-  return apply_inverse_impl(plan, s, b, u, dtype, prec, (hipStream_t)hip_stream, nullptr, nullptr);
+  return apply_inverse_impl(plan, s, b, u, dtype, prec, (hipStream_t)hip_stream, plan->ctx, nullptr);
 }
 
 int ts_apply_exp(ts_plan* plan, double tau, const void* psi_in, void* psi_out, int dtype, int prec,
                  void* hip_stream) {
   if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
-  return apply_exp_impl(plan, tau, psi_in, psi_out, dtype, prec, (hipStream_t)hip_stream, nullptr);
+  return apply_exp_impl(plan, tau, psi_in, psi_out, dtype, prec, (hipStream_t)hip_stream, plan->ctx);
 }
 
 int ts_eigvals(const ts_plan* plan, int axis, double* out) {

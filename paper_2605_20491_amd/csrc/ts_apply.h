@@ -15,18 +15,22 @@ struct ApplyParams {
   Epi epi = Epi::Inv;
   double shift = 0.0;
   const int* skip = nullptr;
+  const double2* phase = nullptr;  // Exp: tables Ep | Er | es of the scaling axis
 };
 
 int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st);
-int plan_workspace(ts_plan* p, size_t bytes, void** out);
 
-// u = (H1 + shift)^{-1} b.  work: N*8 bytes of scratch, or null for the plan's.
-// skip: optional device flag; when set, every kernel of the apply returns at once.
+// Scratch bytes of one apply in each context slot.
+size_t need_inverse(const ts_plan* p, int slot);
+size_t need_exp(const ts_plan* p, int slot);
+
+// u = (H1 + shift)^{-1} b with the context's scratch.  skip: optional device
+// flag; when set, every kernel of the apply returns at once.
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, void* work, const int* skip);
-// psi_out = exp(-i tau H1) psi_in.  work: N*16 bytes or null.
+                       hipStream_t st, ExecCtx& c, const int* skip);
+// psi_out = exp(-i tau H1) psi_in.
 int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
-                   hipStream_t st, void* work);
+                   hipStream_t st, ExecCtx& c);
 
 // Optional pointwise potential factors around one propagator apply (in place,
 // psi_in == psi_out): psi <- e^{-i th_post V2} e^{-i tau H1} e^{-i th_pre V2} psi.
@@ -36,6 +40,15 @@ struct Phases {
   double th_pre = 0.0, th_post = 0.0;
 };
 int apply_exp_phased(ts_plan* p, double tau, void* psi, int dtype, int prec, const Phases& ph,
-                     hipStream_t st, void* work);
+                     hipStream_t st, ExecCtx& c);
+
+// Solvers (solvers.cpp) on an explicit context.
+int pcg_run(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x,
+            double rtol, int maxit, int prec, int* iters, double* relres, hipStream_t st, ExecCtx& c);
+int refine_run(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, int* iters,
+               double* relres, hipStream_t st, ExecCtx& c);
+int split_run(ts_plan* p, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec,
+              hipStream_t st, ExecCtx& c);
+size_t need_solver(const ts_plan* p, int nvec);
 
 }  // namespace ts

@@ -95,6 +95,27 @@ hipError_t launch_phase_tables(const PhaseTableArgs& a, hipStream_t st);
 hipError_t launch_cast_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
 hipError_t launch_cast_f64_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st);
 
+// Scratch of one stream of work on a plan: the apply's ping-pong workspace,
+// the propagator's phase tables, the small path's diagonal tables and the
+// solvers' vectors, plus a pinned host mirror of the solver scalars.  A plan
+// owns a growable context for the plain entry points; the serving loop hands
+// each admitted request a fixed context carved from its memory arena.
+enum CtxSlot : int { kSlotWork = 0, kSlotPhase = 1, kSlotTab = 2, kSlotSolver = 3, kSlots = 4 };
+struct ExecCtx {
+  bool growable = true;
+  void* buf[kSlots] = {};
+  size_t bytes[kSlots] = {};
+  void* host = nullptr;  // pinned, >= 256 bytes
+  std::mutex mu;
+  ExecCtx() = default;
+  ExecCtx(const ExecCtx&) = delete;
+  ExecCtx& operator=(const ExecCtx&) = delete;
+  ~ExecCtx();
+};
+// Pointer to at least `bytes` of the slot (grown with hipMalloc if growable).
+int ctx_get(ExecCtx& c, int slot, size_t bytes, void** out);
+int ctx_host(ExecCtx& c, void** out);
+
 }  // namespace ts
 
 // The opaque plan of the C ABI.
@@ -110,15 +131,6 @@ struct ts_plan {
   double* Lp = nullptr;        // device FP64 [Ps]
   double* Lr = nullptr;        // device FP64 [Rs]
   double lam_min = 0;          // lowest eigenvalue of H1
-  // lazily allocated scratch
-  std::mutex mu;
-  void* work = nullptr;
-  size_t work_bytes = 0;
-  double2* phase = nullptr;    // [Ps + Rs + n_s]
-  void* solver = nullptr;      // solver vectors, partial sums and scalars
-  size_t solver_bytes = 0;
-  void* solver_host = nullptr; // pinned host mirror of the solver scalars
-  void* small_tab = nullptr;   // diagonal tables of the grouped small-extent path
-  size_t small_tab_bytes = 0;
+  ts::ExecCtx ctx;             // scratch of the plain (non-serving) entry points
   ~ts_plan();
 };

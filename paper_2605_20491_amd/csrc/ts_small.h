@@ -73,6 +73,8 @@ struct SmallApply {
   bool pre = false, post = false;
   const int* skip = nullptr;
 };
-int run_small_apply(ts_plan* p, const SmallApply& s, hipStream_t st);
+int run_small_apply(ts_plan* p, const SmallApply& s, hipStream_t st, ExecCtx& c);
+// Bytes of the diagonal tables of one grouped apply.
+size_t small_table_bytes(const ts_plan* p, bool cplx, bool fp64, bool exp);
 
 }  // namespace ts

@@ -58,6 +58,9 @@ hipError_t launch_axpy1(double* x, const double* y, int64_t n, const int* skip, 
 // y = x / sqrt(sc->aux[0]).
 hipError_t launch_scale_invnorm(const double* x, double* y, int64_t n, const SolverScalars* sc, hipStream_t st);
 
+// Zero the scalar block and set its tolerance, on the device.
+hipError_t launch_init_scalars(SolverScalars* sc, double tol2, hipStream_t st);
+
 // Scalar steps of PCG, one thread block each.  `what` selects the step.
 enum class ScalarStep : int {
   InitRR = 0,      // rr <- sum(partial), ff <- sum(partial2) ; done if rr <= tol2 * ff

@@ -156,6 +156,15 @@ __global__ __launch_bounds__(RT) void k_scale_invnorm(const double* x, double* y
   for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) y[i] = x[i] * inv;
 }
 
+// Reset the scalar block on the device (no host round trip).
+__global__ void k_init_scalars(SolverScalars* sc, double tol2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    SolverScalars z{};
+    z.tol2 = tol2;
+    *sc = z;
+  }
+}
+
 // Status codes written by the scalar kernel.
 enum { ST_RUN = 0, ST_BREAKDOWN = 1, ST_NONFINITE = 2, ST_MAXIT = 3 };
 
@@ -266,6 +275,11 @@ hipError_t launch_axpy1(double* x, const double* y, int64_t n, const int* skip, 
 hipError_t launch_scale_invnorm(const double* x, double* y, int64_t n, const SolverScalars* sc, hipStream_t st) {
   unsigned grid = (unsigned)std::min<int64_t>((n + RT - 1) / RT, 4096);
   hipLaunchKernelGGL(k_scale_invnorm, dim3(grid), dim3(RT), 0, st, x, y, n, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_scalars(SolverScalars* sc, double tol2, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, tol2);
   return hipGetLastError();
 }
 

