@@ -184,6 +184,56 @@ def split_section(ts, W, torch, dev, d, n, steps=100, dt=1e-3):
     return out
 
 
+def qhop_section(ts, W, torch, dev, n=499, T=0.1, dt=0.01, Ms=(3, 5, 7)):
+    """The separable splitting example: A = -Delta, B = V1 of eq. (separable_V1)
+    on [-8,8]^3, psi0 = prod sin(pi (x_k + L) / 2L), complex128, T = 0.1.
+    Strang (BAB) and approximated qHOP with M nodes; error relative to ||psi0||
+    against the exact propagator of -Delta + V1."""
+    import numpy as np
+    L = 8.0
+    shape = (n, n, n)
+    m = int(round(T / dt))
+    v = W.f_separable_v1(n, L)
+    x = W.grid_nodes(n, L)
+    g = torch.from_numpy(np.sin(np.pi * (x + L) / (2 * L))).to(dev)
+    vd = torch.from_numpy(v).to(dev)
+    V = (vd[:, None, None] + vd[None, :, None] + vd[None, None, :]).contiguous()
+    psi0 = (g[:, None, None] * g[None, :, None] * g[None, None, :]).to(torch.complex128).contiguous()
+    norm0 = float(torch.linalg.vector_norm(psi0))
+    plan_h = ts.ts_setup(shape, L, [v] * 3, 1.0)
+    exact = ts.ts_apply_exp(plan_h, T, psi0)
+    del plan_h
+    plan = ts.ts_setup(shape, L, [np.zeros(n)] * 3, 1.0)
+    out = {"n": n, "dofs": n ** 3, "T": T, "dt": dt,
+           "paper_gh200_s": {"strang": 0.9, "M3": 3.0, "M5": 4.8, "M7": 6.7},
+           "paper_error": {"strang": 5.22e-3, "M3": 1.02e-3, "M5": 4.11e-4, "M7": 2.21e-4}}
+    runs = [("strang", None)] + [("M%d" % M, M) for M in Ms]
+    for key, M in runs:
+        psi = psi0.clone()
+        if M is None:  # warm-up, then the timed run
+            ts.ts_split_step(plan, V, psi, dt, 1, "strang_bab")
+        else:
+            ts.ts_qhop_step(plan, V, psi, dt, 1, M)
+        psi.copy_(psi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if M is None:
+            ts.ts_split_step(plan, V, psi, dt, m, "strang_bab")
+            n_apply = m + 1
+        else:
+            ts.ts_qhop_step(plan, V, psi, dt, m, M)
+            n_apply = m * M + 1
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        err = float(torch.linalg.vector_norm(psi - exact)) / norm0
+        out[key] = {"s": sec, "error": err, "propagations": n_apply, "ms_per_propagation": 1e3 * sec / n_apply}
+        log("qhop %s at %d^3: %.3f s, error %.3e" % (key, n, sec, err))
+        del psi
+    del plan, V, psi0, exact
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVE_SHAPES = [(2048, 2048), (128, 128, 128), (256, 256, 256), (512, 512, 512), (64,) * 4, (16,) * 6]
 SERVE_KINDS = ["inverse_fp64", "inverse_mixed", "exp_c64"]
 
@@ -410,6 +460,7 @@ def main():
     if not args.no_split:
         extra["split_6d_n24"] = split_section(ts, W, torch, dev, 6, 24)
         extra["split_9d_n8"] = split_section(ts, W, torch, dev, 9, 8)
+        extra["qhop_separable_499"] = qhop_section(ts, W, torch, dev)
     if args.serve_requests > 0:
         extra["serving"] = serve_section(ts, W, torch, dev, args.serve_requests)
         torch.cuda.empty_cache()

@@ -189,6 +189,31 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
 int ts_split_step(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme,
                   int dtype, int prec, void* hip_stream);
 
+/* nsteps steps of the approximated qHOP (Sec. 5.1, eq. (qhop_product)) or,
+ * with magnus2 != 0, of the approximated Magnus-2 (eq. (yoshida): three qHOP
+ * steps of sizes g1 dt, g2 dt, g1 dt) for i psi_t = (A + B) psi, A = H1 of
+ * the plan (exact propagator), B = V2 (pointwise).  One qHOP step of size h:
+ *   e^{-iA h} prod_{k=1..M} e^{iA s_k} e^{-i w_k h B} e^{-iA s_k},
+ * the k = 1 factor acting first, s_k = h x_k and w_k the M-point
+ * Gauss-Legendre nodes and normalised weights on [0, 1] (ts_gauss_legendre).
+ * It runs in the merged form of Remark rem:cost_naive_merged (M + 1
+ * propagations for one step, M per step across steps, 3M per Magnus-2 step),
+ * which changes rounding only.  M = 1 is STRANG_ABA and, with magnus2,
+ * YOSHIDA_ABA.  For A = -Delta (the quantum-algorithm setting) pass a plan
+ * with f = 0 and the whole potential in V2.
+ *   V2, psi, dtype, prec : as ts_split_step
+ *   dt, nsteps           : step size (may be negative) and count >= 0
+ *   M                    : quadrature nodes, 1..64
+ * Errors: TS_ERR_INVALID, TS_ERR_NOMEM, TS_ERR_DEVICE. */
+int ts_qhop_step(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int M, int magnus2,
+                 int dtype, int prec, void* hip_stream);
+
+/* M-point Gauss-Legendre rule on [0, 1] (the s_k / dt and w_k of Sec. 5.1):
+ * nodes ascending in (0, 1), weights positive and summing to 1.  Host
+ * arrays of M doubles; no GPU needed.  Errors: TS_ERR_INVALID (M outside
+ * 1..64 or a null pointer). */
+int ts_gauss_legendre(int M, double* nodes, double* weights);
+
 /* ---------------------------------------------------------- operators -- */
 
 /* out = (H1 + diag(V2) + s I) u by the (2d+1)-point stencil, FP64, zero ghost

@@ -60,6 +60,9 @@ def lib():
                                      ctypes.c_int, ctypes.c_int, _dp, _ip, _vp],
             "ts_split_step": [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                               ctypes.c_int, _vp],
+            "ts_qhop_step": [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, _vp],
+            "ts_gauss_legendre": [ctypes.c_int, _dp, _dp],
             "ts_operator_apply": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp],
             "ts_eigvals": [_vp, ctypes.c_int, _dp],
             "ts_eigvecs": [_vp, ctypes.c_int, _dp],
@@ -252,6 +255,20 @@ def ts_split_step(plan: Plan, V2, psi, dt: float, nsteps: int, scheme="strang_ba
                                int(nsteps), sch, _dtype_code(psi), _prec(prec), _stream(stream)),
            "ts_split_step")
     return psi
+
+
+def ts_qhop_step(plan: Plan, V2, psi, dt: float, nsteps: int, M: int, magnus2: bool = False, prec="fp64",
+                 stream=None):
+    _check(lib().ts_qhop_step(plan.handle, _dev(V2, plan, "V2"), _dev(psi, plan, "psi"), float(dt), int(nsteps),
+                              int(M), int(bool(magnus2)), _dtype_code(psi), _prec(prec), _stream(stream)),
+           "ts_qhop_step")
+    return psi
+
+
+def ts_gauss_legendre(M: int):
+    nodes, weights = np.empty(max(int(M), 1)), np.empty(max(int(M), 1))
+    _check(lib().ts_gauss_legendre(int(M), _dptr(nodes), _dptr(weights)), "ts_gauss_legendre")
+    return nodes, weights
 
 
 def ts_operator_apply(plan: Plan, V2, s: float, u, out=None, stream=None):

@@ -49,6 +49,8 @@ int refine_run(ts_plan* p, const double* f, double* u, int inner, double rtol, i
                double* relres, hipStream_t st, ExecCtx& c);
 int split_run(ts_plan* p, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec,
               hipStream_t st, ExecCtx& c);
+int qhop_run(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int M, bool magnus2, int dtype,
+             int prec, hipStream_t st, ExecCtx& c);
 size_t need_solver(const ts_plan* p, int nvec);
 
 }  // namespace ts

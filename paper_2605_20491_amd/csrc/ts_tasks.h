@@ -43,6 +43,13 @@ std::unique_ptr<Task> make_split_task(ts_plan* p, const void* V2, void* psi, dou
                                       int dtype, int prec, ExecCtx& c);
 
 std::vector<std::pair<char, double>> split_factors(int scheme, double dt, int nsteps);
+std::vector<std::pair<char, double>> merge_factors(const std::vector<std::pair<char, double>>& ops);
+constexpr int kMaxQuadNodes = 64;
+bool gauss_legendre01(int M, double* s, double* w);
+std::vector<std::pair<char, double>> qhop_factors(double dt, int nsteps, int M, bool magnus2);
+std::unique_ptr<Task> make_qhop_task(ts_plan* p, const void* V2, void* psi, double dt, int nsteps, int M,
+                                     bool magnus2, int dtype, int prec, ExecCtx& c);
+int qhop_check(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int M, int dtype, int prec);
 int split_check(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec);
 
 }  // namespace ts

@@ -84,3 +84,21 @@ def test_tridiag_eig_matches_oracle_jacobi(n, kind):
         Pq = Q[:, c] @ Q[:, c].T
         Pv = V[:, c] @ V[:, c].T
         assert np.max(np.abs(Pq - Pv)) <= 1e-9
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 7, 16, 64])
+def test_gauss_legendre_rule(M):
+    """ts_gauss_legendre (the s_k, w_k of Sec. 5.1) against numpy's leggauss on
+    [-1, 1] mapped to [0, 1], and exactness for degree <= 2M - 1."""
+    x, w = ts.ts_gauss_legendre(M)
+    xi, om = np.polynomial.legendre.leggauss(M)
+    assert np.max(np.abs(x - (xi + 1) / 2)) < 1e-15
+    assert np.max(np.abs(w - om / 2)) < 1e-14
+    for j in range(min(2 * M, 24)):
+        assert abs(np.dot(w, x**j) - 1.0 / (j + 1)) < 1e-14
+
+
+def test_gauss_legendre_rejects_bad_m():
+    for M in (0, 65):
+        with pytest.raises(ts.TSError):
+            ts.ts_gauss_legendre(M)
