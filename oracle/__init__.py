@@ -143,6 +143,9 @@ class Plan:
 
     ``shape[k]`` and ``f[k]`` follow C order: axis d-1 is the fastest index
     (the paper's x).  ``Q[k]`` columns are eigenvectors, ``lam[k]`` ascending.
+    For a Q^k SEM plan (``sem_k`` >= 1) ``m[k]`` is the lumped mass and
+    ``K[k]`` the dense M^{-1} S of each axis, and ``Q[k]`` diagonalises the
+    symmetric M^{-1/2} S M^{-1/2} + F of eq. (eigen_decomp).
     """
     shape: tuple
     L: float
@@ -150,6 +153,9 @@ class Plan:
     h: list = field(default_factory=list)
     Q: list = field(default_factory=list)
     lam: list = field(default_factory=list)
+    sem_k: int = 0
+    m: list = field(default_factory=list)
+    K: list = field(default_factory=list)
 
     @property
     def d(self):
@@ -177,6 +183,95 @@ def make_plan(shape, L, f_list) -> Plan:
     return p
 
 
+# --------------------------------------------------------------------------
+# Q^k spectral elements with Gauss-Lobatto quadrature (Sec. 2, eq. (eigen_decomp))
+# --------------------------------------------------------------------------
+
+def gll_rule(k: int):
+    """(k+1)-point Gauss-Lobatto rule on [-1, 1]: the end points and the roots
+    of P_k' (numpy's Legendre series), weights 2 / (k (k+1) P_k(x)^2)."""
+    Pk = np.polynomial.legendre.Legendre.basis(int(k))
+    inner = np.sort(Pk.deriv().roots().real) if k > 1 else np.zeros(0)
+    x = np.concatenate([[-1.0], inner, [1.0]])
+    return x, 2.0 / (k * (k + 1) * Pk(x) ** 2)
+
+
+def lagrange_derivative_matrix(xi: np.ndarray) -> np.ndarray:
+    """D[q, j] = l_j'(xi_q) for the Lagrange basis on the nodes xi, from the
+    product rule applied to l_j(x) = prod_{a != j} (x - xi_a) / (xi_j - xi_a)."""
+    m = len(xi)
+    D = np.zeros((m, m))
+    for q in range(m):
+        for j in range(m):
+            acc = 0.0
+            for a in range(m):
+                if a == j:
+                    continue
+                term = 1.0 / (xi[j] - xi[a])
+                for l in range(m):
+                    if l != j and l != a:
+                        term *= (xi[q] - xi[l]) / (xi[j] - xi[l])
+                acc += term
+            D[q, j] = acc
+    return D
+
+
+def sem_axis(k: int, n_cells: int, L: float):
+    """Interior nodes, lumped mass and dense stiffness of Q^k SEM on [-L, L]
+    with n_cells equal elements and homogeneous Dirichlet ends.
+
+    Element e maps the reference nodes xi to -L + e he + (xi + 1) he / 2,
+    he = 2L / n_cells; mass m = sum over elements of (he/2) w; stiffness
+    S = sum over elements of (2/he) D^T diag(w) D.  The k n_cells - 1 interior
+    nodes are returned (the two end nodes carry the Dirichlet values)."""
+    xi, w = gll_rule(k)
+    D = lagrange_derivative_matrix(xi)
+    he = 2.0 * L / n_cells
+    G = k * n_cells + 1
+    x = np.empty(G)
+    m = np.zeros(G)
+    S = np.zeros((G, G))
+    Se = (2.0 / he) * (D.T * w) @ D
+    for e in range(n_cells):
+        idx = e * k + np.arange(k + 1)
+        x[idx] = -L + e * he + (xi + 1.0) * he / 2.0
+        m[idx] += w * he / 2.0
+        S[np.ix_(idx, idx)] += Se
+    return x[1:-1].copy(), m[1:-1].copy(), np.ascontiguousarray(S[1:-1, 1:-1])
+
+
+def sem_nodes(k: int, n_cells: int, L: float) -> np.ndarray:
+    return sem_axis(k, n_cells, L)[0]
+
+
+def make_plan_sem(k: int, cells, L, f_list) -> Plan:
+    """Q^k SEM plan: H_k = M^{-1} S + F = M^{-1/2} (M^{-1/2} S M^{-1/2} + F) M^{1/2}
+    (eq. (eigen_decomp)); the symmetric middle factor is diagonalised by Jacobi."""
+    cells = tuple(int(c) for c in cells)
+    shape = tuple(k * c - 1 for c in cells)
+    f_list = [np.ascontiguousarray(f, dtype=np.float64) for f in f_list]
+    p = Plan(shape=shape, L=float(L), f=f_list, sem_k=int(k))
+    for c, f in zip(cells, f_list):
+        x, m, S = sem_axis(k, c, L)
+        sq = np.sqrt(m)
+        A = S / np.outer(sq, sq) + np.diag(f)
+        w, V = jacobi_eigh(0.5 * (A + A.T))
+        p.h.append(2.0 * L / c)
+        p.Q.append(V)
+        p.lam.append(w)
+        p.m.append(m)
+        p.K.append(np.ascontiguousarray(S / m[:, None]))
+    return p
+
+
+def _mass_root(plan: Plan, power: float) -> np.ndarray:
+    """prod_k m_k(x_k)^power on the grid."""
+    out = np.ones(())
+    for m in plan.m:
+        out = np.multiply.outer(out, m ** power)
+    return out
+
+
 def _arrays_ptrs(arrs):
     return (_dp * len(arrs))(*[_ptr(a) for a in arrs])
 
@@ -196,7 +291,16 @@ def mode_product(shape, axis, Q, X, transpose: bool):
 
 
 def apply_inverse(plan: Plan, b: np.ndarray, sigma: float) -> np.ndarray:
-    """u = (H1 + sigma I)^{-1} b by the four-step solve (real FP64)."""
+    """u = (H1 + sigma I)^{-1} b by the four-step solve (real FP64).  For SEM,
+    T^{-1} = Q^T M^{1/2} and T = M^{-1/2} Q: the orthogonal solve between the
+    two diagonal mass scalings."""
+    if plan.sem_k:
+        b = np.asarray(b, dtype=np.float64).reshape(plan.shape) * _mass_root(plan, 0.5)
+        return _apply_inverse_q(plan, b, sigma) * _mass_root(plan, -0.5)
+    return _apply_inverse_q(plan, b, sigma)
+
+
+def _apply_inverse_q(plan: Plan, b: np.ndarray, sigma: float) -> np.ndarray:
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(plan.shape)
     u = np.empty_like(b)
     work = np.empty_like(b)
@@ -206,7 +310,14 @@ def apply_inverse(plan: Plan, b: np.ndarray, sigma: float) -> np.ndarray:
 
 
 def apply_exp(plan: Plan, psi: np.ndarray, tau: float) -> np.ndarray:
-    """psi' = exp(-i tau H1) psi (eq. (exact_prop)), complex128."""
+    """psi' = exp(-i tau H1) psi (eq. (exact_prop)), complex128; SEM as apply_inverse."""
+    if plan.sem_k:
+        x = np.asarray(psi, dtype=np.complex128).reshape(plan.shape) * _mass_root(plan, 0.5)
+        return _apply_exp_q(plan, x, tau) * _mass_root(plan, -0.5)
+    return _apply_exp_q(plan, psi, tau)
+
+
+def _apply_exp_q(plan: Plan, psi: np.ndarray, tau: float) -> np.ndarray:
     x = _real_view(np.asarray(psi).reshape(plan.shape))
     out = np.empty_like(x)
     work = np.empty_like(x)
@@ -231,8 +342,41 @@ def stencil_apply(plan: Plan, u: np.ndarray, V2=None, sigma: float = 0.0) -> np.
     return out.view(np.complex128).reshape(plan.shape) if cplx else out.reshape(plan.shape)
 
 
+def operator_apply(plan: Plan, u: np.ndarray, V2=None, sigma: float = 0.0) -> np.ndarray:
+    """(H1 + diag V2 + sigma I) u of eq. (general_system): the stencil for FD
+    plans; for SEM plans sum_k (I x .. x K_k x .. x I) u by mode products with
+    the dense K_k = M_k^{-1} S_k, plus (sum_k f_k + V2 + sigma) u."""
+    if not plan.sem_k:
+        return stencil_apply(plan, u, V2, sigma)
+    u = np.asarray(u).reshape(plan.shape)
+    out = np.zeros_like(u)
+    diag = np.full(plan.shape, float(sigma))
+    for k in range(plan.d):
+        out = out + mode_product(plan.shape, k, plan.K[k], u, transpose=False)
+        idx = [None] * plan.d
+        idx[k] = slice(None)
+        diag = diag + plan.f[k][tuple(idx)]
+    if V2 is not None:
+        diag = diag + np.asarray(V2, dtype=np.float64).reshape(plan.shape)
+    return out + diag * u
+
+
 def dense_operator(plan: Plan, V2=None, sigma: float = 0.0) -> np.ndarray:
-    """Dense N x N matrix of H1 + diag V2 + sigma I built from the stencil rule."""
+    """Dense N x N matrix of H1 + diag V2 + sigma I: from the stencil rule for FD
+    plans; for SEM plans the Kronecker sum of eq. (general_system) assembled
+    with np.kron from the per-axis K_k + F_k."""
+    if plan.sem_k:
+        N = plan.N
+        H = np.zeros((N, N))
+        for k in range(plan.d):
+            left = int(np.prod(plan.shape[:k]))
+            right = int(np.prod(plan.shape[k + 1:]))
+            Hk = plan.K[k] + np.diag(plan.f[k])
+            H += np.kron(np.kron(np.eye(left), Hk), np.eye(right))
+        diag = np.full(N, float(sigma))
+        if V2 is not None:
+            diag += np.asarray(V2, dtype=np.float64).reshape(-1)
+        return H + np.diag(diag)
     N = plan.N
     H = np.empty((N, N))
     V2p = None if V2 is None else _ptr(np.ascontiguousarray(V2, dtype=np.float64).reshape(-1))
@@ -282,45 +426,65 @@ class PCGResult:
     history: list
 
 
+def inner(plan: Plan, x: np.ndarray, y: np.ndarray) -> float:
+    """Inner product in which H1 is self-adjoint: Euclidean for FD plans, the
+    mass-weighted sum_p (prod_k m_k) x_p y_p for SEM plans (H_k = M^{-1} S + F
+    is symmetric with respect to M, not in the plain dot product)."""
+    if plan.sem_k:
+        return float(np.sum(_mass_root(plan, 1.0) * np.asarray(x).reshape(plan.shape)
+                            * np.asarray(y).reshape(plan.shape)))
+    return float(np.vdot(x, y))
+
+
+def norm(plan: Plan, x: np.ndarray) -> float:
+    return float(np.sqrt(inner(plan, x, x)))
+
+
 def pcg(plan: Plan, V2, sigma: float, f: np.ndarray, x0=None, rtol: float = 1e-13,
         maxit: int = 500) -> PCGResult:
-    """Textbook PCG for (H1 + diag V2 + sigma) x = f, preconditioner (H1 + sigma)^{-1}.
+    """Textbook PCG for (H1 + diag V2 + sigma) x = f, preconditioner (H1 + sigma)^{-1},
+    in the inner product of ``inner`` (for SEM plans this is CG on the
+    symmetric weak form S + M (V + sigma)).
 
     The preconditioner is the oracle's own four-step solve in FP64.
     """
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(plan.shape)
     x = np.zeros_like(f) if x0 is None else np.array(x0, dtype=np.float64).reshape(plan.shape)
-    nf = np.linalg.norm(f)
-    r = f - stencil_apply(plan, x, V2, sigma)
+    nf = norm(plan, f)
+    r = f - operator_apply(plan, x, V2, sigma)
     z = apply_inverse(plan, r, sigma)
     p = z.copy()
-    rz = float(np.vdot(r, z))
-    hist = [np.linalg.norm(r) / nf]
+    rz = inner(plan, r, z)
+    hist = [norm(plan, r) / nf]
     k = 0
     while hist[-1] > rtol and k < maxit:
-        q = stencil_apply(plan, p, V2, sigma)
-        alpha = rz / float(np.vdot(p, q))
+        q = operator_apply(plan, p, V2, sigma)
+        alpha = rz / inner(plan, p, q)
         x = x + alpha * p
         r = r - alpha * q
         k += 1
-        hist.append(np.linalg.norm(r) / nf)
+        hist.append(norm(plan, r) / nf)
         if hist[-1] <= rtol:
             break
         z = apply_inverse(plan, r, sigma)
-        rz_new = float(np.vdot(r, z))
+        rz_new = inner(plan, r, z)
         beta = rz_new / rz
         rz = rz_new
         p = z + beta * p
-    true = np.linalg.norm(f - stencil_apply(plan, x, V2, sigma)) / nf
+    true = norm(plan, f - operator_apply(plan, x, V2, sigma)) / nf
     return PCGResult(x=x, iters=k, relres=hist[-1], true_relres=true, history=hist)
 
 
 def separable_ground_state(plan: Plan) -> np.ndarray:
-    """Ground state of H1: the tensor product of each axis's lowest eigenvector."""
+    """Ground state of H1: the tensor product of each axis's lowest eigenvector
+    (for SEM the column of T = M^{-1/2} Q), unit norm in ``inner``."""
     u = np.ones(())
     for k in range(plan.d):
-        u = np.multiply.outer(u, plan.Q[k][:, 0])
-    return np.ascontiguousarray(u / np.linalg.norm(u))
+        v = plan.Q[k][:, 0]
+        if plan.sem_k:
+            v = v / np.sqrt(plan.m[k])
+        u = np.multiply.outer(u, v)
+    return np.ascontiguousarray(u / norm(plan, u))
 
 
 @dataclass
@@ -336,19 +500,20 @@ def inverse_iteration(plan: Plan, V2, shift: float, steps: int = 20, u0=None,
 
     Each step solves (H - shift) w = u by PCG preconditioned with
     (H1 - shift)^{-1}, warm-started from the previous step's solution w;
-    then u <- w / ||w|| and lambda <- u^T H u.
+    then u <- w / ||w|| and lambda <- <u, H u> (norm and inner product of
+    ``inner``).
     """
     u = separable_ground_state(plan) if u0 is None else np.array(u0, dtype=np.float64)
-    u = u / np.linalg.norm(u)
-    lam = [float(np.vdot(u, stencil_apply(plan, u, V2, 0.0)))]
+    u = u / norm(plan, u)
+    lam = [inner(plan, u, operator_apply(plan, u, V2, 0.0))]
     its = []
     w = None
     for _ in range(steps):
         res = pcg(plan, V2, -shift, u, x0=w, rtol=pcg_rtol, maxit=maxit)
         w = res.x
         its.append(res.iters)
-        u = w / np.linalg.norm(w)
-        lam.append(float(np.vdot(u, stencil_apply(plan, u, V2, 0.0))))
+        u = w / norm(plan, w)
+        lam.append(inner(plan, u, operator_apply(plan, u, V2, 0.0)))
     return InvIterResult(u=u, lam=lam, pcg_iters=its)
 
 

@@ -30,28 +30,34 @@ def grid_nodes(n: int, L: float) -> np.ndarray:
 
 
 # ---- separable potential samples f_k(x_j) ------------------------------------
+# Each sampler evaluates at the uniform FD nodes of (n, L), or at the nodes x
+# passed in (for instance the Gauss-Lobatto nodes of a spectral-element grid).
 
-def f_harmonic(n: int, L: float, coef: float = 1.0) -> np.ndarray:
+def _nodes(n, L, x):
+    return grid_nodes(n, L) if x is None else np.asarray(x, dtype=np.float64)
+
+
+def f_harmonic(n: int, L: float, coef: float = 1.0, x=None) -> np.ndarray:
     """f(x) = coef * x^2."""
-    x = grid_nodes(n, L)
+    x = _nodes(n, L, x)
     return coef * x * x
 
 
-def f_harmonic_cos(n: int, L: float) -> np.ndarray:
+def f_harmonic_cos(n: int, L: float, x=None) -> np.ndarray:
     """f(x) = x^2 + 0.5 cos(2x) (the 1e9-DoF workload's per-axis potential)."""
-    x = grid_nodes(n, L)
+    x = _nodes(n, L, x)
     return x * x + 0.5 * np.cos(2.0 * x)
 
 
-def f_separable_v1(n: int, L: float) -> np.ndarray:
+def f_separable_v1(n: int, L: float, x=None) -> np.ndarray:
     """f(x) = x^2 + 100 sin^2(pi x / 4): per-axis term of eq. (separable_V1)."""
-    x = grid_nodes(n, L)
+    x = _nodes(n, L, x)
     return x * x + 100.0 * np.sin(np.pi * x / 4.0) ** 2
 
 
-def f_test_potential(n: int, L: float, c: float) -> np.ndarray:
+def f_test_potential(n: int, L: float, c: float, x=None) -> np.ndarray:
     """f(x) = 1600 sin^2(pi x / 4) + c x^2: one axis of eq. (test_potential)."""
-    x = grid_nodes(n, L)
+    x = _nodes(n, L, x)
     return 1600.0 * np.sin(np.pi * x / 4.0) ** 2 + c * x * x
 
 
