@@ -234,6 +234,73 @@ def qhop_section(ts, W, torch, dev, n=499, T=0.1, dt=0.01, Ms=(3, 5, 7)):
     return out
 
 
+# Rows of Table tab:accuracy_gh200: (label, precision, dim, k, cells, printed error, GH200 setup s, solve s)
+ACCURACY_ROWS = [
+    ("fp64_3d_q1", "fp64", 3, 1, 1100, 3.66e-6, 5.2, 0.508),
+    ("fp64_3d_q2", "fp64", 3, 2, 550, 1.93e-9, 5.1, 0.512),
+    ("fp64_3d_q10", "fp64", 3, 10, 110, 7.66e-13, 6.4, 0.510),
+    ("fp64_4d_q10", "fp64", 4, 10, 18, 1.29e-13, 6.2, 0.195),
+    ("fp64_6d_q2", "fp64", 6, 2, 17, 2.95e-2, 5.9, 0.258),
+    ("fp32_3d_q2", "fp32", 3, 2, 500, 7.17e-7, 5.4, 0.270),
+    ("fp32_4d_q10", "fp32", 4, 10, 15, 4.99e-7, 5.8, 0.058),
+    ("fp32_4d_q10_199", "fp32", 4, 10, 20, 6.20e-7, 5.8, 0.188),
+    ("fp32_6d_q10", "fp32", 6, 10, 3, 4.75e-4, 5.7, 0.052),
+    ("bf16_3d_q2", "bf16", 3, 2, 500, 1.65e-2, 5.4, 0.088),
+    ("bf16_3d_q2_1599", "bf16", 3, 2, 800, 1.64e-2, 5.6, 0.517),
+]
+
+
+def accuracy_section(ts, W, torch, dev, steps=3):
+    """Direct inverse of the paper's test problems with Q^k SEM on [-1,1]^d:
+    eq. (test_potential) with u* = sin(pi x) sin(2 pi y) sin(3 pi z) in 3D,
+    V = sum x_k^2 with u* = prod sin(k pi x_k) in 4D and 6D.  Reports setup
+    and per-solve time and the l2 relative error beside the printed values."""
+    import numpy as np
+    L = 1.0
+    out = {}
+    for label, prec, d, k, cells, printed, p_setup, p_solve in ACCURACY_ROWS:
+        x = ts.ts_sem_nodes(k, cells, L)
+        n = x.size
+        if d == 3:
+            coef = {2: 1.0, 1: 2.0, 0: 3.0}
+            f = [W.f_test_potential(0, L, coef[a], x=x) for a in range(3)]
+            modes = [3, 2, 1]
+        else:
+            f = [W.f_harmonic(0, L, x=x) for _ in range(d)]
+            modes = list(range(d, 0, -1))
+        t0 = time.perf_counter()
+        plan = ts.ts_setup_sem(k, (cells,) * d, L, f, 0.0)
+        setup = time.perf_counter() - t0
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        xd = torch.from_numpy(x).to(dev)
+        fac = [torch.sin(mm * np.pi * xd) for mm in modes]
+        fd = [torch.from_numpy(fa).to(dev) for fa in f]
+        lap = float(sum((mm * np.pi) ** 2 for mm in modes))
+        ustar = fac[0]
+        rhs = fd[0]
+        for a in range(1, d):
+            ustar = ustar.unsqueeze(-1) * fac[a]
+            rhs = rhs.unsqueeze(-1) + fd[a]
+        rhs.add_(lap).mul_(ustar)          # (-Delta + V) u* at the nodes, in place
+        if dt != torch.float64:
+            rhs = rhs.to(dt)
+        u = torch.empty_like(rhs)
+        ms, _ = timed(lambda: ts.ts_apply_inverse(plan, rhs, u, prec=prec), steps, 1)
+        num = den = 0.0
+        for i in range(n):                 # error norms slab by slab (no full-size temporaries)
+            num += float(torch.sum((u[i].to(torch.float64) - ustar[i]) ** 2))
+            den += float(torch.sum(ustar[i] ** 2))
+        err = (num / den) ** 0.5
+        out[label] = {"n": n, "d": d, "k": k, "cells": cells, "dofs": n ** d, "setup_s": setup,
+                      "solve_s": ms * 1e-3, "l2_rel_err": err, "paper_err": printed,
+                      "paper_gh200_setup_s": p_setup, "paper_gh200_solve_s": p_solve}
+        log("accuracy %s: %d^%d setup %.2f s solve %.4f s err %.3e (printed %.3e, GH200 %.3f s)"
+            % (label, n, d, setup, ms * 1e-3, err, printed, p_solve))
+        del plan, rhs, u, ustar, fac
+        torch.cuda.empty_cache()
+    return out
+
+
 SERVE_SHAPES = [(2048, 2048), (128, 128, 128), (256, 256, 256), (512, 512, 512), (64,) * 4, (16,) * 6]
 SERVE_KINDS = ["inverse_fp64", "inverse_mixed", "exp_c64"]
 
@@ -376,6 +443,7 @@ def main():
     ap.add_argument("--cpu-depth", type=int, default=96)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-table", action="store_true", help="skip the Table tab:accuracy_gh200 rows")
     ap.add_argument("--serve-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -461,6 +529,8 @@ def main():
         extra["split_6d_n24"] = split_section(ts, W, torch, dev, 6, 24)
         extra["split_9d_n8"] = split_section(ts, W, torch, dev, 9, 8)
         extra["qhop_separable_499"] = qhop_section(ts, W, torch, dev)
+    if not args.no_table:
+        extra["accuracy_table"] = accuracy_section(ts, W, torch, dev)
     if args.serve_requests > 0:
         extra["serving"] = serve_section(ts, W, torch, dev, args.serve_requests)
         torch.cuda.empty_cache()

@@ -102,6 +102,37 @@ int ts_setup(int d, const int64_t* n, double L, const double* const* f, double s
  * Synchronises the device first, so pending work that uses the plan ends. */
 int ts_destroy(ts_plan* plan);
 
+/* Plan of the Q^k spectral-element discretisation (Sec. 2, eq. (eigen_decomp)):
+ * each axis of [-L, L] is split into cells[a] equal elements carrying the
+ * k+1 Gauss-Lobatto nodes of degree k; n[a] = k cells[a] - 1 interior nodes
+ * (ts_sem_nodes), homogeneous Dirichlet ends, lumped Gauss-Lobatto mass M
+ * and assembled stiffness S.  H_a = M^{-1} S + diag(f_a); it is diagonalised
+ * through the symmetric M^{-1/2} S M^{-1/2} + F = Q Lambda Q^T, so that
+ * T = M^{-1/2} Q and T^{-1} = Q^T M^{1/2} (host FP64 Householder reduction
+ * and QL).  k = 1 is the FD grid of ts_setup with N_cell = n + 1.
+ *   cells : host int64[d], k * cells[a] - 1 in [1, 8192]
+ *   k     : polynomial degree, 1..16
+ *   f     : host FP64 arrays, f[a] holds f_a at the nodes of ts_sem_nodes
+ * Every entry point then works on the nodal values of the SEM grid: the
+ * applies compute (H1 + sigma)^{-1} and e^{-i tau H1} with the T factors;
+ * ts_operator_apply applies M^{-1} S per axis (band of 2k+1 entries); the
+ * solvers (PCG, refinement, inverse iteration) run in the mass inner product
+ * sum_p (prod_a m_a) x_p y_p, in which H1 + V2 is self-adjoint, so their
+ * residual norms and eigenvector normalisation are mass-weighted.
+ * Errors: TS_ERR_INVALID, TS_ERR_NONFINITE, TS_ERR_NOMEM, TS_ERR_DEVICE. */
+int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* const* f, double sigma,
+                 ts_plan** out);
+
+/* Host: the k cells - 1 interior nodes of Q^k SEM on [-L, L] (ascending),
+ * the points at which f_a and V2 are sampled.  x: host array of k cells - 1
+ * doubles.  Errors: TS_ERR_INVALID. */
+int ts_sem_nodes(int k, int64_t cells, double L, double* x);
+
+/* Host copy of the lumped mass of an axis (n[axis] doubles): the
+ * Gauss-Lobatto weights times the element half-length, summed at element
+ * interfaces; h for FD plans. */
+int ts_mass(const ts_plan* plan, int axis, double* out);
+
 /* --------------------------------------------------------------- applies -- */
 
 /* u = (H1 + sigma I)^{-1} b by the four steps of Sec. 2.1: forward transform
@@ -228,7 +259,9 @@ int ts_operator_apply(ts_plan* plan, const double* V2, double s, const double* u
 int ts_eigvals(const ts_plan* plan, int axis, double* out);
 
 /* Host copy of Q_axis, row-major, column j = unit eigenvector of lam[j]
- * (n[axis]^2 doubles).  Eigenvectors are unique up to sign only. */
+ * (n[axis]^2 doubles).  Eigenvectors are unique up to sign only.  For SEM
+ * plans these are the eigenvectors of M^{-1/2} S M^{-1/2} + F; the nodal
+ * eigenfunctions are the columns of T = M^{-1/2} Q (ts_mass). */
 int ts_eigvecs(const ts_plan* plan, int axis, double* out);
 
 /* Device bytes a single apply of the given dtype may allocate as scratch. */
@@ -241,6 +274,14 @@ int ts_workspace_bytes(const ts_plan* plan, int dtype, size_t* bytes);
  * eigenvector of lam[j], sign chosen so its largest-magnitude entry is
  * positive.  Host pointers.  Errors: TS_ERR_INVALID, TS_ERR_NOCONV. */
 int ts_tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q);
+
+/* Host FP64 eigendecomposition of a dense symmetric matrix (row-major n x n;
+ * the symmetric part (A + A^T)/2 is used) by Householder reduction to
+ * tridiagonal form and implicit QL (the per-axis step of eq. (eigen_decomp)
+ * that ts_setup_sem runs).  Needs no GPU.  lam: n ascending eigenvalues; Q:
+ * row-major, column j = unit eigenvector of lam[j], largest-magnitude entry
+ * positive.  Host pointers.  Errors: TS_ERR_INVALID, TS_ERR_NOCONV. */
+int ts_sym_eig(int64_t n, const double* A, double* lam, double* Q);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* ts_last_error(void);

@@ -51,6 +51,10 @@ def lib():
             "ts_setup": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_double,
                          ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
             "ts_destroy": [_vp],
+            "ts_setup_sem": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
+                             ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
+            "ts_sem_nodes": [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _dp],
+            "ts_mass": [_vp, ctypes.c_int, _dp],
             "ts_apply_inverse": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_apply_inverse_shift": [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_apply_exp": [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
@@ -68,6 +72,7 @@ def lib():
             "ts_eigvecs": [_vp, ctypes.c_int, _dp],
             "ts_workspace_bytes": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
             "ts_tridiag_eig": [ctypes.c_int64, _dp, _dp, _dp, _dp],
+            "ts_sym_eig": [ctypes.c_int64, _dp, _dp, _dp],
         }
         for name, argt in sig.items():
             fn = getattr(L, name)
@@ -176,6 +181,32 @@ def ts_setup(shape, L: float, f_list, sigma: float) -> Plan:
     h = _vp()
     _check(lib().ts_setup(d, n, float(L), fp, float(sigma), ctypes.byref(h)), "ts_setup")
     return Plan(h, shape, L, sigma)
+
+
+def ts_setup_sem(k: int, cells, L: float, f_list, sigma: float) -> Plan:
+    """Q^k spectral-element plan; f_list[a] holds f_a at ts_sem_nodes(k, cells[a], L)."""
+    d = len(cells)
+    shape = tuple(int(k) * int(c) - 1 for c in cells)
+    cc = (ctypes.c_int64 * d)(*[int(c) for c in cells])
+    fs = [np.ascontiguousarray(f, dtype=np.float64) for f in f_list]
+    if len(fs) != d or any(f.shape != (n,) for f, n in zip(fs, shape)):
+        raise ValueError("f_list must hold one array of k * cells[a] - 1 samples per axis")
+    fp = (_dp * d)(*[_dptr(f) for f in fs])
+    h = _vp()
+    _check(lib().ts_setup_sem(d, cc, int(k), float(L), fp, float(sigma), ctypes.byref(h)), "ts_setup_sem")
+    return Plan(h, shape, L, sigma)
+
+
+def ts_sem_nodes(k: int, cells: int, L: float) -> np.ndarray:
+    x = np.empty(max(int(k) * int(cells) - 1, 1))
+    _check(lib().ts_sem_nodes(int(k), int(cells), float(L), _dptr(x)), "ts_sem_nodes")
+    return x
+
+
+def ts_mass(plan: Plan, axis: int) -> np.ndarray:
+    out = np.empty(plan.shape[axis])
+    _check(lib().ts_mass(plan.handle, int(axis), _dptr(out)), "ts_mass")
+    return out
 
 
 def ts_destroy(plan: Plan):
@@ -307,6 +338,15 @@ def ts_tridiag_eig(diag: np.ndarray, off: np.ndarray):
     Q = np.empty((n, n))
     offp = _dptr(off) if off.size else _dptr(np.zeros(1))
     _check(lib().ts_tridiag_eig(n, _dptr(diag), offp, _dptr(lam), _dptr(Q)), "ts_tridiag_eig")
+    return lam, Q
+
+
+def ts_sym_eig(A: np.ndarray):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    lam = np.empty(n)
+    Q = np.empty((n, n))
+    _check(lib().ts_sym_eig(n, _dptr(A), _dptr(lam), _dptr(Q)), "ts_sym_eig")
     return lam, Q
 
 

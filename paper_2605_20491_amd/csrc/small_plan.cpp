@@ -134,7 +134,7 @@ int run_small_apply(ts_plan* p, const SmallApply& s, hipStream_t st, ExecCtx& c)
       // forward over the group's axes fastest first, backward slowest first
       for (int i = 0; i <= g.b - g.a; ++i) {
         const int k = forward ? g.b - i : g.a + i;
-        const AxisFactor* F = p->ax[k].get();
+        const AxisFactor* F = (s.sym ? p->ax_sym : p->ax)[k].get();
         GroupStep& S = a.step[ns++];
         if (s.fp64) S.Q = forward ? (const void*)F->Q64 : (const void*)F->QT64;
         else S.Q = forward ? (const void*)F->Q32 : (const void*)F->QT32;

@@ -20,23 +20,39 @@
 
 namespace ts {
 
-StencilArgs stencil_args(const ts_plan* p, const double* V2, double s, const double* u, double* out) {
+StencilArgs stencil_args(const ts_plan* p, const double* V2, double s, const double* u, double* out, bool sym) {
   StencilArgs a;
   a.d = p->d;
   a.N = p->N;
   int64_t st = 1;
+  const auto& ax = sym ? p->ax_sym : p->ax;
   for (int k = p->d - 1; k >= 0; --k) {
     a.n[k] = p->n[k];
     a.stride[k] = st;
     st *= p->n[k];
-    a.ih2[k] = p->ax[k]->ih2;
-    a.f[k] = p->ax[k]->f;
+    a.ih2[k] = ax[k]->ih2;
+    a.f[k] = ax[k]->f;
+    a.band[k] = ax[k]->band;
   }
+  a.bw = p->sem_k ? ax[0]->bw : 0;
   a.V2 = V2;
   a.s = s;
   a.u = u;
   a.out = out;
   return a;
+}
+
+// SEM plans: the solvers run on the symmetric form M^{-1/2} S M^{-1/2} + F in
+// the variables M^{1/2} u (Euclidean inner products there are the mass inner
+// products of u).  Scale x by M^{1/2} (up) or M^{-1/2} (down); no-op for FD.
+hipError_t mass_scale(const ts_plan* p, const double* x, double* y, bool up, hipStream_t st) {
+  if (!p->sem_k) {
+    if (x != y) return hipMemcpyAsync(y, x, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToDevice, st);
+    return hipSuccess;
+  }
+  const double* w[TS_MAX_D];
+  for (int k = 0; k < p->d; ++k) w[k] = up ? p->ax_sym[k]->msq : p->ax_sym[k]->imsq;
+  return launch_axis_scale(x, y, p->d, p->n, w, st);
 }
 
 namespace {
@@ -102,22 +118,28 @@ int status_code(const SolverScalars& s) {
 class PcgTask : public Task {
  public:
   PcgTask(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x, double rtol,
-          int maxit, int prec, ExecCtx& c)
-      : p_(p), V2_(V2), s_op_(s_op), s_pc_(s_pc), f_(f), x_(x), rtol_(rtol), maxit_(maxit), prec_(prec), c_(c) {}
+          int maxit, int prec, bool scale_io, ExecCtx& c)
+      : p_(p), V2_(V2), s_op_(s_op), s_pc_(s_pc), f_(f), x_(x), rtol_(rtol), maxit_(maxit), prec_(prec),
+        scale_(scale_io && p->sem_k), c_(c) {}
 
   int start(hipStream_t st) override {
-    TS_RC(solver_buffers(c_, p_, 4, b_));
+    TS_RC(solver_buffers(c_, p_, scale_ ? 5 : 4, b_));
     r_ = b_.vec[0];
     z_ = b_.vec[1];
     pp_ = b_.vec[2];
     q_ = b_.vec[3];
     N_ = p_->N;
+    if (scale_) {  // f and x into the symmetric form's variables
+      TS_TRY(mass_scale(p_, f_, b_.vec[4], true, st));
+      TS_TRY(mass_scale(p_, x_, x_, true, st));
+      f_ = b_.vec[4];
+    }
     flexible_ = prec_ != TS_PREC_FP64;
     done_ = &b_.sc->done;
     chunk_ = N_ >= (int64_t(1) << 24) ? 2 : (N_ >= (int64_t(1) << 20) ? 4 : 8);
     TS_TRY(launch_init_scalars(b_.sc, rtol_ * rtol_, st));
     // r = f - A x ; ||r||^2 and ||f||^2
-    sa_ = stencil_args(p_, V2_, s_op_, x_, r_);
+    sa_ = stencil_args(p_, V2_, s_op_, x_, r_, true);
     sa_.mode = StOut::FminusAx;
     sa_.rhs = f_;
     sa_.dot = StDot::OutdotOut;
@@ -126,11 +148,11 @@ class PcgTask : public Task {
     TS_TRY(launch_dot(f_, f_, N_, b_.partial2, nullptr, nullptr, nullptr, st));
     TS_TRY(launch_scalar(ScalarStep::InitRR, b_.sc, b_.partial, b_.partial2, flexible_, maxit_, st));
     // z = M^{-1} r ; <r, z> ; p = z
-    TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_));
+    TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_, true));
     TS_TRY(launch_dot(r_, z_, N_, b_.partial, nullptr, nullptr, done_, st));
     TS_TRY(launch_scalar(ScalarStep::InitRZ, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
     TS_TRY(hipMemcpyAsync(pp_, z_, sizeof(double) * N_, hipMemcpyDeviceToDevice, st));
-    sq_ = stencil_args(p_, V2_, s_op_, pp_, q_);
+    sq_ = stencil_args(p_, V2_, s_op_, pp_, q_, true);
     sq_.dot = StDot::UdotOut;
     sq_.partial = b_.partial;
     sq_.skip = done_;
@@ -165,6 +187,7 @@ class PcgTask : public Task {
     } else {
       status = status_code(s);
     }
+    if (scale_) TS_TRY(mass_scale(p_, x_, x_, false, st));  // back to the caller's variables
     *done = true;
     return TS_OK;
   }
@@ -176,7 +199,7 @@ class PcgTask : public Task {
       TS_TRY(launch_scalar(ScalarStep::Alpha, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
       TS_TRY(launch_cg_update(x_, r_, pp_, q_, N_, b_.sc, b_.partial, done_, st));
       TS_TRY(launch_scalar(ScalarStep::RR, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
-      TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_));
+      TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_, true));
       TS_TRY(launch_dot(z_, r_, N_, b_.partial, flexible_ ? q_ : nullptr, flexible_ ? b_.partial2 : nullptr,
                         done_, st));
       TS_TRY(launch_scalar(ScalarStep::Beta, b_.sc, b_.partial, flexible_ ? b_.partial2 : nullptr, flexible_,
@@ -193,6 +216,7 @@ class PcgTask : public Task {
   double* x_;
   double rtol_;
   int maxit_, prec_;
+  bool scale_;
   ExecCtx& c_;
   SolverBufs b_;
   double *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr, *q_ = nullptr;
@@ -210,20 +234,26 @@ class PcgTask : public Task {
 // than 0.9 twice, the rest is flexible CG warm-started from u.
 class RefineTask : public Task {
  public:
-  RefineTask(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, ExecCtx& c)
-      : p_(p), f_(f), u_(u), inner_(inner), rtol_(rtol), maxit_(maxit), c_(c) {}
+  RefineTask(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, bool scale_io,
+             ExecCtx& c)
+      : p_(p), f_(f), u_(u), inner_(inner), rtol_(rtol), maxit_(maxit), scale_(scale_io && p->sem_k), c_(c) {}
 
   int start(hipStream_t st) override {
-    TS_RC(solver_buffers(c_, p_, 2, b_));
+    // vector 4 holds the scaled right-hand side: the CG fallback uses 0..3
+    TS_RC(solver_buffers(c_, p_, scale_ ? 5 : 2, b_));
     r_ = b_.vec[0];
     dlt_ = b_.vec[1];
     N_ = p_->N;
+    if (scale_) {
+      TS_TRY(mass_scale(p_, f_, b_.vec[4], true, st));
+      f_ = b_.vec[4];
+    }
     TS_TRY(launch_init_scalars(b_.sc, rtol_ * rtol_, st));
     TS_TRY(launch_dot(f_, f_, N_, b_.partial, nullptr, nullptr, nullptr, st));
     TS_TRY(launch_scalar(ScalarStep::SetAux0, b_.sc, b_.partial, nullptr, 0, maxit_, st));
     // first sweep from u = 0: u = M^{-1} f, then its residual
-    TS_RC(apply_inverse_impl(p_, p_->sigma, f_, u_, TS_F64, inner_, st, c_, nullptr));
-    sa_ = stencil_args(p_, nullptr, p_->sigma, u_, r_);
+    TS_RC(apply_inverse_impl(p_, p_->sigma, f_, u_, TS_F64, inner_, st, c_, nullptr, true));
+    sa_ = stencil_args(p_, nullptr, p_->sigma, u_, r_, true);
     sa_.mode = StOut::FminusAx;
     sa_.rhs = f_;
     sa_.dot = StDot::OutdotOut;
@@ -236,6 +266,13 @@ class RefineTask : public Task {
   }
 
   int advance(hipStream_t st, bool* done) override {
+    TS_RC(step(st, done));
+    if (*done && scale_) TS_TRY(mass_scale(p_, u_, u_, false, st));  // back to the caller's variables
+    return TS_OK;
+  }
+
+ private:
+  int step(hipStream_t st, bool* done) {
     if (cg_) {
       TS_RC(cg_->advance(st, done));
       if (*done) {
@@ -262,10 +299,10 @@ class RefineTask : public Task {
     if (sweeps_ >= maxit_) { set_error("refinement did not reach rtol"); status = TS_ERR_NOCONV; return TS_OK; }
     *done = false;
     if (slow_ >= 2) {
-      cg_ = make_pcg_task(p_, nullptr, p_->sigma, p_->sigma, f_, u_, rtol_, maxit_ - sweeps_, inner_, c_);
+      cg_ = make_pcg_task(p_, nullptr, p_->sigma, p_->sigma, f_, u_, rtol_, maxit_ - sweeps_, inner_, c_, false);
       return cg_->start(st);
     }
-    TS_RC(apply_inverse_impl(p_, p_->sigma, r_, dlt_, TS_F64, inner_, st, c_, nullptr));
+    TS_RC(apply_inverse_impl(p_, p_->sigma, r_, dlt_, TS_F64, inner_, st, c_, nullptr, true));
     TS_TRY(launch_axpy1(u_, dlt_, N_, nullptr, st));
     TS_TRY(launch_stencil(sa_, st));
     TS_TRY(launch_scalar(ScalarStep::SetRR, b_.sc, b_.partial, nullptr, 0, maxit_, st));
@@ -274,13 +311,13 @@ class RefineTask : public Task {
     return TS_OK;
   }
 
- private:
   ts_plan* p_;
   const double* f_;
   double* u_;
   int inner_;
   double rtol_;
   int maxit_;
+  bool scale_;
   ExecCtx& c_;
   SolverBufs b_;
   double *r_ = nullptr, *dlt_ = nullptr;
@@ -333,12 +370,12 @@ int run_blocking(Task& t, hipStream_t st) {
 }
 
 std::unique_ptr<Task> make_pcg_task(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f,
-                                    double* x, double rtol, int maxit, int prec, ExecCtx& c) {
-  return std::unique_ptr<Task>(new PcgTask(p, V2, s_op, s_pc, f, x, rtol, maxit, prec, c));
+                                    double* x, double rtol, int maxit, int prec, ExecCtx& c, bool scale_io) {
+  return std::unique_ptr<Task>(new PcgTask(p, V2, s_op, s_pc, f, x, rtol, maxit, prec, scale_io, c));
 }
 std::unique_ptr<Task> make_refine_task(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit,
                                        ExecCtx& c) {
-  return std::unique_ptr<Task>(new RefineTask(p, f, u, inner, rtol, maxit, c));
+  return std::unique_ptr<Task>(new RefineTask(p, f, u, inner, rtol, maxit, true, c));
 }
 std::unique_ptr<Task> make_inverse_task(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
                                         ExecCtx& c) {
@@ -352,8 +389,8 @@ std::unique_ptr<Task> make_exp_task(ts_plan* p, double tau, const void* in, void
 size_t need_solver(const ts_plan* p, int nvec) { return solver_header() + solver_vbytes(p) * nvec; }
 
 int pcg_run(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x, double rtol,
-            int maxit, int prec, int* iters, double* relres, hipStream_t st, ExecCtx& c) {
-  PcgTask t(p, V2, s_op, s_pc, f, x, rtol, maxit, prec, c);
+            int maxit, int prec, int* iters, double* relres, hipStream_t st, ExecCtx& c, bool scale_io) {
+  PcgTask t(p, V2, s_op, s_pc, f, x, rtol, maxit, prec, scale_io, c);
   int rc = run_blocking(t, st);
   if (iters) *iters = t.iters;
   if (relres) *relres = t.relres;
@@ -362,7 +399,7 @@ int pcg_run(ts_plan* p, const double* V2, double s_op, double s_pc, const double
 
 int refine_run(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, int* iters,
                double* relres, hipStream_t st, ExecCtx& c) {
-  RefineTask t(p, f, u, inner, rtol, maxit, c);
+  RefineTask t(p, f, u, inner, rtol, maxit, true, c);
   int rc = run_blocking(t, st);
   if (iters) *iters = t.iters;
   if (relres) *relres = t.relres;
@@ -379,7 +416,7 @@ int ts_operator_apply(ts_plan* plan, const double* V2, double s, const double* u
                       void* hip_stream) {
   if (!plan || !u || !out) { set_error("null argument"); return TS_ERR_INVALID; }
   if (u == out) { set_error("u and out must not alias"); return TS_ERR_INVALID; }
-  hipError_t e = launch_stencil(stencil_args(plan, V2, s, u, out), (hipStream_t)hip_stream);
+  hipError_t e = launch_stencil(stencil_args(plan, V2, s, u, out, false), (hipStream_t)hip_stream);
   if (e != hipSuccess) { set_error(std::string("stencil launch failed: ") + hipGetErrorString(e)); return TS_ERR_DEVICE; }
   return TS_OK;
 }
@@ -419,13 +456,15 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
   TS_RC(solver_buffers(c, plan, 6, b));
   double* Hu = b.vec[4];
   double* w = b.vec[5];
+  // SEM: iterate on the symmetric form, u in the variables M^{1/2} u
+  TS_TRY(mass_scale(plan, u, u, true, st));
   auto rayleigh = [&](double* lam) -> int {
     // ||u||^2 -> aux0, u <- u / ||u||, lambda = u^T H u (s = 0)
     TS_TRY(launch_init_scalars(b.sc, 0.0, st));
     TS_TRY(launch_dot(u, u, N, b.partial, nullptr, nullptr, nullptr, st));
     TS_TRY(launch_scalar(ScalarStep::SetAux0, b.sc, b.partial, nullptr, 0, 1, st));
     TS_TRY(launch_scale_invnorm(u, u, N, b.sc, st));
-    StencilArgs s = stencil_args(plan, V2, 0.0, u, Hu);
+    StencilArgs s = stencil_args(plan, V2, 0.0, u, Hu, true);
     s.dot = StDot::UdotOut;
     s.partial = b.partial;
     TS_TRY(launch_stencil(s, st));
@@ -442,13 +481,17 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
   for (int k = 0; k < steps; ++k) {
     int it = 0;
     double rr = 0.0;
-    int rc = pcg_run(plan, V2, -shift, -shift, u, w, pcg_rtol, maxit, precond, &it, &rr, st, c);
+    int rc = pcg_run(plan, V2, -shift, -shift, u, w, pcg_rtol, maxit, precond, &it, &rr, st, c, false);
     if (pcg_iters) pcg_iters[k] = it;
-    if (rc) return rc;
+    if (rc) {
+      mass_scale(plan, u, u, false, st);
+      return rc;
+    }
     TS_TRY(hipMemcpyAsync(u, w, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
     TS_RC(rayleigh(&lam));
     if (lam_hist) lam_hist[k + 1] = lam;
   }
+  TS_TRY(mass_scale(plan, u, u, false, st));
   TS_TRY(hipStreamSynchronize(st));
   return TS_OK;
 }

@@ -12,6 +12,7 @@
 #include "../../include/ts.h"
 #include "ts_internal.h"
 #include "ts_apply.h"
+#include "ts_sem.h"
 #include "ts_small.h"
 
 namespace ts {
@@ -28,15 +29,92 @@ AxisFactor::~AxisFactor() {
   hipFree(QT32);
   hipFree(Q16);
   hipFree(QT16);
+  hipFree(band);
+  hipFree(msq);
+  hipFree(imsq);
 }
+
+namespace {
+
+// Upload one factor set.  Fwd and Bwd are row-major n x n with the pass
+// convention y_j = sum_i W[i][j] x_i; they are zero-padded to [kpad][ld].
+// band (n * (2 bw + 1) entries) and the mass roots are optional.
+int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd, const std::vector<double>& Bwd,
+                  const std::vector<double>* band, const std::vector<double>* m) {
+  const int64_t n = F.n;
+  F.ld = round_up(n, kTileF);
+  F.kpad = F.ld;  // square padding: every kernel's tiles stay inside
+  const size_t padded = (size_t)(F.kpad * F.ld);
+  std::vector<double> Qp(padded, 0.0), QTp(padded, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      Qp[(size_t)(i * F.ld + j)] = Fwd[(size_t)(i * n + j)];
+      QTp[(size_t)(i * F.ld + j)] = Bwd[(size_t)(i * n + j)];
+    }
+  std::vector<double> ms, ims;
+  if (m) {
+    ms.resize(n);
+    ims.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+      ms[i] = std::sqrt((*m)[i]);
+      ims[i] = 1.0 / ms[i];
+    }
+  }
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&F.lam, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&F.f, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&F.Q64, sizeof(double) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F.QT64, sizeof(double) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F.Q32, sizeof(float) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F.QT32, sizeof(float) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F.Q16, sizeof(uint16_t) * padded);
+  if (e == hipSuccess) e = hipMalloc(&F.QT16, sizeof(uint16_t) * padded);
+  if (e == hipSuccess && band) e = hipMalloc(&F.band, sizeof(double) * band->size());
+  if (e == hipSuccess && m) e = hipMalloc(&F.msq, sizeof(double) * n);
+  if (e == hipSuccess && m) e = hipMalloc(&F.imsq, sizeof(double) * n);
+  if (e != hipSuccess) {
+    set_error(std::string("device allocation of factors failed: ") + hipGetErrorString(e));
+    return TS_ERR_NOMEM;
+  }
+  // upload on a private non-blocking stream: setup never waits for other work
+  hipStream_t st = nullptr;
+  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.lam, F.lam_h.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.f, f, sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.Q64, Qp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.QT64, QTp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && band)
+    e = hipMemcpyAsync(F.band, band->data(), sizeof(double) * band->size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && m) e = hipMemcpyAsync(F.msq, ms.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && m) e = hipMemcpyAsync(F.imsq, ims.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  // reduced-precision copies are cast on the device from the FP64 copy
+  if (e == hipSuccess) e = launch_cast_f64_to_f32(F.Q64, F.Q32, (int64_t)padded, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_f32(F.QT64, F.QT32, (int64_t)padded, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F.Q64, F.Q16, (int64_t)padded, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F.QT64, F.QT16, (int64_t)padded, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (st) hipStreamDestroy(st);
+  if (e != hipSuccess) {
+    set_error(std::string("factor upload failed: ") + hipGetErrorString(e));
+    return TS_ERR_DEVICE;
+  }
+  return TS_OK;
+}
+
+std::vector<double> transpose(const std::vector<double>& A, int64_t n) {
+  std::vector<double> T(A.size());
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) T[(size_t)(j * n + i)] = A[(size_t)(i * n + j)];
+  return T;
+}
+
+}  // namespace
 
 // Build and upload the factors of H = h^-2 tridiag(-1,2,-1) + diag(f).
 static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<AxisFactor>& out) {
   auto F = std::make_shared<AxisFactor>();
   F->n = n;
   F->L = L;
-  F->ld = round_up(n, kTileF);
-  F->kpad = F->ld;  // square padding: every kernel's tiles stay inside
   const double h = 2.0 * L / (double)(n + 1);
   const double ih2 = 1.0 / (h * h);
   F->ih2 = ih2;
@@ -49,45 +127,68 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
     set_error("tridiagonal eigensolver did not converge");
     return TS_ERR_INVALID;
   }
-  const size_t padded = (size_t)(F->kpad * F->ld);
-  std::vector<double> Qp(padded, 0.0), QTp(padded, 0.0);
+  int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, nullptr);
+  if (rc) return rc;
+  out = F;
+  return TS_OK;
+}
+
+// Q^k SEM axis (eq. (eigen_decomp)): Q diagonalises A = M^{-1/2} S M^{-1/2} + F.
+// sym: factors (Q, Q^T), band of M^{-1/2} S M^{-1/2}, mass roots.
+// phys: T^{-1} = Q^T M^{1/2}, T = M^{-1/2} Q, band of M^{-1} S.
+static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::shared_ptr<AxisFactor>& phys,
+                          std::shared_ptr<AxisFactor>& sym) {
+  SemAxis ax;
+  if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis"); return TS_ERR_INVALID; }
+  const int64_t n = ax.n, w = 2 * k + 1;
+  std::vector<double> ms(n), A((size_t)(n * n), 0.0), bsym((size_t)(n * w), 0.0), bphys((size_t)(n * w), 0.0);
+  for (int64_t i = 0; i < n; ++i) ms[i] = std::sqrt(ax.m[i]);
+  for (int64_t i = 0; i < n; ++i)
+    for (int t = 0; t < w; ++t) {
+      const int64_t j = i - k + t;
+      if (j < 0 || j >= n) continue;
+      const double sij = ax.S[(size_t)(i * w + t)];
+      bsym[(size_t)(i * w + t)] = sij / (ms[i] * ms[j]);
+      bphys[(size_t)(i * w + t)] = sij / ax.m[i];
+      A[(size_t)(i * n + j)] = sij / (ms[i] * ms[j]);
+    }
+  for (int64_t i = 0; i < n; ++i) A[(size_t)(i * n + i)] += f[i];
+  for (int64_t i = 0; i < n; ++i)  // exact symmetry (S is symmetric up to the rounding of its entries)
+    for (int64_t j = 0; j < i; ++j) {
+      const double a = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
+      A[(size_t)(i * n + j)] = A[(size_t)(j * n + i)] = a;
+    }
+  auto S = std::make_shared<AxisFactor>();
+  S->n = n;
+  S->L = L;
+  S->lam_h.resize(n);
+  S->Q_h.resize((size_t)(n * n));
+  if (!dense_sym_eig(n, A, S->lam_h.data(), S->Q_h.data())) {
+    set_error("symmetric eigensolver did not converge");
+    return TS_ERR_INVALID;
+  }
+  S->bw = k;
+  S->m_h = ax.m;
+  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, &ax.m);
+  if (rc) return rc;
+  auto P = std::make_shared<AxisFactor>();
+  P->n = n;
+  P->L = L;
+  P->lam_h = S->lam_h;
+  P->Q_h = S->Q_h;
+  P->bw = k;
+  P->m_h = ax.m;
+  std::vector<double> Fwd((size_t)(n * n)), Bwd((size_t)(n * n));
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = 0; j < n; ++j) {
-      Qp[(size_t)(i * F->ld + j)] = F->Q_h[(size_t)(i * n + j)];
-      QTp[(size_t)(j * F->ld + i)] = F->Q_h[(size_t)(i * n + j)];
+      const double q = S->Q_h[(size_t)(i * n + j)];
+      Fwd[(size_t)(i * n + j)] = ms[i] * q;   // (T^{-1})^T = M^{1/2} Q
+      Bwd[(size_t)(j * n + i)] = q / ms[i];   // T^T = Q^T M^{-1/2}
     }
-  hipError_t e = hipSuccess;
-  e = hipMalloc(&F->lam, sizeof(double) * n);
-  if (e == hipSuccess) e = hipMalloc(&F->f, sizeof(double) * n);
-  if (e == hipSuccess) e = hipMalloc(&F->Q64, sizeof(double) * padded);
-  if (e == hipSuccess) e = hipMalloc(&F->QT64, sizeof(double) * padded);
-  if (e == hipSuccess) e = hipMalloc(&F->Q32, sizeof(float) * padded);
-  if (e == hipSuccess) e = hipMalloc(&F->QT32, sizeof(float) * padded);
-  if (e == hipSuccess) e = hipMalloc(&F->Q16, sizeof(uint16_t) * padded);
-  if (e == hipSuccess) e = hipMalloc(&F->QT16, sizeof(uint16_t) * padded);
-  if (e != hipSuccess) {
-    set_error(std::string("device allocation of factors failed: ") + hipGetErrorString(e));
-    return TS_ERR_NOMEM;
-  }
-  // upload on a private non-blocking stream: setup never waits for other work
-  hipStream_t st = nullptr;
-  e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMemcpyAsync(F->lam, F->lam_h.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(F->f, f, sizeof(double) * n, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(F->Q64, Qp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(F->QT64, QTp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
-  // reduced-precision copies are cast on the device from the FP64 copy
-  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->Q64, F->Q32, (int64_t)padded, st);
-  if (e == hipSuccess) e = launch_cast_f64_to_f32(F->QT64, F->QT32, (int64_t)padded, st);
-  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->Q64, F->Q16, (int64_t)padded, st);
-  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F->QT64, F->QT16, (int64_t)padded, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (st) hipStreamDestroy(st);
-  if (e != hipSuccess) {
-    set_error(std::string("factor upload failed: ") + hipGetErrorString(e));
-    return TS_ERR_DEVICE;
-  }
-  out = F;
+  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, &ax.m);
+  if (rc) return rc;
+  phys = P;
+  sym = S;
   return TS_OK;
 }
 
@@ -177,7 +278,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     pa.tin = src_t;
     pa.tout = dst_t;
     pa.prec = ap.prec;
-    pa.fac = p->ax[k].get();
+    pa.fac = (ap.sym ? p->ax_sym : p->ax)[k].get();
     pa.forward = fwd;
     pa.n = p->n[k];
     pa.P = 1;
@@ -207,7 +308,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
 }
 
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, ExecCtx& c, const int* skip) {
+                       hipStream_t st, ExecCtx& c, const int* skip, bool sym) {
   if (!p || !b || !u) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_F64 && dtype != TS_F32) { set_error("inverse apply needs TS_F64 or TS_F32 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
@@ -226,6 +327,7 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
     sa.epi = Epi::Inv;
     sa.shift = shift;
     sa.skip = skip;
+    sa.sym = sym;
     return run_small_apply(p, sa, st, c);
   }
   void* work = nullptr;
@@ -241,6 +343,7 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
   ap.epi = Epi::Inv;
   ap.shift = shift;
   ap.skip = skip;
+  ap.sym = sym;
   return run_apply(p, ap, st);
 }
 
@@ -349,6 +452,55 @@ ts_plan::~ts_plan() {
   hipFree(Lr);
 }
 
+namespace ts {
+// Eigenvalue bound, scaling axis and its eigenvalue-sum tables (shared by FD
+// and SEM setup).
+static int finish_plan(ts_plan* p) {
+  const int d = p->d;
+  if (p->ax_sym.empty()) p->ax_sym = p->ax;
+  p->lam_min = 0.0;
+  for (int k = 0; k < d; ++k) p->lam_min += p->ax[k]->lam_h[0];
+  // scaling axis: a non-fastest axis balancing the two table lengths
+  p->s = 0;
+  if (d >= 2) {
+    int64_t best = -1;
+    for (int s = 0; s <= d - 2; ++s) {
+      int64_t P = 1, R = 1;
+      for (int m = 0; m < s; ++m) P *= p->n[m];
+      for (int m = s + 1; m < d; ++m) R *= p->n[m];
+      int64_t c = std::max(P, R);
+      if (best < 0 || c < best) { best = c; p->s = s; }
+    }
+  }
+  p->Ps = 1;
+  p->Rs = 1;
+  for (int m = 0; m < p->s; ++m) p->Ps *= p->n[m];
+  for (int m = p->s + 1; m < d; ++m) p->Rs *= p->n[m];
+  // eigenvalue-sum tables of the axes before / after s (FP64, host-built)
+  std::vector<double> Lp(p->Ps), Lr(p->Rs);
+  for (int64_t i = 0; i < p->Ps; ++i) {
+    int64_t idx = i;
+    double s = 0.0;
+    for (int m = p->s - 1; m >= 0; --m) { s += p->ax[m]->lam_h[idx % p->n[m]]; idx /= p->n[m]; }
+    Lp[i] = s;
+  }
+  for (int64_t i = 0; i < p->Rs; ++i) {
+    int64_t idx = i;
+    double s = 0.0;
+    for (int m = d - 1; m > p->s; --m) { s += p->ax[m]->lam_h[idx % p->n[m]]; idx /= p->n[m]; }
+    Lr[i] = s;
+  }
+  hipError_t e = hipMalloc(&p->Lp, sizeof(double) * p->Ps);
+  if (e == hipSuccess) e = hipMalloc(&p->Lr, sizeof(double) * p->Rs);
+  if (e != hipSuccess) { set_error("table allocation failed"); return TS_ERR_NOMEM; }
+  e = hipMemcpy(p->Lp, Lp.data(), sizeof(double) * p->Ps, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->Lr, Lr.data(), sizeof(double) * p->Rs, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { set_error("table upload failed"); return TS_ERR_DEVICE; }
+  return TS_OK;
+}
+
+}  // namespace ts
+
 using namespace ts;
 
 extern "C" {
@@ -392,45 +544,76 @@ int ts_setup(int d, const int64_t* n, double L, const double* const* f, double s
     cache[{n[k], key}] = F;
     p->ax.push_back(F);
   }
-  p->lam_min = 0.0;
-  for (int k = 0; k < d; ++k) p->lam_min += p->ax[k]->lam_h[0];
-  // scaling axis: a non-fastest axis balancing the two table lengths
-  p->s = 0;
-  if (d >= 2) {
-    int64_t best = -1;
-    for (int s = 0; s <= d - 2; ++s) {
-      int64_t P = 1, R = 1;
-      for (int m = 0; m < s; ++m) P *= n[m];
-      for (int m = s + 1; m < d; ++m) R *= n[m];
-      int64_t c = std::max(P, R);
-      if (best < 0 || c < best) { best = c; p->s = s; }
-    }
-  }
-  p->Ps = 1;
-  p->Rs = 1;
-  for (int m = 0; m < p->s; ++m) p->Ps *= n[m];
-  for (int m = p->s + 1; m < d; ++m) p->Rs *= n[m];
-  // eigenvalue-sum tables of the axes before / after s (FP64, host-built)
-  std::vector<double> Lp(p->Ps), Lr(p->Rs);
-  for (int64_t i = 0; i < p->Ps; ++i) {
-    int64_t idx = i;
-    double s = 0.0;
-    for (int m = p->s - 1; m >= 0; --m) { s += p->ax[m]->lam_h[idx % n[m]]; idx /= n[m]; }
-    Lp[i] = s;
-  }
-  for (int64_t i = 0; i < p->Rs; ++i) {
-    int64_t idx = i;
-    double s = 0.0;
-    for (int m = d - 1; m > p->s; --m) { s += p->ax[m]->lam_h[idx % n[m]]; idx /= n[m]; }
-    Lr[i] = s;
-  }
-  hipError_t e = hipMalloc(&p->Lp, sizeof(double) * p->Ps);
-  if (e == hipSuccess) e = hipMalloc(&p->Lr, sizeof(double) * p->Rs);
-  if (e != hipSuccess) { set_error("table allocation failed"); return TS_ERR_NOMEM; }
-  e = hipMemcpy(p->Lp, Lp.data(), sizeof(double) * p->Ps, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(p->Lr, Lr.data(), sizeof(double) * p->Rs, hipMemcpyHostToDevice);
-  if (e != hipSuccess) { set_error("table upload failed"); return TS_ERR_DEVICE; }
+  int rc = finish_plan(p.get());
+  if (rc) return rc;
   *out = p.release();
+  return TS_OK;
+}
+
+int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* const* f, double sigma,
+                 ts_plan** out) {
+  set_error("");
+  if (!out || !cells || !f) { set_error("null argument"); return TS_ERR_INVALID; }
+  *out = nullptr;
+  if (d < 1 || d > TS_MAX_D) { set_error("d must be in [1, 12]"); return TS_ERR_INVALID; }
+  if (k < 1 || k > kMaxSemOrder) { set_error("k must be in [1, 16]"); return TS_ERR_INVALID; }
+  if (!(L > 0.0) || !std::isfinite(L)) { set_error("L must be positive"); return TS_ERR_INVALID; }
+  if (!std::isfinite(sigma)) { set_error("sigma must be finite"); return TS_ERR_INVALID; }
+  int64_t N = 1;
+  for (int a = 0; a < d; ++a) {
+    const int64_t n = (int64_t)k * cells[a] - 1;
+    if (cells[a] < 1 || n < 1 || n > 8192) { set_error("k * cells[a] - 1 must be in [1, 8192]"); return TS_ERR_INVALID; }
+    if (!f[a]) { set_error("f[a] is null"); return TS_ERR_INVALID; }
+    for (int64_t j = 0; j < n; ++j)
+      if (!std::isfinite(f[a][j])) { set_error("f[a] has a non-finite sample"); return TS_ERR_NONFINITE; }
+    N *= n;
+    if (N >= (int64_t(1) << 40)) { set_error("grid too large"); return TS_ERR_INVALID; }
+  }
+  auto p = std::unique_ptr<ts_plan>(new ts_plan());
+  p->d = d;
+  p->N = N;
+  p->L = L;
+  p->sigma = sigma;
+  p->sem_k = k;
+  hipGetDevice(&p->device);
+  std::map<std::pair<int64_t, std::string>, std::pair<std::shared_ptr<AxisFactor>, std::shared_ptr<AxisFactor>>> cache;
+  for (int a = 0; a < d; ++a) {
+    const int64_t n = (int64_t)k * cells[a] - 1;
+    p->n[a] = n;
+    std::string key((const char*)f[a], sizeof(double) * (size_t)n);
+    auto it = cache.find({cells[a], key});
+    if (it == cache.end()) {
+      std::shared_ptr<AxisFactor> P, S;
+      int rc = build_axis_sem(k, cells[a], L, f[a], P, S);
+      if (rc) return rc;
+      it = cache.insert({{cells[a], key}, {P, S}}).first;
+    }
+    p->ax.push_back(it->second.first);
+    p->ax_sym.push_back(it->second.second);
+  }
+  int rc = finish_plan(p.get());
+  if (rc) return rc;
+  *out = p.release();
+  return TS_OK;
+}
+
+int ts_sem_nodes(int k, int64_t cells, double L, double* x) {
+  if (!x) { set_error("null argument"); return TS_ERR_INVALID; }
+  SemAxis ax;
+  if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis (k in [1, 16], cells >= 1, L > 0)"); return TS_ERR_INVALID; }
+  std::memcpy(x, ax.x.data(), sizeof(double) * (size_t)ax.n);
+  return TS_OK;
+}
+
+int ts_mass(const ts_plan* plan, int axis, double* out) {
+  if (!plan || !out || axis < 0 || axis >= plan->d) { set_error("bad argument"); return TS_ERR_INVALID; }
+  const auto& F = *plan->ax[axis];
+  if (plan->sem_k) {
+    std::memcpy(out, F.m_h.data(), sizeof(double) * (size_t)F.n);
+  } else {
+    const double h = 2.0 * plan->L / (double)(F.n + 1);
+    for (int64_t i = 0; i < F.n; ++i) out[i] = h;
+  }
   return TS_OK;
 }
 
@@ -476,6 +659,15 @@ int ts_eigvecs(const ts_plan* plan, int axis, double* out) {
 int ts_tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q) {
   if (n < 1 || !diag || !lam || !Q || (n > 1 && !off)) { set_error("bad argument"); return TS_ERR_INVALID; }
   if (!tridiag_eig(n, diag, off, lam, Q)) { set_error("QL iteration limit reached"); return TS_ERR_NOCONV; }
+  return TS_OK;
+}
+
+int ts_sym_eig(int64_t n, const double* A, double* lam, double* Q) {
+  if (n < 1 || !A || !lam || !Q) { set_error("bad argument"); return TS_ERR_INVALID; }
+  std::vector<double> W(A, A + n * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < i; ++j) W[(size_t)(i * n + j)] = W[(size_t)(j * n + i)] = 0.5 * (A[i * n + j] + A[j * n + i]);
+  if (!dense_sym_eig(n, W, lam, Q)) { set_error("QL iteration limit reached"); return TS_ERR_NOCONV; }
   return TS_OK;
 }
 

@@ -16,6 +16,7 @@ struct ApplyParams {
   double shift = 0.0;
   const int* skip = nullptr;
   const double2* phase = nullptr;  // Exp: tables Ep | Er | es of the scaling axis
+  bool sym = false;                // use the plan's orthogonal (solver) factors
 };
 
 int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st);
@@ -25,9 +26,11 @@ size_t need_inverse(const ts_plan* p, int slot);
 size_t need_exp(const ts_plan* p, int slot);
 
 // u = (H1 + shift)^{-1} b with the context's scratch.  skip: optional device
-// flag; when set, every kernel of the apply returns at once.
+// flag; when set, every kernel of the apply returns at once.  sym: apply the
+// symmetric form's inverse (the solvers' variables; differs from the public
+// apply only for SEM plans).
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, ExecCtx& c, const int* skip);
+                       hipStream_t st, ExecCtx& c, const int* skip, bool sym = false);
 // psi_out = exp(-i tau H1) psi_in.
 int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
                    hipStream_t st, ExecCtx& c);
@@ -44,7 +47,8 @@ int apply_exp_phased(ts_plan* p, double tau, void* psi, int dtype, int prec, con
 
 // Solvers (solvers.cpp) on an explicit context.
 int pcg_run(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x,
-            double rtol, int maxit, int prec, int* iters, double* relres, hipStream_t st, ExecCtx& c);
+            double rtol, int maxit, int prec, int* iters, double* relres, hipStream_t st, ExecCtx& c,
+            bool scale_io = true);
 int refine_run(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, int* iters,
                double* relres, hipStream_t st, ExecCtx& c);
 int split_run(ts_plan* p, const void* V2, void* psi, double dt, int nsteps, int scheme, int dtype, int prec,

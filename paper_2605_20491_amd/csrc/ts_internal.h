@@ -25,17 +25,20 @@ constexpr int kTileK = 32;    // K padding granularity (covers BK of every kerne
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
-// Per-axis eigen-factors of one distinct (n, L, f_k) on the device.
-// Matrices are stored k-major and zero-padded to [kpad][ld]:
-//   Q  : Q[i][j]   = component i of eigenvector j      (used by forward passes)
-//   QT : QT[i][j]  = Q[j][i]                           (used by backward passes)
-// so an MFMA tile of either operand role reads whole padded rows.
+// Per-axis eigen-factors of one distinct axis operator on the device.  A pass
+// computes y_j = sum_i W[i][j] x_i with W stored k-major and zero-padded to
+// [kpad][ld], so an MFMA tile of either operand role reads whole padded rows:
+//   Q  : forward  W = (T^{-1})^T   (FD: W[i][j] = Q[i][j])
+//   QT : backward W = T^T          (FD: W[i][j] = Q[j][i])
+// For Q^k SEM T = M^{-1/2} Q; a plan holds these mass-scaled factors for its
+// public applies and a second, orthogonal set (T = Q) for the solvers, which
+// work with the symmetric operator M^{-1/2} S M^{-1/2} + F.
 struct AxisFactor {
   int64_t n = 0, ld = 0, kpad = 0;
   double L = 0;
   std::vector<double> lam_h;  // ascending
-  std::vector<double> Q_h;    // row-major n x n
-  double ih2 = 0;             // h^-2, h = 2L/(n+1)
+  std::vector<double> Q_h;    // row-major n x n, orthonormal eigenvectors of the symmetric form
+  double ih2 = 0;             // FD: h^-2, h = 2L/(n+1)
   double* lam = nullptr;      // device [n]
   double* f = nullptr;        // device [n]: the samples f_k(x_j)
   double* Q64 = nullptr;      // device [kpad][ld]
@@ -44,6 +47,12 @@ struct AxisFactor {
   float* QT32 = nullptr;
   uint16_t* Q16 = nullptr;    // bf16 bit patterns, same padded layout
   uint16_t* QT16 = nullptr;
+  // SEM only: operator band [n][2 bw + 1] (entry (i, i - bw + t)), M^{1/2} and M^{-1/2}
+  int bw = 0;
+  double* band = nullptr;
+  double* msq = nullptr;
+  double* imsq = nullptr;
+  std::vector<double> m_h;    // lumped mass
   ~AxisFactor();
 };
 
@@ -125,7 +134,9 @@ struct ts_plan {
   int64_t N = 0;
   double L = 0, sigma = 0;
   int device = 0;
-  std::vector<std::shared_ptr<ts::AxisFactor>> ax;
+  std::vector<std::shared_ptr<ts::AxisFactor>> ax;      // factors of the public applies
+  std::vector<std::shared_ptr<ts::AxisFactor>> ax_sym;  // orthogonal factors of the solvers (FD: = ax)
+  int sem_k = 0;               // 0: FD; k >= 1: Q^k SEM
   int s = 0;                   // axis whose forward pass carries the scaling
   int64_t Ps = 1, Rs = 1;      // products of the extents before / after axis s
   double* Lp = nullptr;        // device FP64 [Ps]

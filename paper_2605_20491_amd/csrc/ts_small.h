@@ -72,6 +72,7 @@ struct SmallApply {
   double th_pre = 0.0, th_post = 0.0;
   bool pre = false, post = false;
   const int* skip = nullptr;
+  bool sym = false;  // the plan's orthogonal (solver) factors
 };
 int run_small_apply(ts_plan* p, const SmallApply& s, hipStream_t st, ExecCtx& c);
 // Bytes of the diagonal tables of one grouped apply.

@@ -31,8 +31,10 @@ class Task {
 // Run a task to completion on `st`, waiting on an event between units.
 int run_blocking(Task& t, hipStream_t st);
 
+// scale_io: for SEM plans, f and x are in the caller's variables and are
+// moved to and from the symmetric form's variables M^{1/2} x.
 std::unique_ptr<Task> make_pcg_task(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f,
-                                    double* x, double rtol, int maxit, int prec, ExecCtx& c);
+                                    double* x, double rtol, int maxit, int prec, ExecCtx& c, bool scale_io = true);
 std::unique_ptr<Task> make_refine_task(ts_plan* p, const double* f, double* u, int inner, double rtol,
                                        int maxit, ExecCtx& c);
 std::unique_ptr<Task> make_inverse_task(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,

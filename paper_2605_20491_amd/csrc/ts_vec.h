@@ -29,9 +29,17 @@ struct StencilArgs {
   StDot dot = StDot::None;
   double* partial = nullptr;       // [kRedBlocks] when dot != None
   const int* skip = nullptr;
+  // Q^k SEM: per-axis operator bands [n_k][2 bw + 1] (entry (i, i - bw + t))
+  // replace the h^-2 (-1, 2, -1) stencil when bw > 0
+  int bw = 0;
+  const double* band[TS_MAX_D] = {};
 };
 
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st);
+
+// y = x * prod_k w_k(i_k) pointwise (x may equal y); w_k device vectors of n_k.
+hipError_t launch_axis_scale(const double* x, double* y, int d, const int64_t* n, const double* const* w,
+                             hipStream_t st);
 
 // Device scalar block used by the solvers (all FP64 except the int flags).
 struct SolverScalars {

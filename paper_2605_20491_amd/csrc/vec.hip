@@ -94,6 +94,66 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a) {
   }
 }
 
+// Banded per-axis operator of Q^k SEM: sum_k (I x .. x B_k x .. x I) u plus
+// the diagonal (sum_k f_k + V2 + s) u, one output point per thread.  The
+// 2 bw + 1 neighbours of every axis are read in place (the fastest axis from
+// the same cache lines, the others from L2 / the last-level cache).
+template <int MODE, int DOT>
+__global__ __launch_bounds__(RT) void k_band(StencilArgs a) {
+  if (a.skip && *a.skip) {
+    if (DOT && threadIdx.x == 0 && blockIdx.x < kRedBlocks) a.partial[blockIdx.x] = 0.0;
+    return;
+  }
+  const int w = 2 * a.bw + 1;
+  double dsum = 0.0;
+  for (int64_t idx = blockIdx.x * (int64_t)RT + threadIdx.x; idx < a.N; idx += (int64_t)gridDim.x * RT) {
+    double acc = 0.0;
+    double diag = a.s + (a.V2 ? a.V2[idx] : 0.0);
+    int64_t rem = idx;
+    for (int k = a.d - 1; k >= 0; --k) {
+      const int64_t nk = a.n[k];
+      const int64_t i = rem % nk;
+      rem /= nk;
+      diag += a.f[k][i];
+      const double* row = a.band[k] + i * w;
+      const int64_t st = a.stride[k];
+      const int64_t j0 = i - a.bw;
+      for (int t = 0; t < w; ++t) {
+        const int64_t j = j0 + t;
+        if (j >= 0 && j < nk) acc += row[t] * a.u[idx + (j - i) * st];
+      }
+    }
+    const double uc = a.u[idx];
+    double v = acc + diag * uc;
+    if (MODE == (int)StOut::FminusAx) v = a.rhs[idx] - v;
+    a.out[idx] = v;
+    if (DOT == (int)StDot::UdotOut) dsum += uc * v;
+    if (DOT == (int)StDot::OutdotOut) dsum += v * v;
+  }
+  if (DOT) {
+    double s = block_sum(dsum);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+  }
+}
+
+struct ScaleArgs {
+  int d;
+  int64_t n[TS_MAX_D];
+  const double* w[TS_MAX_D];
+};
+
+__global__ __launch_bounds__(RT) void k_axis_scale(const double* x, double* y, int64_t N, ScaleArgs a) {
+  for (int64_t idx = blockIdx.x * (int64_t)RT + threadIdx.x; idx < N; idx += (int64_t)gridDim.x * RT) {
+    double s = 1.0;
+    int64_t rem = idx;
+    for (int k = a.d - 1; k >= 0; --k) {
+      s *= a.w[k][rem % a.n[k]];
+      rem /= a.n[k];
+    }
+    y[idx] = x[idx] * s;
+  }
+}
+
 __global__ __launch_bounds__(RT) void k_dot(const double* x, const double* y, int64_t n, double* partial,
                                             const double* w, double* partial2, const int* skip) {
   if (skip && *skip) {
@@ -235,6 +295,16 @@ inline int red_grid(int64_t n) { (void)n; return kRedBlocks; }
 
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
+  if (a.bw > 0) {
+    const unsigned g = a.dot != StDot::None ? kRedBlocks
+                                            : (unsigned)std::min<int64_t>((a.N + RT - 1) / RT, 1 << 20);
+    const int m = (int)a.mode, dt = (int)a.dot;
+#define TS_BD(M, D) \
+  if (m == M && dt == D) { hipLaunchKernelGGL((k_band<M, D>), dim3(g), dim3(RT), 0, st, a); return hipGetLastError(); }
+    TS_BD(0, 0) TS_BD(0, 1) TS_BD(0, 2) TS_BD(1, 0) TS_BD(1, 1) TS_BD(1, 2)
+#undef TS_BD
+    return hipErrorInvalidValue;
+  }
   const int64_t work = (a.N / a.n[0]) * ((a.n[0] + kMarch - 1) / kMarch);
   unsigned grid;
   if (a.dot != StDot::None) grid = kRedBlocks;
@@ -245,6 +315,22 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
   TS_ST(0, 0) TS_ST(0, 1) TS_ST(0, 2) TS_ST(1, 0) TS_ST(1, 1) TS_ST(1, 2)
 #undef TS_ST
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_axis_scale(const double* x, double* y, int d, const int64_t* n, const double* const* w,
+                             hipStream_t st) {
+  ScaleArgs a;
+  a.d = d;
+  int64_t N = 1;
+  for (int k = 0; k < d; ++k) {
+    a.n[k] = n[k];
+    a.w[k] = w[k];
+    N *= n[k];
+  }
+  if (N <= 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>((N + RT - 1) / RT, 1 << 20);
+  hipLaunchKernelGGL(k_axis_scale, dim3(g), dim3(RT), 0, st, x, y, N, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partial, const double* w,

@@ -102,3 +102,44 @@ def test_gauss_legendre_rejects_bad_m():
     for M in (0, 65):
         with pytest.raises(ts.TSError):
             ts.ts_gauss_legendre(M)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 6, 10, 16])
+def test_sem_nodes_match_oracle(k):
+    """ts_sem_nodes (Newton on P_k') against the oracle's nodes (numpy's
+    Legendre roots), on meshes of 1, 3 and 7 elements."""
+    for cells in (1, 3, 7):
+        if k * cells - 1 < 1:
+            continue
+        a = ts.ts_sem_nodes(k, cells, 1.7)
+        b = oracle.sem_nodes(k, cells, 1.7)
+        assert np.max(np.abs(a - b)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 150])
+def test_dense_symmetric_eig(n):
+    """ts_sym_eig (Householder + QL) against LAPACK's eigh on random symmetric
+    matrices: eigenvalues, orthonormality, residual."""
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    lam, Q = ts.ts_sym_eig(A)
+    ref = np.linalg.eigvalsh(A)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(lam - ref)) < 1e-13 * scale * max(1, np.sqrt(n))
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) < 1e-13 * max(1, n)
+    assert np.max(np.abs(A @ Q - Q * lam)) < 1e-13 * scale * max(1, n)
+
+
+@pytest.mark.parametrize("k,cells", [(2, 20), (6, 9), (10, 5)])
+def test_dense_symmetric_eig_on_sem_axis(k, cells):
+    """The SEM symmetric form M^{-1/2} S M^{-1/2} + F from the oracle's assembly:
+    eigenvalues from ts_sym_eig against the oracle's Jacobi (relative to the
+    largest eigenvalue, which grows like k^4 / h^2)."""
+    L = 4.0
+    x, m, S = oracle.sem_axis(k, cells, L)
+    sq = np.sqrt(m)
+    A = S / np.outer(sq, sq) + np.diag(W.f_harmonic(0, L, x=x))
+    lam, Q = ts.ts_sym_eig(A)
+    w, _ = oracle.jacobi_eigh(0.5 * (A + A.T))
+    assert np.max(np.abs(lam - w)) < 1e-13 * np.max(np.abs(w)) * np.sqrt(len(w))
