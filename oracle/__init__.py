@@ -602,3 +602,91 @@ def qhop_propagate(plan: Plan, V2, psi0, dt, nsteps, M: int, yoshida: bool = Fal
     for _ in range(int(nsteps)):
         psi = magnus2_step(plan, V2, psi, dt, M) if yoshida else qhop_step(plan, V2, psi, dt, M)
     return psi
+
+
+# --------------------------------------------------------------------------
+# GPE ground state by Riemannian gradient flows (Sec. 4.2, 4.3)
+# --------------------------------------------------------------------------
+
+def l2_weights(plan: Plan) -> np.ndarray:
+    """Quadrature weights of the discrete L^2 inner product on the grid:
+    prod_k m_k (Gauss-Lobatto mass) for SEM plans, h^d for FD plans."""
+    if plan.sem_k:
+        return _mass_root(plan, 1.0)
+    return np.full(plan.shape, float(np.prod(plan.h)))
+
+
+def gpe_energy(plan_lap: Plan, V, beta: float, u: np.ndarray) -> float:
+    """eq. (gpe_energy): E(u) = 1/2 [(grad u, grad u) + (V u, u)] + beta/4 (u^4, 1),
+    with (grad u, grad u) = (-Delta_h u, u) and the plan's L^2 weights.
+    plan_lap discretises -Delta alone (f = 0); V is the full potential on the grid."""
+    w = l2_weights(plan_lap)
+    lap_u = operator_apply(plan_lap, u, None, 0.0)
+    return float(0.5 * np.sum(w * u * lap_u) + 0.5 * np.sum(w * V * u * u) + 0.25 * beta * np.sum(w * u**4))
+
+
+def gpe_eigenvalue(plan_lap: Plan, V, beta: float, u: np.ndarray) -> float:
+    """lambda = ((-Delta + V + beta u^2) u, u) for ||u||_{L^2} = 1 (eq. (gpe))."""
+    w = l2_weights(plan_lap)
+    Hu = operator_apply(plan_lap, u, V + beta * u * u, 0.0)
+    return float(np.sum(w * u * Hu))
+
+
+def _riemannian_step(u, grad_g, normal_g, tau, w):
+    """eq. (riemannian_update): project the metric gradient G^{-1} E'(u) onto the
+    tangent space {v : (u, v) = 0} of the L^2 sphere along the metric normal
+    G^{-1} u, step by tau and renormalise in L^2."""
+    coef = np.sum(w * u * grad_g) / np.sum(w * u * normal_g)
+    r = grad_g - coef * normal_g
+    v = u - tau * r
+    return v / np.sqrt(np.sum(w * v * v))
+
+
+def h1_flow_step(plan_lap: Plan, V, beta: float, alpha: float, tau: float, u: np.ndarray) -> np.ndarray:
+    """Modified H^1 flow, metric eq. (h1_metric) with G = -Delta + alpha: the two
+    solves G^{-1} E'(u) and G^{-1} u, E'(u) = (-Delta + V + beta u^2) u."""
+    Eprime = operator_apply(plan_lap, u, V + beta * u * u, 0.0)
+    grad_g = apply_inverse(plan_lap, Eprime, alpha)
+    normal_g = apply_inverse(plan_lap, u, alpha)
+    return _riemannian_step(u, grad_g, normal_g, tau, l2_weights(plan_lap))
+
+
+def au_flow_step(plan_v1: Plan, V2, beta: float, tau: float, u: np.ndarray, pcg_rtol: float = 1e-13):
+    """a_u flow, metric eq. (au_metric) with G_u = -Delta + V + beta u^2: then
+    G_u^{-1} E'(u) = u, and the normal G_u^{-1} u is one PCG solve with the
+    preconditioner (-Delta + V1)^{-1} (plan_v1 holds V1; V2 the rest of V).
+    Returns (u_new, pcg iterations)."""
+    extra = beta * u * u if V2 is None else V2 + beta * u * u
+    res = pcg(plan_v1, extra, 0.0, u, rtol=pcg_rtol)
+    return _riemannian_step(u, u, res.x, tau, l2_weights(plan_v1)), res.iters
+
+
+@dataclass
+class GPEResult:
+    u: np.ndarray
+    energy: list
+    eigenvalue: float
+    iters: int
+
+
+def gpe_ground_state(plan_lap: Plan, V, beta: float, u0: np.ndarray, method: str = "h1", alpha: float = 20.0,
+                     tau: float = 0.1, tol: float = 1e-12, maxit: int = 2000, plan_v1: Plan = None,
+                     V2=None) -> GPEResult:
+    """Iterate a flow until |E_k - E_{k-1}| <= tol |E_k|.  The start is
+    renormalised in L^2.  method 'h1' uses plan_lap (f = 0); 'au' uses plan_v1
+    (f = V1) and V2 = V - V1 (None when V is separable)."""
+    w = l2_weights(plan_lap)
+    u = np.array(u0, dtype=np.float64).reshape(plan_lap.shape)
+    u = u / np.sqrt(np.sum(w * u * u))
+    E = [gpe_energy(plan_lap, V, beta, u)]
+    k = 0
+    while k < maxit:
+        if method == "h1":
+            u = h1_flow_step(plan_lap, V, beta, alpha, tau, u)
+        else:
+            u, _ = au_flow_step(plan_v1, V2, beta, tau, u)
+        k += 1
+        E.append(gpe_energy(plan_lap, V, beta, u))
+        if abs(E[-1] - E[-2]) <= tol * abs(E[-1]):
+            break
+    return GPEResult(u=u, energy=E, eigenvalue=gpe_eigenvalue(plan_lap, V, beta, u), iters=k)
