@@ -245,6 +245,41 @@ int ts_qhop_step(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps
  * 1..64 or a null pointer). */
 int ts_gauss_legendre(int M, double* nodes, double* weights);
 
+/* ------------------------------------------------------- GPE flows -- */
+
+/* Ground state of the GPE eq. (gpe), -Delta u + V u + beta u^3 = lambda u
+ * with ||u||_{L^2} = 1, by the modified H^1 Riemannian gradient flow
+ * (Sec. 4.3, eq. (riemannian_update), metric eq. (h1_metric)):
+ *   R(u) = G^{-1} E'(u) - [(u, G^{-1} E'(u)) / (u, G^{-1} u)] G^{-1} u,
+ *   u <- (u - tau R(u)) / ||u - tau R(u)||,   G = -Delta + alpha,
+ * E'(u) = (-Delta + V + beta u^2) u; two applies of (-Delta + alpha)^{-1} per
+ * step.  Inner products are the grid's L^2 sums (weights prod_k m_k, see
+ * ts_mass).  Stops when |E_k - E_{k-1}| <= tol |E_k|, E of eq. (gpe_energy).
+ *   plan        : plan of -Delta alone (f = 0), FD or SEM; its sigma is unused
+ *   V           : device FP64, the whole potential on the grid (may be NULL)
+ *   u           : device FP64; in: start (normalised first), out: ground state
+ *   maxit       : step limit; energy_hist: HOST array of maxit + 1 doubles or NULL
+ *   iters       : steps taken; eigenvalue: lambda = (u, E'(u)); energy: E (host, may be NULL)
+ * All vectors, sums and decisions stay on the device; the host polls every
+ * few steps.  Errors: TS_ERR_INVALID, TS_ERR_NOT_SPD, TS_ERR_NOCONV (limit
+ * reached; u holds the last iterate), TS_ERR_NONFINITE, TS_ERR_NOMEM. */
+int ts_gpe_h1_flow(ts_plan* plan, const double* V, double beta, double alpha, double tau, double* u, int maxit,
+                   double tol, double* energy_hist, int* iters, double* eigenvalue, double* energy,
+                   void* hip_stream);
+
+/* The a_u Riemannian flow (Sec. 4.3, metric eq. (au_metric)): G = G_u =
+ * -Delta + V + beta u^2, so G^{-1} E'(u) = u and each step solves G_u z = u
+ * by PCG with the preconditioner (-Delta + V1)^{-1} (ts_pcg_solve's solver,
+ * warm-started from the previous z, in `precond` precision).
+ *   plan          : plan of -Delta + V1 (sigma unused)
+ *   V2            : device FP64, V - V1 on the grid, or NULL
+ *   pcg_rtol/maxit: inner PCG tolerance and limit
+ *   linear_iters  : total PCG iterations (host, may be NULL)
+ * Other arguments as ts_gpe_h1_flow.  Errors: as ts_gpe_h1_flow and PCG's. */
+int ts_gpe_au_flow(ts_plan* plan, const double* V2, double beta, double tau, double* u, int maxit, double tol,
+                   double pcg_rtol, int pcg_maxit, int precond, double* energy_hist, int* iters,
+                   int* linear_iters, double* eigenvalue, double* energy, void* hip_stream);
+
 /* ---------------------------------------------------------- operators -- */
 
 /* out = (H1 + diag(V2) + s I) u by the (2d+1)-point stencil, FP64, zero ghost

@@ -68,6 +68,10 @@ def lib():
                              ctypes.c_int, ctypes.c_int, _vp],
             "ts_gauss_legendre": [ctypes.c_int, _dp, _dp],
             "ts_operator_apply": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp],
+            "ts_gpe_h1_flow": [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int,
+                               ctypes.c_double, _dp, _ip, _dp, _dp, _vp],
+            "ts_gpe_au_flow": [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _ip, _ip, _dp, _dp, _vp],
             "ts_eigvals": [_vp, ctypes.c_int, _dp],
             "ts_eigvecs": [_vp, ctypes.c_int, _dp],
             "ts_workspace_bytes": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
@@ -300,6 +304,39 @@ def ts_gauss_legendre(M: int):
     nodes, weights = np.empty(max(int(M), 1)), np.empty(max(int(M), 1))
     _check(lib().ts_gauss_legendre(int(M), _dptr(nodes), _dptr(weights)), "ts_gauss_legendre")
     return nodes, weights
+
+
+class GpeResult:
+    def __init__(self, u, energy, eigenvalue, iters, history, linear_iters=None, status=0):
+        self.u, self.energy, self.eigenvalue, self.iters = u, energy, eigenvalue, iters
+        self.history, self.linear_iters, self.status = history, linear_iters, status
+
+
+def ts_gpe_h1_flow(plan: Plan, V, beta: float, u, alpha: float = 20.0, tau: float = 0.1, maxit: int = 1000,
+                   tol: float = 1e-12, stream=None, raise_on_noconv=True) -> GpeResult:
+    hist = np.zeros(int(maxit) + 1)
+    it, lam, E = ctypes.c_int(0), ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().ts_gpe_h1_flow(plan.handle, _dev(V, plan, "V"), float(beta), float(alpha), float(tau),
+                              _dev(u, plan, "u"), int(maxit), float(tol), _dptr(hist), ctypes.byref(it),
+                              ctypes.byref(lam), ctypes.byref(E), _stream(stream))
+    if not (rc == TS_ERR_NOCONV and not raise_on_noconv):
+        _check(rc, "ts_gpe_h1_flow")
+    return GpeResult(u, E.value, lam.value, it.value, hist[: it.value + 1].copy(), status=rc)
+
+
+def ts_gpe_au_flow(plan: Plan, V2, beta: float, u, tau: float = 1.0, maxit: int = 500, tol: float = 1e-12,
+                   pcg_rtol: float = 1e-12, pcg_maxit: int = 500, precond="fp64", stream=None,
+                   raise_on_noconv=True) -> GpeResult:
+    hist = np.zeros(int(maxit) + 1)
+    it, lin = ctypes.c_int(0), ctypes.c_int(0)
+    lam, E = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    rc = lib().ts_gpe_au_flow(plan.handle, _dev(V2, plan, "V2"), float(beta), float(tau), _dev(u, plan, "u"),
+                              int(maxit), float(tol), float(pcg_rtol), int(pcg_maxit), _prec(precond),
+                              _dptr(hist), ctypes.byref(it), ctypes.byref(lin), ctypes.byref(lam),
+                              ctypes.byref(E), _stream(stream))
+    if not (rc == TS_ERR_NOCONV and not raise_on_noconv):
+        _check(rc, "ts_gpe_au_flow")
+    return GpeResult(u, E.value, lam.value, it.value, hist[: it.value + 1].copy(), lin.value, rc)
 
 
 def ts_operator_apply(plan: Plan, V2, s: float, u, out=None, stream=None):

@@ -30,6 +30,7 @@ AxisFactor::~AxisFactor() {
   hipFree(Q16);
   hipFree(QT16);
   hipFree(band);
+  hipFree(mass);
   hipFree(msq);
   hipFree(imsq);
 }
@@ -38,9 +39,10 @@ namespace {
 
 // Upload one factor set.  Fwd and Bwd are row-major n x n with the pass
 // convention y_j = sum_i W[i][j] x_i; they are zero-padded to [kpad][ld].
-// band (n * (2 bw + 1) entries) and the mass roots are optional.
+// m: the axis's L^2 weights; band (n * (2 bw + 1) entries) and the mass
+// roots (roots = true) are for SEM.
 int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd, const std::vector<double>& Bwd,
-                  const std::vector<double>* band, const std::vector<double>* m) {
+                  const std::vector<double>* band, const std::vector<double>& m, bool roots) {
   const int64_t n = F.n;
   F.ld = round_up(n, kTileF);
   F.kpad = F.ld;  // square padding: every kernel's tiles stay inside
@@ -52,11 +54,11 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
       QTp[(size_t)(i * F.ld + j)] = Bwd[(size_t)(i * n + j)];
     }
   std::vector<double> ms, ims;
-  if (m) {
+  if (roots) {
     ms.resize(n);
     ims.resize(n);
     for (int64_t i = 0; i < n; ++i) {
-      ms[i] = std::sqrt((*m)[i]);
+      ms[i] = std::sqrt(m[i]);
       ims[i] = 1.0 / ms[i];
     }
   }
@@ -70,8 +72,9 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
   if (e == hipSuccess) e = hipMalloc(&F.Q16, sizeof(uint16_t) * padded);
   if (e == hipSuccess) e = hipMalloc(&F.QT16, sizeof(uint16_t) * padded);
   if (e == hipSuccess && band) e = hipMalloc(&F.band, sizeof(double) * band->size());
-  if (e == hipSuccess && m) e = hipMalloc(&F.msq, sizeof(double) * n);
-  if (e == hipSuccess && m) e = hipMalloc(&F.imsq, sizeof(double) * n);
+  if (e == hipSuccess) e = hipMalloc(&F.mass, sizeof(double) * n);
+  if (e == hipSuccess && roots) e = hipMalloc(&F.msq, sizeof(double) * n);
+  if (e == hipSuccess && roots) e = hipMalloc(&F.imsq, sizeof(double) * n);
   if (e != hipSuccess) {
     set_error(std::string("device allocation of factors failed: ") + hipGetErrorString(e));
     return TS_ERR_NOMEM;
@@ -85,8 +88,9 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
   if (e == hipSuccess) e = hipMemcpyAsync(F.QT64, QTp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && band)
     e = hipMemcpyAsync(F.band, band->data(), sizeof(double) * band->size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && m) e = hipMemcpyAsync(F.msq, ms.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && m) e = hipMemcpyAsync(F.imsq, ims.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.mass, m.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && roots) e = hipMemcpyAsync(F.msq, ms.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && roots) e = hipMemcpyAsync(F.imsq, ims.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
   // reduced-precision copies are cast on the device from the FP64 copy
   if (e == hipSuccess) e = launch_cast_f64_to_f32(F.Q64, F.Q32, (int64_t)padded, st);
   if (e == hipSuccess) e = launch_cast_f64_to_f32(F.QT64, F.QT32, (int64_t)padded, st);
@@ -127,7 +131,7 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
     set_error("tridiagonal eigensolver did not converge");
     return TS_ERR_INVALID;
   }
-  int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, nullptr);
+  int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, std::vector<double>(n, h), false);
   if (rc) return rc;
   out = F;
   return TS_OK;
@@ -169,7 +173,7 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
   }
   S->bw = k;
   S->m_h = ax.m;
-  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, &ax.m);
+  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, ax.m, true);
   if (rc) return rc;
   auto P = std::make_shared<AxisFactor>();
   P->n = n;
@@ -185,7 +189,7 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
       Fwd[(size_t)(i * n + j)] = ms[i] * q;   // (T^{-1})^T = M^{1/2} Q
       Bwd[(size_t)(j * n + i)] = q / ms[i];   // T^T = Q^T M^{-1/2}
     }
-  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, &ax.m);
+  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, ax.m, true);
   if (rc) return rc;
   phys = P;
   sym = S;

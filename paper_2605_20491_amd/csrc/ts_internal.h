@@ -47,6 +47,7 @@ struct AxisFactor {
   float* QT32 = nullptr;
   uint16_t* Q16 = nullptr;    // bf16 bit patterns, same padded layout
   uint16_t* QT16 = nullptr;
+  double* mass = nullptr;     // device [n]: L^2 quadrature weights (FD: h; SEM: lumped mass)
   // SEM only: operator band [n][2 bw + 1] (entry (i, i - bw + t)), M^{1/2} and M^{-1/2}
   int bw = 0;
   double* band = nullptr;

@@ -8,33 +8,13 @@
 // index order and takes the solver decision (alpha, beta, convergence) on the
 // device.  Results are bitwise reproducible from run to run.
 #include "ts_internal.h"
+#include "ts_reduce.h"
 #include "ts_vec.h"
 
 namespace ts {
 namespace {
 
-constexpr int RT = 256;          // threads per block of the vector kernels
 constexpr int kMarch = 32;       // stencil: points per thread along axis 0
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-  return v;
-}
-
-// Sum over the block; the result is valid in thread 0.
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double sh[RT / 64];
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < RT / 64; ++i) s += sh[i];
-  return s;
-}
 
 // Stencil: each thread owns one index r of the faster axes (1..d-1) and a run
 // of kMarch consecutive points along axis 0, keeping the axis-0 neighbours in
