@@ -156,6 +156,7 @@ class Plan:
     sem_k: int = 0
     m: list = field(default_factory=list)
     K: list = field(default_factory=list)
+    x: list = field(default_factory=list)   # grid nodes of each axis
 
     @property
     def d(self):
@@ -180,6 +181,7 @@ def make_plan(shape, L, f_list) -> Plan:
         p.h.append(grid_spacing(n, L))
         p.Q.append(V)
         p.lam.append(w)
+        p.x.append(-L + grid_spacing(n, L) * np.arange(1, n + 1))
     return p
 
 
@@ -261,6 +263,7 @@ def make_plan_sem(k: int, cells, L, f_list) -> Plan:
         p.lam.append(w)
         p.m.append(m)
         p.K.append(np.ascontiguousarray(S / m[:, None]))
+        p.x.append(x)
     return p
 
 
@@ -495,13 +498,14 @@ class InvIterResult:
 
 
 def inverse_iteration(plan: Plan, V2, shift: float, steps: int = 20, u0=None,
-                      pcg_rtol: float = 1e-13, maxit: int = 500) -> InvIterResult:
+                      pcg_rtol: float = 1e-13, maxit: int = 500, lam_tol: float = 0.0) -> InvIterResult:
     """Shifted inverse iteration for the lowest eigenpair of H = H1 + diag V2.
 
     Each step solves (H - shift) w = u by PCG preconditioned with
     (H1 - shift)^{-1}, warm-started from the previous step's solution w;
     then u <- w / ||w|| and lambda <- <u, H u> (norm and inner product of
-    ``inner``).
+    ``inner``).  With lam_tol > 0 the iteration stops early once
+    |lambda_k - lambda_{k-1}| <= lam_tol |lambda_k|.
     """
     u = separable_ground_state(plan) if u0 is None else np.array(u0, dtype=np.float64)
     u = u / norm(plan, u)
@@ -514,7 +518,58 @@ def inverse_iteration(plan: Plan, V2, shift: float, steps: int = 20, u0=None,
         its.append(res.iters)
         u = w / norm(plan, w)
         lam.append(inner(plan, u, operator_apply(plan, u, V2, 0.0)))
+        if lam_tol > 0 and abs(lam[-1] - lam[-2]) <= lam_tol * abs(lam[-1]):
+            break
     return InvIterResult(u=u, lam=lam, pcg_iters=its)
+
+
+def interpolate(coarse: Plan, fine: Plan, u: np.ndarray) -> np.ndarray:
+    """Tensor-product linear interpolation from the nodes of `coarse` to those
+    of `fine` (Sec. 5.3.1), with the Dirichlet zeros at -L and L; one axis at a
+    time with numpy's interp."""
+    out = np.asarray(u, dtype=np.float64).reshape(coarse.shape)
+    L = coarse.L
+    for k in range(coarse.d):
+        xc = np.concatenate([[-L], coarse.x[k], [L]])
+        xf = fine.x[k]
+        moved = np.moveaxis(out, k, -1)
+        flat = moved.reshape(-1, moved.shape[-1])
+        res = np.empty((flat.shape[0], xf.size))
+        for r in range(flat.shape[0]):
+            res[r] = np.interp(xf, xc, np.concatenate([[0.0], flat[r], [0.0]]))
+        out = np.moveaxis(res.reshape(moved.shape[:-1] + (xf.size,)), -1, k)
+    return np.ascontiguousarray(out)
+
+
+@dataclass
+class MultilevelResult:
+    u: np.ndarray
+    lam: float
+    steps: list        # inverse-iteration steps per level
+    pcg_iters: list    # PCG iterations per level (sum over its steps)
+    lam_levels: list   # final lambda of each level
+
+
+def multilevel_inverse_iteration(levels, lam_tol: float = 1e-13, max_steps: int = 100,
+                                 pcg_rtol: float = 1e-12, maxit: int = 500) -> MultilevelResult:
+    """Multi-level shifted inverse iteration (Sec. 5.3.1): `levels` is a list of
+    (plan, V2, shift) from coarse to fine.  The first level starts from the
+    separable ground state of its plan; each later level starts from the
+    previous level's eigenvector, linearly interpolated."""
+    u = None
+    steps, its, lams = [], [], []
+    prev = None
+    for plan, V2, shift in levels:
+        if prev is not None:
+            u = interpolate(prev, plan, u)
+        r = inverse_iteration(plan, V2, shift, steps=max_steps, u0=u, pcg_rtol=pcg_rtol, maxit=maxit,
+                              lam_tol=lam_tol)
+        u = r.u
+        steps.append(len(r.lam) - 1)
+        its.append(int(sum(r.pcg_iters)))
+        lams.append(r.lam[-1])
+        prev = plan
+    return MultilevelResult(u=u, lam=lams[-1], steps=steps, pcg_iters=its, lam_levels=lams)
 
 
 # --------------------------------------------------------------------------
