@@ -245,6 +245,37 @@ int ts_qhop_step(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps
  * 1..64 or a null pointer). */
 int ts_gauss_legendre(int M, double* nodes, double* weights);
 
+/* Tensor-product linear interpolation from the grid of `coarse` to the grid
+ * of `fine` (Sec. 5.3.1): one axis at a time, each fine node taking the two
+ * bracketing coarse nodes, with the Dirichlet zeros at -L and L.  The plans
+ * must share d and L (FD or SEM grids, any extents).  uc, uf: device FP64
+ * arrays of the two grids.  Synchronises the stream.  Errors: TS_ERR_INVALID,
+ * TS_ERR_NOMEM, TS_ERR_DEVICE. */
+int ts_interpolate(const ts_plan* coarse, const ts_plan* fine, const double* uc, double* uf, void* hip_stream);
+
+/* u = the separable ground state of H1: the outer product of each axis's
+ * lowest eigenvector (for SEM the column of T = M^{-1/2} Q), not normalised.
+ * Device FP64.  Synchronises. */
+int ts_separable_ground_state(const ts_plan* plan, double* u, void* hip_stream);
+
+/* Multi-level shifted inverse iteration (Sec. 5.3.1, Table tab:multilevel)
+ * for the lowest eigenpair of H = H1 + diag(V2) on a sequence of grids from
+ * coarse to fine.  Level 0 starts from its separable ground state; every
+ * later level starts from the previous level's eigenvector interpolated by
+ * ts_interpolate.  On each level: the steps of ts_inverse_iteration until
+ * |lambda_k - lambda_{k-1}| <= lam_tol |lambda_k| or max_steps.
+ *   plans[l], V2[l] (device, may be NULL; V2 itself may be NULL), shifts[l]
+ *   (host; below lambda_min(H1) of level l)
+ *   u          : device FP64 of the finest grid, out: its eigenvector (unit
+ *                norm in the plan's inner product, see ts_setup_sem)
+ *   lam_levels, steps, pcg_iters : host arrays of nlevels (may be NULL):
+ *                final lambda, steps and total PCG iterations per level
+ * Errors: as ts_inverse_iteration. */
+int ts_multilevel_inverse_iteration(int nlevels, ts_plan* const* plans, const double* const* V2,
+                                    const double* shifts, double* u, int max_steps, double lam_tol,
+                                    double pcg_rtol, int pcg_maxit, int precond, double* lam_levels,
+                                    int* steps, int* pcg_iters, void* hip_stream);
+
 /* ------------------------------------------------------- GPE flows -- */
 
 /* Ground state of the GPE eq. (gpe), -Delta u + V u + beta u^3 = lambda u

@@ -68,6 +68,11 @@ def lib():
                              ctypes.c_int, ctypes.c_int, _vp],
             "ts_gauss_legendre": [ctypes.c_int, _dp, _dp],
             "ts_operator_apply": [_vp, _vp, ctypes.c_double, _vp, _vp, _vp],
+            "ts_interpolate": [_vp, _vp, _vp, _vp, _vp],
+            "ts_separable_ground_state": [_vp, _vp, _vp],
+            "ts_multilevel_inverse_iteration": [ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _dp, _vp,
+                                                ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                ctypes.c_int, _dp, _ip, _ip, _vp],
             "ts_gpe_h1_flow": [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int,
                                ctypes.c_double, _dp, _ip, _dp, _dp, _vp],
             "ts_gpe_au_flow": [_vp, _vp, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_int, ctypes.c_double,
@@ -304,6 +309,44 @@ def ts_gauss_legendre(M: int):
     nodes, weights = np.empty(max(int(M), 1)), np.empty(max(int(M), 1))
     _check(lib().ts_gauss_legendre(int(M), _dptr(nodes), _dptr(weights)), "ts_gauss_legendre")
     return nodes, weights
+
+
+def ts_interpolate(coarse: Plan, fine: Plan, uc, uf=None, stream=None):
+    torch = _torch()
+    if uf is None:
+        uf = torch.empty(fine.shape, dtype=torch.float64, device=uc.device)
+    _check(lib().ts_interpolate(coarse.handle, fine.handle, _dev(uc, coarse, "uc"), _dev(uf, fine, "uf"),
+                                _stream(stream)), "ts_interpolate")
+    return uf
+
+
+def ts_separable_ground_state(plan: Plan, u=None, stream=None):
+    torch = _torch()
+    if u is None:
+        u = torch.empty(plan.shape, dtype=torch.float64, device="cuda")
+    _check(lib().ts_separable_ground_state(plan.handle, _dev(u, plan, "u"), _stream(stream)),
+           "ts_separable_ground_state")
+    return u
+
+
+def ts_multilevel_inverse_iteration(plans, V2s, shifts, u=None, max_steps=100, lam_tol=1e-13, pcg_rtol=1e-12,
+                                    pcg_maxit=500, precond="fp64", stream=None):
+    """Returns (u on the finest grid, lambda per level, steps per level, PCG iterations per level)."""
+    torch = _torch()
+    L = len(plans)
+    if u is None:
+        u = torch.empty(plans[-1].shape, dtype=torch.float64, device="cuda")
+    ph = (_vp * L)(*[p.handle for p in plans])
+    vh = (_vp * L)(*[_dev(v, p, "V2") for v, p in zip(V2s, plans)])
+    sh = np.ascontiguousarray(shifts, dtype=np.float64)
+    lam = np.zeros(L)
+    steps = (ctypes.c_int * L)()
+    its = (ctypes.c_int * L)()
+    _check(lib().ts_multilevel_inverse_iteration(L, ph, vh, _dptr(sh), _dev(u, plans[-1], "u"), int(max_steps),
+                                                 float(lam_tol), float(pcg_rtol), int(pcg_maxit), _prec(precond),
+                                                 _dptr(lam), steps, its, _stream(stream)),
+           "ts_multilevel_inverse_iteration")
+    return u, lam, list(steps), list(its)
 
 
 class GpeResult:

@@ -406,6 +406,77 @@ int refine_run(ts_plan* p, const double* f, double* u, int inner, double rtol, i
   return rc;
 }
 
+// Shifted inverse iteration with an optional stop on the eigenvalue change
+// (|lambda_k - lambda_{k-1}| <= lam_tol |lambda_k|).  Writes lam_hist[0..k]
+// and pcg_iters[0..k-1] (host, may be null) and the steps taken.
+int invit_run(ts_plan* plan, const double* V2, double shift, double* u, int steps, double lam_tol,
+              double pcg_rtol, int maxit, int precond, double* lam_hist, int* pcg_iters, int* steps_done,
+              hipStream_t st) {
+  if (!plan || !u || steps < 0) { set_error("bad argument"); return TS_ERR_INVALID; }
+  if (!std::isfinite(shift) || !(pcg_rtol > 0.0) || maxit < 1 || !(lam_tol >= 0.0)) {
+    set_error("bad argument");
+    return TS_ERR_INVALID;
+  }
+  if (precond < TS_PREC_FP64 || precond > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
+  if (!(plan->lam_min - shift > 0.0)) {
+    set_error("shift must lie below lambda_min(H1) for the preconditioner (H1 - shift)^{-1}");
+    return TS_ERR_NOT_SPD;
+  }
+  const int64_t N = plan->N;
+  ExecCtx& c = plan->ctx;
+  // PCG uses vectors 0..3; H u and the warm-started iterate w take 4 and 5
+  SolverBufs b;
+  TS_RC(solver_buffers(c, plan, 6, b));
+  double* Hu = b.vec[4];
+  double* w = b.vec[5];
+  // SEM: iterate on the symmetric form, u in the variables M^{1/2} u
+  TS_TRY(mass_scale(plan, u, u, true, st));
+  auto rayleigh = [&](double* lam) -> int {
+    // ||u||^2 -> aux0, u <- u / ||u||, lambda = u^T H u (s = 0)
+    TS_TRY(launch_init_scalars(b.sc, 0.0, st));
+    TS_TRY(launch_dot(u, u, N, b.partial, nullptr, nullptr, nullptr, st));
+    TS_TRY(launch_scalar(ScalarStep::SetAux0, b.sc, b.partial, nullptr, 0, 1, st));
+    TS_TRY(launch_scale_invnorm(u, u, N, b.sc, st));
+    StencilArgs sa = stencil_args(plan, V2, 0.0, u, Hu, true);
+    sa.dot = StDot::UdotOut;
+    sa.partial = b.partial;
+    TS_TRY(launch_stencil(sa, st));
+    TS_TRY(launch_scalar(ScalarStep::SetAux0, b.sc, b.partial, nullptr, 0, 1, st));
+    TS_TRY(snapshot(b, st));
+    TS_TRY(hipStreamSynchronize(st));
+    *lam = b.host->aux[0];
+    return TS_OK;
+  };
+  double lam = 0.0;
+  TS_RC(rayleigh(&lam));
+  if (lam_hist) lam_hist[0] = lam;
+  TS_TRY(hipMemsetAsync(w, 0, sizeof(double) * N, st));
+  int k = 0;
+  for (; k < steps; ++k) {
+    int it = 0;
+    double rr = 0.0;
+    int rc = pcg_run(plan, V2, -shift, -shift, u, w, pcg_rtol, maxit, precond, &it, &rr, st, c, false);
+    if (pcg_iters) pcg_iters[k] = it;
+    if (rc) {
+      mass_scale(plan, u, u, false, st);
+      if (steps_done) *steps_done = k;
+      return rc;
+    }
+    TS_TRY(hipMemcpyAsync(u, w, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    const double prev = lam;
+    TS_RC(rayleigh(&lam));
+    if (lam_hist) lam_hist[k + 1] = lam;
+    if (lam_tol > 0.0 && std::fabs(lam - prev) <= lam_tol * std::fabs(lam)) {
+      ++k;
+      break;
+    }
+  }
+  if (steps_done) *steps_done = k;
+  TS_TRY(mass_scale(plan, u, u, false, st));
+  TS_TRY(hipStreamSynchronize(st));
+  return TS_OK;
+}
+
 }  // namespace ts
 
 using namespace ts;
@@ -442,58 +513,8 @@ int ts_inverse_iteration(ts_plan* plan, const double* V2, double shift, double* 
                          double pcg_rtol, int maxit, int precond, double* lam_hist, int* pcg_iters,
                          void* hip_stream) {
   if (!plan || !u || steps < 0) { set_error("bad argument"); return TS_ERR_INVALID; }
-  if (!std::isfinite(shift) || !(pcg_rtol > 0.0) || maxit < 1) { set_error("bad argument"); return TS_ERR_INVALID; }
-  if (precond < TS_PREC_FP64 || precond > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
-  if (!(plan->lam_min - shift > 0.0)) {
-    set_error("shift must lie below lambda_min(H1) for the preconditioner (H1 - shift)^{-1}");
-    return TS_ERR_NOT_SPD;
-  }
-  hipStream_t st = (hipStream_t)hip_stream;
-  const int64_t N = plan->N;
-  ExecCtx& c = plan->ctx;
-  // PCG uses vectors 0..3; H u and the warm-started iterate w take 4 and 5
-  SolverBufs b;
-  TS_RC(solver_buffers(c, plan, 6, b));
-  double* Hu = b.vec[4];
-  double* w = b.vec[5];
-  // SEM: iterate on the symmetric form, u in the variables M^{1/2} u
-  TS_TRY(mass_scale(plan, u, u, true, st));
-  auto rayleigh = [&](double* lam) -> int {
-    // ||u||^2 -> aux0, u <- u / ||u||, lambda = u^T H u (s = 0)
-    TS_TRY(launch_init_scalars(b.sc, 0.0, st));
-    TS_TRY(launch_dot(u, u, N, b.partial, nullptr, nullptr, nullptr, st));
-    TS_TRY(launch_scalar(ScalarStep::SetAux0, b.sc, b.partial, nullptr, 0, 1, st));
-    TS_TRY(launch_scale_invnorm(u, u, N, b.sc, st));
-    StencilArgs s = stencil_args(plan, V2, 0.0, u, Hu, true);
-    s.dot = StDot::UdotOut;
-    s.partial = b.partial;
-    TS_TRY(launch_stencil(s, st));
-    TS_TRY(launch_scalar(ScalarStep::SetAux0, b.sc, b.partial, nullptr, 0, 1, st));
-    TS_TRY(snapshot(b, st));
-    TS_TRY(hipStreamSynchronize(st));
-    *lam = b.host->aux[0];
-    return TS_OK;
-  };
-  double lam = 0.0;
-  TS_RC(rayleigh(&lam));
-  if (lam_hist) lam_hist[0] = lam;
-  TS_TRY(hipMemsetAsync(w, 0, sizeof(double) * N, st));
-  for (int k = 0; k < steps; ++k) {
-    int it = 0;
-    double rr = 0.0;
-    int rc = pcg_run(plan, V2, -shift, -shift, u, w, pcg_rtol, maxit, precond, &it, &rr, st, c, false);
-    if (pcg_iters) pcg_iters[k] = it;
-    if (rc) {
-      mass_scale(plan, u, u, false, st);
-      return rc;
-    }
-    TS_TRY(hipMemcpyAsync(u, w, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
-    TS_RC(rayleigh(&lam));
-    if (lam_hist) lam_hist[k + 1] = lam;
-  }
-  TS_TRY(mass_scale(plan, u, u, false, st));
-  TS_TRY(hipStreamSynchronize(st));
-  return TS_OK;
+  return invit_run(plan, V2, shift, u, steps, 0.0, pcg_rtol, maxit, precond, lam_hist, pcg_iters, nullptr,
+                   (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

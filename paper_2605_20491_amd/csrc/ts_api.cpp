@@ -133,6 +133,8 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
   }
   int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, std::vector<double>(n, h), false);
   if (rc) return rc;
+  F->x_h.resize(n);
+  for (int64_t j = 0; j < n; ++j) F->x_h[j] = -L + h * (double)(j + 1);
   out = F;
   return TS_OK;
 }
@@ -173,6 +175,7 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
   }
   S->bw = k;
   S->m_h = ax.m;
+  S->x_h = ax.x;
   int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, ax.m, true);
   if (rc) return rc;
   auto P = std::make_shared<AxisFactor>();
@@ -182,6 +185,7 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
   P->Q_h = S->Q_h;
   P->bw = k;
   P->m_h = ax.m;
+  P->x_h = ax.x;
   std::vector<double> Fwd((size_t)(n * n)), Bwd((size_t)(n * n));
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = 0; j < n; ++j) {

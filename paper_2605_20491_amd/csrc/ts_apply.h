@@ -55,6 +55,9 @@ int split_run(ts_plan* p, const void* V2, void* psi, double dt, int nsteps, int 
               hipStream_t st, ExecCtx& c);
 int qhop_run(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps, int M, bool magnus2, int dtype,
              int prec, hipStream_t st, ExecCtx& c);
+int invit_run(ts_plan* plan, const double* V2, double shift, double* u, int steps, double lam_tol,
+              double pcg_rtol, int maxit, int precond, double* lam_hist, int* pcg_iters, int* steps_done,
+              hipStream_t st);
 size_t need_solver(const ts_plan* p, int nvec);
 
 }  // namespace ts

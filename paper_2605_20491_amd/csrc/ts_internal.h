@@ -54,6 +54,7 @@ struct AxisFactor {
   double* msq = nullptr;
   double* imsq = nullptr;
   std::vector<double> m_h;    // lumped mass
+  std::vector<double> x_h;    // grid nodes (interior), ascending
   ~AxisFactor();
 };
 
