@@ -301,6 +301,72 @@ def accuracy_section(ts, W, torch, dev, steps=3):
     return out
 
 
+def gpe_section(ts, W, torch, dev, betas=(10.0, 100.0), cells=30, k=20, tol=1e-14, maxit=3000):
+    """Modified H^1 flow of Table tab:h1_flow: V1 of eq. (separable_V1) on
+    [-8,8]^3, Q^20 SEM at 599^3, alpha = 20, tau = 0.1, linear-ground-state
+    start; stops when the successive energy change is below tol (relative)."""
+    import numpy as np
+    L = 8.0
+    x = ts.ts_sem_nodes(k, cells, L)
+    v = W.f_separable_v1(0, L, x=x)
+    t0 = time.perf_counter()
+    lap = ts.ts_setup_sem(k, (cells,) * 3, L, [np.zeros_like(x)] * 3, 1.0)
+    pv1 = ts.ts_setup_sem(k, (cells,) * 3, L, [v] * 3, 1.0)
+    setup = time.perf_counter() - t0
+    vd = torch.from_numpy(v).to(dev)
+    V = (vd[:, None, None] + vd[None, :, None] + vd[None, None, :]).contiguous()
+    out = {"n": x.size, "k": k, "setup_s": setup,
+           "paper": {"beta10": {"iters": 175, "total_s": 34.8, "energy": 14.1965761916},
+                     "beta100": {"iters": 405, "total_s": 71.9, "energy": 20.6824463703}}}
+    for beta in betas:
+        u = ts.ts_separable_ground_state(pv1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ts.ts_gpe_h1_flow(lap, V, beta, u, alpha=20.0, tau=0.1, maxit=maxit, tol=tol, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        key = "beta%g" % beta
+        out[key] = {"iters": r.iters, "s": sec, "s_per_iter": sec / max(r.iters, 1), "energy": r.energy,
+                    "eigenvalue": r.eigenvalue}
+        log("gpe h1 %s: %d steps %.2f s, E %.12f lambda %.10f" % (key, r.iters, sec, r.energy, r.eigenvalue))
+        del u
+    del lap, pv1, V
+    torch.cuda.empty_cache()
+    return out
+
+
+def multilevel_section(ts, W, torch, dev, k=20, cells=(5, 10, 25)):
+    """Table tab:multilevel: the stirrer potential, Q^20 SEM 99^3 -> 199^3 -> 499^3."""
+    import numpy as np
+    L = 8.0
+    t0 = time.perf_counter()
+    plans, V2s, shifts = [], [], []
+    for c in cells:
+        x = ts.ts_sem_nodes(k, c, L)
+        plan = ts.ts_setup_sem(k, (c,) * 3, L, [4.0 * x * x, x * x, x * x], 1.0)
+        xd = torch.from_numpy(x).to(dev)
+        V2 = (8.0 * torch.exp(-((xd - 1.0) ** 2)[None, None, :] - (xd ** 2)[None, :, None])
+              * torch.ones(x.size, 1, 1, dtype=torch.float64, device=dev)).contiguous()
+        plans.append(plan)
+        V2s.append(V2)
+        shifts.append(0.9 * sum(float(ts.ts_eigvals(plan, a)[0]) for a in range(3)))
+    setup = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, lam, steps, its = ts.ts_multilevel_inverse_iteration(plans, V2s, shifts, max_steps=60, lam_tol=1e-13,
+                                                            pcg_rtol=1e-12)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    log("multilevel stirrer: lambda %.12f, steps %s, PCG %s, %.1f s (+ %.1f s setup)" % (lam[-1], steps, its, sec,
+                                                                                        setup))
+    out = {"levels_n": [k * c - 1 for c in cells], "lambda": list(lam), "steps": steps, "pcg_iters": its,
+           "solve_s": sec, "setup_s": setup, "paper_lambda": 5.286155366963,
+           "paper_a100": {"inverse_iters": [30, 21, 11], "pcg_per_iter": [75, 24, 21], "total_s": 62}}
+    del plans, V2s, u
+    torch.cuda.empty_cache()
+    return out
+
+
 SERVE_SHAPES = [(2048, 2048), (128, 128, 128), (256, 256, 256), (512, 512, 512), (64,) * 4, (16,) * 6]
 SERVE_KINDS = ["inverse_fp64", "inverse_mixed", "exp_c64"]
 
@@ -444,6 +510,9 @@ def main():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-table", action="store_true", help="skip the Table tab:accuracy_gh200 rows")
+    ap.add_argument("--no-gpe", action="store_true", help="skip the GPE and multi-level sections")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB device copy three times first (reference for HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -458,6 +527,15 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # 2^27 doubles: each copy reads and writes exactly 1 GiB
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 copies of 1 GiB")
     n, L, sigma, tau = args.n, 10.0, 1.0, 0.01
     shape = (n, n, n)
     N = n ** 3
@@ -531,6 +609,9 @@ def main():
         extra["qhop_separable_499"] = qhop_section(ts, W, torch, dev)
     if not args.no_table:
         extra["accuracy_table"] = accuracy_section(ts, W, torch, dev)
+    if not args.no_gpe:
+        extra["gpe_h1_flow_599"] = gpe_section(ts, W, torch, dev)
+        extra["multilevel_stirrer"] = multilevel_section(ts, W, torch, dev)
     if args.serve_requests > 0:
         extra["serving"] = serve_section(ts, W, torch, dev, args.serve_requests)
         torch.cuda.empty_cache()

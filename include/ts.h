@@ -111,7 +111,7 @@ int ts_destroy(ts_plan* plan);
  * T = M^{-1/2} Q and T^{-1} = Q^T M^{1/2} (host FP64 Householder reduction
  * and QL).  k = 1 is the FD grid of ts_setup with N_cell = n + 1.
  *   cells : host int64[d], k * cells[a] - 1 in [1, 8192]
- *   k     : polynomial degree, 1..16
+ *   k     : polynomial degree, 1..32
  *   f     : host FP64 arrays, f[a] holds f_a at the nodes of ts_sem_nodes
  * Every entry point then works on the nodal values of the SEM grid: the
  * applies compute (H1 + sigma)^{-1} and e^{-i tau H1} with the T factors;

@@ -33,10 +33,17 @@ struct Rot {
 
 // diag[n], off[n-1] (off[i] couples i and i+1).  On success returns true and
 // fills lam (ascending) and Q (row-major n x n, column j = eigenvector j).
+//
+// QL chases from the bottom and keeps small eigenvalues to high relative
+// accuracy when the matrix is graded with its large entries at the bottom;
+// a matrix graded the other way (as Householder reduction leaves the Q^k SEM
+// operators) is reversed first and its eigenvectors reversed back.
 bool tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q) {
-  std::vector<double> d(diag, diag + n);
+  const bool flip = n > 1 && std::fabs(diag[0]) + std::fabs(off[0]) > std::fabs(diag[n - 1]) + std::fabs(off[n - 2]);
+  std::vector<double> d(n);
   std::vector<double> e(n, 0.0);
-  for (int64_t i = 0; i + 1 < n; ++i) e[i] = off[i];
+  for (int64_t i = 0; i < n; ++i) d[i] = flip ? diag[n - 1 - i] : diag[i];
+  for (int64_t i = 0; i + 1 < n; ++i) e[i] = flip ? off[n - 2 - i] : off[i];
   std::vector<Rot> rots;
   rots.reserve((size_t)std::max<int64_t>(16, 2 * n * n));
   const double eps = std::numeric_limits<double>::epsilon();
@@ -118,13 +125,14 @@ bool tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, 
   for (int64_t i = 0; i < n; ++i) perm[i] = i;
   std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return d[a] < d[b]; });
   for (int64_t j = 0; j < n; ++j) {
-    const double* z = &Zt[(size_t)(perm[j] * n)];
+    const double* zr = &Zt[(size_t)(perm[j] * n)];
+    auto z = [&](int64_t k) { return flip ? zr[n - 1 - k] : zr[k]; };
     int64_t arg = 0;
     for (int64_t k = 1; k < n; ++k)
-      if (std::fabs(z[k]) > std::fabs(z[arg])) arg = k;
-    double sg = z[arg] < 0.0 ? -1.0 : 1.0;
+      if (std::fabs(z(k)) > std::fabs(z(arg))) arg = k;
+    double sg = z(arg) < 0.0 ? -1.0 : 1.0;
     lam[j] = d[perm[j]];
-    for (int64_t k = 0; k < n; ++k) Q[k * n + j] = sg * z[k];
+    for (int64_t k = 0; k < n; ++k) Q[k * n + j] = sg * z(k);
   }
   return true;
 }

@@ -564,7 +564,7 @@ int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* con
   if (!out || !cells || !f) { set_error("null argument"); return TS_ERR_INVALID; }
   *out = nullptr;
   if (d < 1 || d > TS_MAX_D) { set_error("d must be in [1, 12]"); return TS_ERR_INVALID; }
-  if (k < 1 || k > kMaxSemOrder) { set_error("k must be in [1, 16]"); return TS_ERR_INVALID; }
+  if (k < 1 || k > kMaxSemOrder) { set_error("k must be in [1, 32]"); return TS_ERR_INVALID; }
   if (!(L > 0.0) || !std::isfinite(L)) { set_error("L must be positive"); return TS_ERR_INVALID; }
   if (!std::isfinite(sigma)) { set_error("sigma must be finite"); return TS_ERR_INVALID; }
   int64_t N = 1;
@@ -608,7 +608,7 @@ int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* con
 int ts_sem_nodes(int k, int64_t cells, double L, double* x) {
   if (!x) { set_error("null argument"); return TS_ERR_INVALID; }
   SemAxis ax;
-  if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis (k in [1, 16], cells >= 1, L > 0)"); return TS_ERR_INVALID; }
+  if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis (k in [1, 32], cells >= 1, L > 0)"); return TS_ERR_INVALID; }
   std::memcpy(x, ax.x.data(), sizeof(double) * (size_t)ax.n);
   return TS_OK;
 }

@@ -6,7 +6,7 @@
 
 namespace ts {
 
-constexpr int kMaxSemOrder = 16;
+constexpr int kMaxSemOrder = 32;
 
 // One axis of Q^k SEM on [-L, L] with `cells` elements, Dirichlet ends.
 struct SemAxis {
