@@ -30,6 +30,33 @@ HBM_PEAK = 8000.0                                      # GB/s
 METRIC = "DoF/s of separable inverse apply at 3D 1e9 DoFs; mixed vs FP64 PCG solve time"
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_modeprod_fp64_n1000.json")
+TRAFFIC_SOURCES = ["paper_2605_20491_amd/csrc/modeprod.hip", "paper_2605_20491_amd/csrc/modeprod_common.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(root, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size);
+    None when absent or when the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, None
+    with open(TRAFFIC_FILE) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return d["bytes_per_launch"], d
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -563,8 +590,13 @@ def main():
     flops_pass = 2.0 * N * n
     t_pass = ms / 6.0
     achieved = flops_pass / (t_pass * 1e-3) / 1e12
+    traffic, tinfo = measured_traffic()
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp64"], "traffic": None,
+                "frac": achieved / PEAK["fp64"], "traffic": traffic, "traffic_unit": "bytes per launch",
+                "traffic_algorithmic": 2 * 8 * N,
+                "traffic_note": (tinfo if isinstance(tinfo, str) else
+                                 (None if tinfo is None else {k: tinfo[k] for k in ("fetch_bytes", "write_bytes",
+                                                                                     "copy_scale", "profile")})),
                 "kernel": "k_mode_mfma<double> (FP64 16x16x4 MFMA mode-product pass)",
                 "per_launch_flops": flops_pass, "avg_launch_ms": t_pass}
 

@@ -285,7 +285,9 @@ int ts_multilevel_inverse_iteration(int nlevels, ts_plan* const* plans, const do
  *   u <- (u - tau R(u)) / ||u - tau R(u)||,   G = -Delta + alpha,
  * E'(u) = (-Delta + V + beta u^2) u; two applies of (-Delta + alpha)^{-1} per
  * step.  Inner products are the grid's L^2 sums (weights prod_k m_k, see
- * ts_mass).  Stops when |E_k - E_{k-1}| <= tol |E_k|, E of eq. (gpe_energy).
+ * ts_mass).  Stops when |E_k - E_{k-1}| <= tol |E_k|, E of eq. (gpe_energy);
+ * tol <= 0 runs exactly maxit steps (the eigenvalue, first order in the state
+ * error, keeps converging after the energy has reached its rounding level).
  *   plan        : plan of -Delta alone (f = 0), FD or SEM; its sigma is unused
  *   V           : device FP64, the whole potential on the grid (may be NULL)
  *   u           : device FP64; in: start (normalised first), out: ground state

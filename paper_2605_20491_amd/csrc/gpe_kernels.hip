@@ -149,7 +149,7 @@ __global__ __launch_bounds__(RT) void k_gpe_scalar(int what, GpeScalars* sc, con
       sc->lam = a;
       if (!isfinite(E)) { sc->status = 2; sc->done = 1; break; }
       if (hist) hist[sc->iters] = E;
-      if (sc->iters > 0 && fabs(E - sc->E) <= sc->tol * fabs(E)) sc->done = 1;
+      if (sc->tol > 0.0 && sc->iters > 0 && fabs(E - sc->E) <= sc->tol * fabs(E)) sc->done = 1;
       else if (sc->iters >= sc->maxit) { sc->status = 3; sc->done = 1; }
       sc->E = E;
       if (!sc->done) sc->iters += 1;
