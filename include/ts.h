@@ -102,6 +102,17 @@ int ts_setup(int d, const int64_t* n, double L, const double* const* f, double s
  * Synchronises the device first, so pending work that uses the plan ends. */
 int ts_destroy(ts_plan* plan);
 
+/* Half-extent passes on reflection-symmetric axes.  When f_k is symmetric
+ * (f_k(x_j) = f_k(x_{n-1-j}) to 1e-13 relative) every eigenvector of H_k is
+ * even or odd; the passes on that axis (n_k >= 64, FP64 and FP32 transforms)
+ * then fold x into x_i +- x_{n-1-i} and contract half the extent against the
+ * even and odd halves of the factor (half the MFMA work), with a butterfly
+ * after each backward pass.  The result is the same up to rounding.
+ * ts_set_fold(plan, 0) turns this off for the plan (1 turns it back on);
+ * ts_fold_axes reports the axes that qualify as a bit mask (bit k = axis k). */
+int ts_set_fold(ts_plan* plan, int enable);
+int ts_fold_axes(const ts_plan* plan, int* folded);
+
 /* Plan of the Q^k spectral-element discretisation (Sec. 2, eq. (eigen_decomp)):
  * each axis of [-L, L] is split into cells[a] equal elements carrying the
  * k+1 Gauss-Lobatto nodes of degree k; n[a] = k cells[a] - 1 interior nodes

@@ -51,6 +51,8 @@ def lib():
             "ts_setup": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_double,
                          ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
             "ts_destroy": [_vp],
+            "ts_set_fold": [_vp, ctypes.c_int],
+            "ts_fold_axes": [_vp, _ip],
             "ts_setup_sem": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
             "ts_sem_nodes": [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _dp],
@@ -216,6 +218,16 @@ def ts_mass(plan: Plan, axis: int) -> np.ndarray:
     out = np.empty(plan.shape[axis])
     _check(lib().ts_mass(plan.handle, int(axis), _dptr(out)), "ts_mass")
     return out
+
+
+def ts_set_fold(plan: Plan, enable: bool):
+    _check(lib().ts_set_fold(plan.handle, int(bool(enable))), "ts_set_fold")
+
+
+def ts_fold_axes(plan: Plan) -> int:
+    m = ctypes.c_int(0)
+    _check(lib().ts_fold_axes(plan.handle, ctypes.byref(m)), "ts_fold_axes")
+    return m.value
 
 
 def ts_destroy(plan: Plan):

@@ -17,6 +17,17 @@
 //     Inv: y / (lam_k[j] + Lp[p] + Lr[q] + shift)       (FP64 denominator)
 //     Exp: y * es[j] * Ep[p] * Er[q]                     (FP64 phase factors)
 // where q indexes the faster axes (r, or r/2 for complex data).
+//
+// Reflection-symmetric axes (FOLD != 0) contract half the extent: every
+// eigenvector is even or odd, the spectral index is ordered [even | odd], and
+//   forward  (FOLD = 1): y_even = Fe^T s,  y_odd = Fo^T d,
+//            s_i = x_i + x_{n-1-i} (s_h = x_h for odd n), d_i = x_i - x_{n-1-i}
+//            (the fold is applied as the data tile is loaded);
+//   backward (FOLD = 2): E = Be^T z_even, O = Bo^T z_odd, written with O's
+//            rows reversed (row n-1-i), then x_i = E_i + O_i and
+//            x_{n-1-i} = E_i - O_i by the in-place butterfly k_unfold.
+// Tiles of the output dimension are split between the two halves, so each
+// tile runs one half-size GEMM: half the MFMA work of the plain pass.
 #include "ts_internal.h"
 #include "modeprod_common.h"
 
@@ -29,7 +40,7 @@ constexpr int BM = 128, BN = 128, BK = 16, NT = 256;
 constexpr int LDS_LD = BM + 4;  // padded LDS row length (elements)
 
 
-template <typename TC, typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI>
+template <typename TC, typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD>
 __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ TC As[2][BK][LDS_LD];
@@ -51,10 +62,23 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
     ntile = rest % a.nt;
     p = rest / a.nt;
   }
-  const int64_t m0 = mtile * BM, n0 = ntile * BN;
-  const int64_t K = a.n;
-  const TIn* X = (const TIn*)a.X;
+  // half-extent passes: which half this tile belongs to, its GEMM K and factor
+  bool odd = false;
+  int64_t K = a.n;
   const TC* S = (const TC*)a.S;
+  int64_t ldS = a.ld;
+  if (FOLD) {
+    int64_t& split = ROWS ? ntile : mtile;
+    odd = split >= a.te;
+    if (odd) split -= a.te;
+    K = FOLD == 1 ? (odd ? a.hh : a.hh + a.cc) : (odd ? a.no : a.ne);
+    S = (const TC*)(odd ? a.So : a.Se);
+    ldS = a.fld;
+  }
+  const int64_t m0 = mtile * BM, n0 = ntile * BN;
+  const TIn* X = (const TIn*)a.X;
+  // input row (along the pass axis) feeding GEMM index k; FOLD = 1 adds the mirror
+  const int64_t koff = (FOLD == 2 && odd) ? a.ne : 0;
 
   TC rres[8];
   TIn rdat[8];
@@ -67,7 +91,7 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
 #pragma unroll
     for (int it = 0; it < 8; ++it) {
       int r = r0 + 2 * it;
-      rres[it] = S[(k0 + r) * a.ld + f0 + c];
+      rres[it] = S[(k0 + r) * ldS + f0 + c];
     }
     if (!ROWS) {
       // B = X[p] rows k, columns n0..n0+127
@@ -75,14 +99,30 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
       for (int it = 0; it < 8; ++it) {
         int r = r0 + 2 * it;
         int64_t k = k0 + r, col = n0 + c;
-        rdat[it] = (k < K && col < a.R) ? X[(p * a.n + k) * a.R + col] : (TIn)0;
+        TIn v = (TIn)0;
+        if (k < K && col < a.R) {
+          v = X[(p * a.n + koff + k) * a.R + col];
+          if (FOLD == 1 && k < a.hh) {
+            const TIn w = X[(p * a.n + (a.n - 1 - k)) * a.R + col];
+            v = odd ? v - w : v + w;
+          }
+        }
+        rdat[it] = v;
       }
     } else if (!CPLX) {
       const int kk = t & 15, mr = t >> 4;
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
         int64_t m = m0 + mr + 16 * it, k = k0 + kk;
-        rdat[it] = (m < a.M && k < K) ? X[m * a.n + k] : (TIn)0;
+        TIn v = (TIn)0;
+        if (m < a.M && k < K) {
+          v = X[m * a.n + koff + k];
+          if (FOLD == 1 && k < a.hh) {
+            const TIn w = X[m * a.n + (a.n - 1 - k)];
+            v = odd ? v - w : v + w;
+          }
+        }
+        rdat[it] = v;
       }
     } else {
       const int kk = (t & 31) >> 1, cc = t & 1, pr = t >> 5;
@@ -90,7 +130,15 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
 #pragma unroll
       for (int it = 0; it < 8; ++it) {
         int64_t pp = pb + pr + 8 * it, k = k0 + kk;
-        rdat[it] = (pp < a.P && k < K) ? X[((pp * a.n + k) << 1) + cc] : (TIn)0;
+        TIn v = (TIn)0;
+        if (pp < a.P && k < K) {
+          v = X[((pp * a.n + koff + k) << 1) + cc];
+          if (FOLD == 1 && k < a.hh) {
+            const TIn w = X[((pp * a.n + (a.n - 1 - k)) << 1) + cc];
+            v = odd ? v - w : v + w;
+          }
+        }
+        rdat[it] = v;
       }
     }
   };
@@ -158,35 +206,106 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
         double partner = 0.0;
         // (re, im) of one element sit in lanes 2u, 2u+1 (columns col, col^1)
         if (EPI == (int)Epi::Exp) partner = __shfl_xor(v, 1);
-        if (ROWS) store_rows<TOut, CPLX>(a, Y, m, col, v);
-        else store_cols<TOut, CPLX, EPI>(a, Y, p, m, col, v, partner);
+        if (FOLD) {
+          // index along the pass axis within this half, and its place in the output
+          const int64_t loc = ROWS ? col : m;
+          const int64_t cnt = FOLD == 1 ? (odd ? a.no : a.ne) : (odd ? a.hh : a.hh + a.cc);
+          if (loc >= cnt) continue;
+          const int64_t dst = FOLD == 1 ? (odd ? a.ne + loc : loc) : (odd ? a.n - 1 - loc : loc);
+          if (ROWS) store_rows<TOut, CPLX>(a, Y, m, dst, v);
+          else store_cols<TOut, CPLX, EPI>(a, Y, p, dst, col, v, partner);
+        } else if (ROWS) {
+          store_rows<TOut, CPLX>(a, Y, m, col, v);
+        } else {
+          store_cols<TOut, CPLX, EPI>(a, Y, p, m, col, v, partner);
+        }
       }
+}
+
+template <typename TC, typename TIn, typename TOut, int FOLD>
+hipError_t launch_fold(const KArgs& a, const PassArgs& pa, hipStream_t st) {
+  dim3 grid((unsigned)a.nblocks), block(NT);
+  if (a.rows) {
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, true, 0, FOLD>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, false, 0, FOLD>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Exp) {
+    if (!pa.cplx) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Exp, FOLD>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Inv) {
+    if (pa.cplx)
+      hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, 0, FOLD>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+// x_i, x_{n-1-i} <- x_i + x_{n-1-i}, x_i - x_{n-1-i} for i < hh, over [P][n][R].
+template <typename T>
+__global__ __launch_bounds__(256) void k_unfold(T* Y, int64_t P, int64_t n, int64_t R, int64_t hh) {
+  const int64_t total = P * hh * R;
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t r = e % R;
+    const int64_t q = e / R;
+    const int64_t i = q % hh, p = q / hh;
+    T* lo = Y + (p * n + i) * R + r;
+    T* hi = Y + (p * n + (n - 1 - i)) * R + r;
+    const T a = *lo, b = *hi;
+    *lo = a + b;
+    *hi = a - b;
+  }
 }
 
 template <typename TC, typename TIn, typename TOut>
 hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   KArgs a{};
   const AxisFactor* F = pa.fac;
+  const bool dbl = std::is_same<TC, double>::value;
   const void* S;
-  if (std::is_same<TC, double>::value) S = pa.forward ? (const void*)F->Q64 : (const void*)F->QT64;
+  if (dbl) S = pa.forward ? (const void*)F->Q64 : (const void*)F->QT64;
   else S = pa.forward ? (const void*)F->Q32 : (const void*)F->QT32;
   fill_kargs(pa, a, S, BM, BN);
-  const bool rows = a.rows;
+  const int fold = pa.fold ? (pa.forward ? 1 : 2) : 0;
+  if (fold) {
+    a.ne = F->ne;
+    a.no = F->no;
+    a.hh = F->hh;
+    a.cc = F->cc;
+    a.fld = F->fkp;
+    if (pa.forward) {
+      a.Se = dbl ? (const void*)F->Fe64 : (const void*)F->Fe32;
+      a.So = dbl ? (const void*)F->Fo64 : (const void*)F->Fo32;
+    } else {
+      a.Se = dbl ? (const void*)F->Be64 : (const void*)F->Be32;
+      a.So = dbl ? (const void*)F->Bo64 : (const void*)F->Bo32;
+    }
+    // outputs of each half along the pass axis
+    const int64_t me = fold == 1 ? F->ne : F->hh + F->cc, mo = fold == 1 ? F->no : F->hh;
+    const int64_t tb = a.rows ? BN : BM;
+    a.te = (me + tb - 1) / tb;
+    const int64_t tsplit = a.te + (mo + tb - 1) / tb;
+    if (a.rows) {
+      a.nt = tsplit;
+      a.nblocks = a.mt * a.nt;
+    } else {
+      a.mt = tsplit;
+      a.nblocks = a.mt * a.nt * pa.P;
+    }
+  }
   if (a.nblocks <= 0) return hipSuccess;
   if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)a.nblocks), block(NT);
-  if (rows) {
-    if (pa.cplx) hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, true, 0>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, false, 0>), grid, block, 0, st, a);
-  } else if (pa.epi == Epi::Exp) {
-    if (!pa.cplx) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Exp>), grid, block, 0, st, a);
-  } else if (pa.epi == Epi::Inv) {
-    if (pa.cplx) hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Inv>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, (int)Epi::Inv>), grid, block, 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, 0>), grid, block, 0, st, a);
-  }
+  hipError_t e;
+  if (fold == 1) e = launch_fold<TC, TIn, TOut, 1>(a, pa, st);
+  else if (fold == 2) e = launch_fold<TC, TIn, TOut, 2>(a, pa, st);
+  else e = launch_fold<TC, TIn, TOut, 0>(a, pa, st);
+  if (e != hipSuccess || fold != 2 || F->hh == 0) return e;
+  // butterfly of the backward pass, in place on its output
+  const int64_t Rr = pa.R;  // real values per (p, i), complex included
+  const int64_t total = pa.P * F->hh * Rr;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL((k_unfold<TOut>), dim3(blocks), dim3(256), 0, st, (TOut*)pa.Y, pa.P, pa.n, Rr, F->hh);
   return hipGetLastError();
 }
 
@@ -266,6 +385,31 @@ __global__ void k_cast_bf16(const double* x, uint16_t* y, int64_t n) {
     if (av == 0.0) pick = 0;
     y[i] = (uint16_t)((pick >> 16) | (sign << 15));
   }
+}
+
+// y[j][i] = bf16(x[i][j]) for a square [ld][ld] matrix: the K-contiguous BF16
+// copy of a k-major factor.
+__global__ void k_cast_bf16_t(const double* x, uint16_t* y, int64_t ld) {
+  const int64_t total = ld * ld;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / ld, i = e % ld;  // output row j, column i
+    const double v = x[i * ld + j];
+    const double av = fabs(v);
+    const float f = (float)av;
+    const uint32_t fb = __float_as_uint(f) & 0xffff0000u;
+    const float lo = __uint_as_float(fb), hi = __uint_as_float(fb + 0x10000u);
+    const double dlo = av - (double)lo, dhi = (double)hi - av;
+    uint32_t pick = dlo < dhi ? fb : (dhi < dlo ? fb + 0x10000u : (((fb >> 16) & 1u) ? fb + 0x10000u : fb));
+    if (av == 0.0) pick = 0;
+    y[e] = (uint16_t)((pick >> 16) | ((v < 0.0 ? 1u : 0u) << 15));
+  }
+}
+
+hipError_t launch_cast_f64_to_bf16_t(const double* x, uint16_t* y, int64_t ld, hipStream_t st) {
+  int blocks = (int)std::min<int64_t>(4096, (ld * ld + 255) / 256);
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_bf16_t, dim3(blocks), dim3(256), 0, st, x, y, ld);
+  return hipGetLastError();
 }
 
 hipError_t launch_cast_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {

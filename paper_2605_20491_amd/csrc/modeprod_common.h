@@ -65,6 +65,12 @@ struct KArgs {
   const double2* es;
   const int* skip;
   bool rows;          // row pass (fastest axis) rather than column pass
+  // half-extent passes of a reflection-symmetric axis (fold = 1 forward, 2 backward):
+  // tiles [0, te) of the split dimension belong to the even part, the rest to the odd part
+  int64_t ne, no, hh, cc, te;
+  const void* Se;     // half factors, k-major [fld][fld]
+  const void* So;
+  int64_t fld;
 };
 
 // Map the hardware block id to a logical tile id so that consecutive logical

@@ -30,6 +30,14 @@ AxisFactor::~AxisFactor() {
   hipFree(Q16);
   hipFree(QT16);
   hipFree(band);
+  hipFree(Fe64);
+  hipFree(Fo64);
+  hipFree(Be64);
+  hipFree(Bo64);
+  hipFree(Fe32);
+  hipFree(Fo32);
+  hipFree(Be32);
+  hipFree(Bo32);
   hipFree(mass);
   hipFree(msq);
   hipFree(imsq);
@@ -37,13 +45,64 @@ AxisFactor::~AxisFactor() {
 
 namespace {
 
+// Even/odd structure of a reflection-symmetric axis.  Q's columns are tested
+// for parity (sum_i q_i q_{n-1-i} = +-1); when every column is clean and the
+// counts are ceil(n/2) even and floor(n/2) odd, the spectral order becomes
+// [even | odd] and the half factors are cut from the (permuted) Fwd / Bwd.
+struct FoldPlan {
+  bool on = false;
+  std::vector<int64_t> perm;  // internal spectral index -> ascending index
+  int64_t ne = 0, no = 0, hh = 0, cc = 0;
+};
+
+FoldPlan plan_fold(int64_t n, const std::vector<double>& Q, const double* f) {
+  FoldPlan fp;
+  if (n < 64) return fp;  // the grouped small-extent path does not use it
+  double fmax = 0.0, fasym = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    fmax = std::max(fmax, std::fabs(f[i]));
+    fasym = std::max(fasym, std::fabs(f[i] - f[n - 1 - i]));
+  }
+  if (fasym > 1e-13 * std::max(1.0, fmax)) return fp;
+  std::vector<int64_t> even, odd;
+  for (int64_t j = 0; j < n; ++j) {
+    double par = 0.0;
+    for (int64_t i = 0; i < n; ++i) par += Q[(size_t)(i * n + j)] * Q[(size_t)((n - 1 - i) * n + j)];
+    if (par > 1.0 - 1e-10) even.push_back(j);
+    else if (par < -1.0 + 1e-10) odd.push_back(j);
+    else return fp;
+  }
+  fp.hh = n / 2;
+  fp.cc = n % 2;
+  if ((int64_t)even.size() != fp.hh + fp.cc || (int64_t)odd.size() != fp.hh) return fp;
+  fp.on = true;
+  fp.ne = (int64_t)even.size();
+  fp.no = (int64_t)odd.size();
+  fp.perm = even;
+  fp.perm.insert(fp.perm.end(), odd.begin(), odd.end());
+  return fp;
+}
+
 // Upload one factor set.  Fwd and Bwd are row-major n x n with the pass
 // convention y_j = sum_i W[i][j] x_i; they are zero-padded to [kpad][ld].
 // m: the axis's L^2 weights; band (n * (2 bw + 1) entries) and the mass
 // roots (roots = true) are for SEM.
-int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd, const std::vector<double>& Bwd,
-                  const std::vector<double>* band, const std::vector<double>& m, bool roots) {
+int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd0, const std::vector<double>& Bwd0,
+                  const std::vector<double>* band, const std::vector<double>& m, bool roots, const FoldPlan& fp) {
   const int64_t n = F.n;
+  // internal spectral order: columns of Fwd and rows of Bwd, and lam
+  std::vector<double> Fwd = Fwd0, Bwd = Bwd0;
+  F.lam_int_h = F.lam_h;
+  if (fp.on) {
+    for (int64_t jj = 0; jj < n; ++jj) {
+      const int64_t j = fp.perm[jj];
+      F.lam_int_h[jj] = F.lam_h[j];
+      for (int64_t i = 0; i < n; ++i) {
+        Fwd[(size_t)(i * n + jj)] = Fwd0[(size_t)(i * n + j)];
+        Bwd[(size_t)(jj * n + i)] = Bwd0[(size_t)(j * n + i)];
+      }
+    }
+  }
   F.ld = round_up(n, kTileF);
   F.kpad = F.ld;  // square padding: every kernel's tiles stay inside
   const size_t padded = (size_t)(F.kpad * F.ld);
@@ -82,7 +141,7 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
   // upload on a private non-blocking stream: setup never waits for other work
   hipStream_t st = nullptr;
   e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipMemcpyAsync(F.lam, F.lam_h.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(F.lam, F.lam_int_h.data(), sizeof(double) * n, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(F.f, f, sizeof(double) * n, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(F.Q64, Qp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(F.QT64, QTp.data(), sizeof(double) * padded, hipMemcpyHostToDevice, st);
@@ -94,8 +153,39 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
   // reduced-precision copies are cast on the device from the FP64 copy
   if (e == hipSuccess) e = launch_cast_f64_to_f32(F.Q64, F.Q32, (int64_t)padded, st);
   if (e == hipSuccess) e = launch_cast_f64_to_f32(F.QT64, F.QT32, (int64_t)padded, st);
-  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F.Q64, F.Q16, (int64_t)padded, st);
-  if (e == hipSuccess) e = launch_cast_f64_to_bf16(F.QT64, F.QT16, (int64_t)padded, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(F.Q64, F.QT16, F.ld, st);
+  if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(F.QT64, F.Q16, F.ld, st);
+  // half factors of a symmetric axis
+  std::vector<double> H[4];
+  if (e == hipSuccess && fp.on) {
+    F.fold = true;
+    F.ne = fp.ne;
+    F.no = fp.no;
+    F.hh = fp.hh;
+    F.cc = fp.cc;
+    F.fkp = round_up(fp.hh + fp.cc, kTileF);
+    const int64_t kp = F.fkp;
+    for (auto& h : H) h.assign((size_t)(kp * kp), 0.0);
+    for (int64_t i = 0; i < fp.hh + fp.cc; ++i)
+      for (int64_t j = 0; j < fp.ne; ++j) {
+        H[0][(size_t)(i * kp + j)] = Fwd[(size_t)(i * n + j)];  // Fe[i][j']
+        H[2][(size_t)(j * kp + i)] = Bwd[(size_t)(j * n + i)];  // Be[j'][i]
+      }
+    for (int64_t i = 0; i < fp.hh; ++i)
+      for (int64_t j = 0; j < fp.no; ++j) {
+        H[1][(size_t)(i * kp + j)] = Fwd[(size_t)(i * n + fp.ne + j)];  // Fo[i][j'']
+        H[3][(size_t)(j * kp + i)] = Bwd[(size_t)((fp.ne + j) * n + i)];  // Bo[j''][i]
+      }
+    double** d64[4] = {&F.Fe64, &F.Fo64, &F.Be64, &F.Bo64};
+    float** d32[4] = {&F.Fe32, &F.Fo32, &F.Be32, &F.Bo32};
+    const size_t cnt = (size_t)(kp * kp);
+    for (int q = 0; q < 4 && e == hipSuccess; ++q) {
+      e = hipMalloc(d64[q], sizeof(double) * cnt);
+      if (e == hipSuccess) e = hipMalloc(d32[q], sizeof(float) * cnt);
+      if (e == hipSuccess) e = hipMemcpyAsync(*d64[q], H[q].data(), sizeof(double) * cnt, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = launch_cast_f64_to_f32(*d64[q], *d32[q], (int64_t)cnt, st);
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (st) hipStreamDestroy(st);
   if (e != hipSuccess) {
@@ -131,7 +221,8 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
     set_error("tridiagonal eigensolver did not converge");
     return TS_ERR_INVALID;
   }
-  int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, std::vector<double>(n, h), false);
+  int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, std::vector<double>(n, h), false,
+                         plan_fold(n, F->Q_h, f));
   if (rc) return rc;
   F->x_h.resize(n);
   for (int64_t j = 0; j < n; ++j) F->x_h[j] = -L + h * (double)(j + 1);
@@ -176,7 +267,8 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
   S->bw = k;
   S->m_h = ax.m;
   S->x_h = ax.x;
-  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, ax.m, true);
+  const FoldPlan fp = plan_fold(n, S->Q_h, f);
+  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, ax.m, true, fp);
   if (rc) return rc;
   auto P = std::make_shared<AxisFactor>();
   P->n = n;
@@ -193,7 +285,7 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
       Fwd[(size_t)(i * n + j)] = ms[i] * q;   // (T^{-1})^T = M^{1/2} Q
       Bwd[(size_t)(j * n + i)] = q / ms[i];   // T^T = Q^T M^{-1/2}
     }
-  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, ax.m, true);
+  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, ax.m, true, fp);
   if (rc) return rc;
   phys = P;
   sym = S;
@@ -295,6 +387,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     for (int m = k + 1; m < d; ++m) pa.R *= p->n[m];
     pa.cplx = cplx;
     pa.skip = ap.skip;
+    pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
     if (fwd && t == d) {
       pa.epi = ap.epi;
       pa.Lp = p->Lp;
@@ -489,13 +582,13 @@ static int finish_plan(ts_plan* p) {
   for (int64_t i = 0; i < p->Ps; ++i) {
     int64_t idx = i;
     double s = 0.0;
-    for (int m = p->s - 1; m >= 0; --m) { s += p->ax[m]->lam_h[idx % p->n[m]]; idx /= p->n[m]; }
+    for (int m = p->s - 1; m >= 0; --m) { s += p->ax[m]->lam_int_h[idx % p->n[m]]; idx /= p->n[m]; }
     Lp[i] = s;
   }
   for (int64_t i = 0; i < p->Rs; ++i) {
     int64_t idx = i;
     double s = 0.0;
-    for (int m = d - 1; m > p->s; --m) { s += p->ax[m]->lam_h[idx % p->n[m]]; idx /= p->n[m]; }
+    for (int m = d - 1; m > p->s; --m) { s += p->ax[m]->lam_int_h[idx % p->n[m]]; idx /= p->n[m]; }
     Lr[i] = s;
   }
   hipError_t e = hipMalloc(&p->Lp, sizeof(double) * p->Ps);
@@ -622,6 +715,21 @@ int ts_mass(const ts_plan* plan, int axis, double* out) {
     const double h = 2.0 * plan->L / (double)(F.n + 1);
     for (int64_t i = 0; i < F.n; ++i) out[i] = h;
   }
+  return TS_OK;
+}
+
+int ts_set_fold(ts_plan* plan, int enable) {
+  if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
+  plan->fold_enabled = enable != 0;
+  return TS_OK;
+}
+
+int ts_fold_axes(const ts_plan* plan, int* folded) {
+  if (!plan || !folded) { set_error("null argument"); return TS_ERR_INVALID; }
+  int mask = 0;
+  for (int k = 0; k < plan->d; ++k)
+    if (plan->ax[k]->fold) mask |= 1 << k;
+  *folded = mask;
   return TS_OK;
 }
 

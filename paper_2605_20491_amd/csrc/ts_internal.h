@@ -45,7 +45,9 @@ struct AxisFactor {
   double* QT64 = nullptr;
   float* Q32 = nullptr;
   float* QT32 = nullptr;
-  uint16_t* Q16 = nullptr;    // bf16 bit patterns, same padded layout
+  // BF16 copies for the BF16 passes, whose operands are K-contiguous: QT16 is
+  // the transpose of Q (forward), Q16 the transpose of QT (backward)
+  uint16_t* Q16 = nullptr;
   uint16_t* QT16 = nullptr;
   double* mass = nullptr;     // device [n]: L^2 quadrature weights (FD: h; SEM: lumped mass)
   // SEM only: operator band [n][2 bw + 1] (entry (i, i - bw + t)), M^{1/2} and M^{-1/2}
@@ -55,6 +57,18 @@ struct AxisFactor {
   double* imsq = nullptr;
   std::vector<double> m_h;    // lumped mass
   std::vector<double> x_h;    // grid nodes (interior), ascending
+  // Reflection symmetry (f_k(x) = f_k(-x) on a symmetric grid): every
+  // eigenvector is even or odd, and the passes on this axis contract half the
+  // extent.  The internal spectral order is then [even modes | odd modes]
+  // (each ascending), used by lam, lam_int_h and the full factors alike.
+  // Half factors, k-major [fkp][fkp]:
+  //   Fe / Fo: forward, rows = physical i < h + c (resp. h), columns = even (odd) modes
+  //   Be / Bo: backward, rows = even (odd) modes, columns = physical i < h + c (resp. h)
+  bool fold = false;
+  int64_t ne = 0, no = 0, hh = 0, cc = 0, fkp = 0;
+  double *Fe64 = nullptr, *Fo64 = nullptr, *Be64 = nullptr, *Bo64 = nullptr;
+  float *Fe32 = nullptr, *Fo32 = nullptr, *Be32 = nullptr, *Bo32 = nullptr;
+  std::vector<double> lam_int_h;  // eigenvalues in the internal spectral order
   ~AxisFactor();
 };
 
@@ -83,6 +97,7 @@ struct PassArgs {
   const double2* Er = nullptr;
   const double2* es = nullptr;
   const int* skip = nullptr;   // if non-null and *skip != 0 the kernel returns
+  bool fold = false;           // half-extent pass of a symmetric axis (FP64 / FP32 only)
 };
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);
@@ -105,6 +120,8 @@ hipError_t launch_phase_tables(const PhaseTableArgs& a, hipStream_t st);
 // Device-side casts for the plan's reduced-precision copies of Q.
 hipError_t launch_cast_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
 hipError_t launch_cast_f64_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st);
+// Transposing cast of a square [ld][ld] factor: y[j][i] = bf16(x[i][j]).
+hipError_t launch_cast_f64_to_bf16_t(const double* x, uint16_t* y, int64_t ld, hipStream_t st);
 
 // Scratch of one stream of work on a plan: the apply's ping-pong workspace,
 // the propagator's phase tables, the small path's diagonal tables and the
@@ -139,6 +156,7 @@ struct ts_plan {
   std::vector<std::shared_ptr<ts::AxisFactor>> ax;      // factors of the public applies
   std::vector<std::shared_ptr<ts::AxisFactor>> ax_sym;  // orthogonal factors of the solvers (FD: = ax)
   int sem_k = 0;               // 0: FD; k >= 1: Q^k SEM
+  bool fold_enabled = true;    // use the half-extent passes on symmetric axes
   int s = 0;                   // axis whose forward pass carries the scaling
   int64_t Ps = 1, Rs = 1;      // products of the extents before / after axis s
   double* Lp = nullptr;        // device FP64 [Ps]

@@ -1,0 +1,82 @@
+"""Half-extent passes on reflection-symmetric axes (ts_set_fold): with f_k
+symmetric every eigenvector is even or odd and the passes contract half the
+extent.  The folded and plain passes must agree to rounding, and both must
+match the oracle; axes with non-symmetric f_k, or n_k < 64, are not folded.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_20491_amd as ts
+import workloads as W
+from gpu_common import DEV, announce, exp_tol, make_pair, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64,), (65,), (200,), (128, 96), (97, 64), (100, 99, 130), (64, 65, 66, 67), (33, 130, 80)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fold_matches_plain_and_oracle(shape):
+    plan, oplan, f = make_pair(shape, 6.0, "cos", sigma=1.0)  # x^2 + 0.5 cos 2x: symmetric
+    mask = ts.ts_fold_axes(plan)
+    expect = sum(1 << k for k, n in enumerate(shape) if n >= 64)
+    assert mask == expect, (mask, expect)
+    b = W.rhs_normal(shape, 1)
+    psi = W.complex_normal(shape, 2)
+    out = {}
+    for fold in (True, False):
+        ts.ts_set_fold(plan, fold)
+        out[fold] = (to_host(ts.ts_apply_inverse(plan, to_dev(b))),
+                     to_host(ts.ts_apply_inverse_shift(plan, 2.5, to_dev(b))),
+                     to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi))),
+                     to_host(ts.ts_apply_inverse(plan, to_dev(b).float(), prec="fp32")).astype(np.float64),
+                     to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi).to(torch.complex64), prec="fp32")))
+    refs = (oracle.apply_inverse(oplan, b, 1.0), oracle.apply_inverse(oplan, b, 2.5), oracle.apply_exp(oplan, psi, 0.05))
+    d = [rel(a, c) for a, c in zip(out[True], out[False])]
+    e = [rel(out[True][i], refs[i]) for i in range(3)]
+    e32 = rel(out[True][3], refs[0])
+    e64c = rel(out[True][4].astype(np.complex128), refs[2])
+    announce("fold %s mask %d: fold vs plain %s; vs oracle %s; fp32 %.2e c64 %.2e"
+             % (shape, mask, ["%.1e" % x for x in d], ["%.1e" % x for x in e], e32, e64c))
+    assert max(d[:3]) <= 1e-13 and max(d[3:]) <= 2e-6
+    assert e[0] <= 1e-12 and e[1] <= 1e-12 and e[2] <= exp_tol(oplan, 0.05)
+    assert e32 <= 2e-6 and e64c <= 2e-6
+
+
+def test_non_symmetric_axes_are_not_folded():
+    shape = (80, 70)
+    plan, oplan, f = make_pair(shape, 6.0, "rand", sigma=1.0)
+    assert ts.ts_fold_axes(plan) == 0
+    shape = (80, 70)
+    rng = np.random.default_rng(0)
+    fs = [W.f_harmonic(80, 6.0), rng.uniform(0, 2, 70)]
+    plan = ts.ts_setup(shape, 6.0, fs, 1.0)
+    assert ts.ts_fold_axes(plan) == 1
+    oplan = oracle.make_plan(shape, 6.0, fs)
+    b = W.rhs_normal(shape, 3)
+    assert rel(to_host(ts.ts_apply_inverse(plan, to_dev(b))), oracle.apply_inverse(oplan, b, 1.0)) <= 1e-12
+
+
+def test_fold_in_solvers_and_sem():
+    """PCG with a folded preconditioner, and a symmetric SEM plan (mass-scaled factors)."""
+    shape, L = (96, 80, 72), 8.0
+    plan, oplan, f = make_pair(shape, L, "harm", sigma=1.0)
+    assert ts.ts_fold_axes(plan) == 7
+    V2 = W.gaussian_bumps(shape, L, 4, seed=5)
+    V2 = V2 - min(0.0, V2.min())
+    rhs = W.rhs_normal(shape, 6)
+    u = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    _, its, rr, _ = ts.ts_pcg_solve(plan, to_dev(V2), to_dev(rhs), u, rtol=1e-10, maxit=200)
+    true = np.linalg.norm(rhs - oracle.stencil_apply(oplan, to_host(u), V2, 1.0)) / np.linalg.norm(rhs)
+    assert true <= 2e-10
+    k, cells = 4, (20, 18)
+    fs = [W.f_harmonic(0, L, x=ts.ts_sem_nodes(k, c, L)) for c in cells]
+    sp = ts.ts_setup_sem(k, cells, L, fs, 1.0)
+    assert ts.ts_fold_axes(sp) == 3
+    osp = oracle.make_plan_sem(k, cells, L, fs)
+    b = W.rhs_normal(sp.shape, 7)
+    assert rel(to_host(ts.ts_apply_inverse(sp, to_dev(b))), oracle.apply_inverse(osp, b, 1.0)) <= 1e-12
+    u16 = to_host(ts.ts_apply_inverse(sp, to_dev(b).float(), prec="bf16")).astype(np.float64)
+    assert rel(u16, oracle.apply_inverse(osp, b, 1.0)) <= 3e-2

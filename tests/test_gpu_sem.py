@@ -54,11 +54,15 @@ def test_sem_apply_parity(k, cells):
     e_exp = rel(to_host(ts.ts_apply_exp(plan, tau, to_dev(psi))), oracle.apply_exp(oplan, psi, tau))
     u32 = to_host(ts.ts_apply_inverse(plan, to_dev(b).float(), prec="fp32")).astype(np.float64)
     e32 = rel(u32, oracle.apply_inverse(oplan, b, 1.0))
-    announce("sem k=%d cells=%s n=%s: inv %.2e shift %.2e exp %.2e (tol %.1e) fp32 %.2e"
-             % (k, cells, plan.shape, e_inv, e_sh, e_exp, exp_tol(oplan, tau), e32))
+    u16 = to_host(ts.ts_apply_inverse(plan, to_dev(b).float(), prec="bf16")).astype(np.float64)
+    e16 = rel(u16, oracle.apply_inverse(oplan, b, 1.0))
+    announce("sem k=%d cells=%s n=%s: inv %.2e shift %.2e exp %.2e (tol %.1e) fp32 %.2e bf16 %.2e"
+             % (k, cells, plan.shape, e_inv, e_sh, e_exp, exp_tol(oplan, tau), e32, e16))
     assert e_inv <= 1e-12 and e_sh <= 1e-12
     assert e_exp <= exp_tol(oplan, tau)
     assert e32 <= 2e-5
+    # BF16 operands (8-bit mantissa) through 2d passes; the grouped small path computes in FP32
+    assert e16 <= 3e-2
 
 
 @pytest.mark.parametrize("k,cells", [(2, (6, 5, 4)), (6, (3, 2, 3)), (3, (22, 17, 15)), (10, (2, 3))])
