@@ -354,6 +354,13 @@ int ts_workspace_bytes(const ts_plan* plan, int dtype, size_t* bytes);
  * positive.  Host pointers.  Errors: TS_ERR_INVALID, TS_ERR_NOCONV. */
 int ts_tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q);
 
+/* Host: ts_tridiag_eig for a reflection-symmetric tridiagonal (diag[i] =
+ * diag[n-1-i], off[i] = off[n-2-i], exactly), solved as the two blocks of its
+ * even and odd subspaces (the way ts_setup treats a symmetric f): every
+ * eigenvector has exact parity.  Same outputs and conventions as
+ * ts_tridiag_eig; n >= 2.  Errors: TS_ERR_INVALID, TS_ERR_NOCONV. */
+int ts_tridiag_eig_even_odd(int64_t n, const double* diag, const double* off, double* lam, double* Q);
+
 /* Host FP64 eigendecomposition of a dense symmetric matrix (row-major n x n;
  * the symmetric part (A + A^T)/2 is used) by Householder reduction to
  * tridiagonal form and implicit QL (the per-axis step of eq. (eigen_decomp)

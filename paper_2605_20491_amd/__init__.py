@@ -84,6 +84,7 @@ def lib():
             "ts_workspace_bytes": [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
             "ts_tridiag_eig": [ctypes.c_int64, _dp, _dp, _dp, _dp],
             "ts_sym_eig": [ctypes.c_int64, _dp, _dp, _dp],
+            "ts_tridiag_eig_even_odd": [ctypes.c_int64, _dp, _dp, _dp, _dp],
         }
         for name, argt in sig.items():
             fn = getattr(L, name)
@@ -430,6 +431,16 @@ def ts_tridiag_eig(diag: np.ndarray, off: np.ndarray):
     Q = np.empty((n, n))
     offp = _dptr(off) if off.size else _dptr(np.zeros(1))
     _check(lib().ts_tridiag_eig(n, _dptr(diag), offp, _dptr(lam), _dptr(Q)), "ts_tridiag_eig")
+    return lam, Q
+
+
+def ts_tridiag_eig_even_odd(diag: np.ndarray, off: np.ndarray):
+    diag = np.ascontiguousarray(diag, dtype=np.float64)
+    off = np.ascontiguousarray(off, dtype=np.float64)
+    n = diag.size
+    lam = np.empty(n)
+    Q = np.empty((n, n))
+    _check(lib().ts_tridiag_eig_even_odd(n, _dptr(diag), _dptr(off), _dptr(lam), _dptr(Q)), "ts_tridiag_eig_even_odd")
     return lam, Q
 
 

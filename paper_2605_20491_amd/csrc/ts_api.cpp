@@ -45,42 +45,133 @@ AxisFactor::~AxisFactor() {
 
 namespace {
 
-// Even/odd structure of a reflection-symmetric axis.  Q's columns are tested
-// for parity (sum_i q_i q_{n-1-i} = +-1); when every column is clean and the
-// counts are ceil(n/2) even and floor(n/2) odd, the spectral order becomes
-// [even | odd] and the half factors are cut from the (permuted) Fwd / Bwd.
+// Even/odd structure of a reflection-symmetric axis.  The operator A
+// (A[n-1-i][n-1-j] = A[i][j]) leaves the even and odd subspaces invariant.
+// In the orthonormal bases (e_i +- e_{n-1-i}) / sqrt(2), i < h (plus e_h for
+// odd n), its blocks are
+//   even: A[i][j] + A[i][n-1-j]   (i, j < h),  sqrt(2) A[i][h],  A[h][h]
+//   odd:  A[i][j] - A[i][n-1-j]   (i, j < h),
+// each diagonalised on its own, so every eigenvector has exact parity even
+// where the two subspaces hold nearly equal eigenvalues (for instance the top
+// modes of a confining potential, localised at the two walls).  The spectral
+// order inside the plan is then [even modes | odd modes], each ascending.
 struct FoldPlan {
-  bool on = false;
+  bool on = false;            // the passes may fold (n >= 64)
   std::vector<int64_t> perm;  // internal spectral index -> ascending index
   int64_t ne = 0, no = 0, hh = 0, cc = 0;
 };
 
-FoldPlan plan_fold(int64_t n, const std::vector<double>& Q, const double* f) {
-  FoldPlan fp;
-  if (n < 64) return fp;  // the grouped small-extent path does not use it
+// f symmetric to 1e-13 relative
+bool symmetric_samples(int64_t n, const double* f) {
   double fmax = 0.0, fasym = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     fmax = std::max(fmax, std::fabs(f[i]));
     fasym = std::max(fasym, std::fabs(f[i] - f[n - 1 - i]));
   }
-  if (fasym > 1e-13 * std::max(1.0, fmax)) return fp;
-  std::vector<int64_t> even, odd;
-  for (int64_t j = 0; j < n; ++j) {
-    double par = 0.0;
-    for (int64_t i = 0; i < n; ++i) par += Q[(size_t)(i * n + j)] * Q[(size_t)((n - 1 - i) * n + j)];
-    if (par > 1.0 - 1e-10) even.push_back(j);
-    else if (par < -1.0 + 1e-10) odd.push_back(j);
-    else return fp;
+  return fasym <= 1e-13 * std::max(1.0, fmax);
+}
+
+// Assemble the full eigenvectors from the two blocks (Ue: ne x ne, Uo: no x no,
+// row-major, column = eigenvector), sort ascending, sign: largest entry
+// positive (lowest index on ties).  Fills lam, Q (n x n) and the fold plan.
+void assemble_split(int64_t n, const std::vector<double>& le, const std::vector<double>& Ue,
+                    const std::vector<double>& lo, const std::vector<double>& Uo, double* lam, double* Q,
+                    FoldPlan& fp) {
+  const int64_t hh = n / 2, cc = n % 2, ne = hh + cc, no = hh;
+  const double r2 = 1.0 / std::sqrt(2.0);
+  std::vector<double> V((size_t)(n * n), 0.0);  // column c: even modes first, then odd
+  std::vector<double> lv(n);
+  for (int64_t j = 0; j < ne; ++j) {
+    lv[j] = le[j];
+    for (int64_t i = 0; i < hh; ++i) {
+      const double v = Ue[(size_t)(i * ne + j)] * r2;
+      V[(size_t)(i * n + j)] = v;
+      V[(size_t)((n - 1 - i) * n + j)] = v;
+    }
+    if (cc) V[(size_t)(hh * n + j)] = Ue[(size_t)(hh * ne + j)];
   }
-  fp.hh = n / 2;
-  fp.cc = n % 2;
-  if ((int64_t)even.size() != fp.hh + fp.cc || (int64_t)odd.size() != fp.hh) return fp;
-  fp.on = true;
-  fp.ne = (int64_t)even.size();
-  fp.no = (int64_t)odd.size();
-  fp.perm = even;
-  fp.perm.insert(fp.perm.end(), odd.begin(), odd.end());
-  return fp;
+  for (int64_t j = 0; j < no; ++j) {
+    lv[ne + j] = lo[j];
+    for (int64_t i = 0; i < hh; ++i) {
+      const double v = Uo[(size_t)(i * no + j)] * r2;
+      V[(size_t)(i * n + ne + j)] = v;
+      V[(size_t)((n - 1 - i) * n + ne + j)] = -v;
+    }
+  }
+  // public order: ascending eigenvalue (ties: even first)
+  std::vector<int64_t> order(n);
+  for (int64_t c = 0; c < n; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return lv[a] < lv[b]; });
+  std::vector<int64_t> pos(n);  // internal column -> ascending index
+  for (int64_t j = 0; j < n; ++j) pos[order[j]] = j;
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t c = order[j];
+    int64_t arg = 0;
+    for (int64_t i = 1; i < n; ++i)
+      if (std::fabs(V[(size_t)(i * n + c)]) > std::fabs(V[(size_t)(arg * n + c)])) arg = i;
+    const double sg = V[(size_t)(arg * n + c)] < 0.0 ? -1.0 : 1.0;
+    lam[j] = lv[c];
+    for (int64_t i = 0; i < n; ++i) Q[(size_t)(i * n + j)] = sg * V[(size_t)(i * n + c)];
+  }
+  fp.hh = hh;
+  fp.cc = cc;
+  fp.ne = ne;
+  fp.no = no;
+  fp.perm.resize(n);
+  for (int64_t c = 0; c < n; ++c) fp.perm[c] = pos[c];
+  fp.on = n >= 64;
+}
+
+// Tridiagonal symmetric operator (diag, off constant-free): the two blocks are tridiagonal too.
+bool split_eig_tridiag(int64_t n, const double* dg, const double* off, double* lam, double* Q, FoldPlan& fp) {
+  const int64_t hh = n / 2, cc = n % 2, ne = hh + cc, no = hh;
+  if (hh == 0) return false;
+  std::vector<double> de(ne), oe(ne > 1 ? ne - 1 : 1, 0.0), dd(no), od(no > 1 ? no - 1 : 1, 0.0);
+  for (int64_t i = 0; i < hh; ++i) {
+    de[i] = dg[i];
+    dd[i] = dg[i];
+  }
+  for (int64_t i = 0; i + 1 < hh; ++i) oe[i] = od[i] = off[i];
+  if (cc) {
+    de[hh] = dg[hh];
+    oe[hh - 1] = std::sqrt(2.0) * off[hh - 1];  // e_{h-1} pair coupled to the centre
+  } else {
+    de[hh - 1] += off[hh - 1];  // the pair h-1, h = n-1-(h-1) couples to itself
+    dd[hh - 1] -= off[hh - 1];
+  }
+  std::vector<double> le(ne), Ue((size_t)(ne * ne)), lo(no), Uo((size_t)(no * no));
+  if (!tridiag_eig(ne, de.data(), oe.data(), le.data(), Ue.data())) return false;
+  if (!tridiag_eig(no, dd.data(), od.data(), lo.data(), Uo.data())) return false;
+  assemble_split(n, le, Ue, lo, Uo, lam, Q, fp);
+  return true;
+}
+
+// Dense reflection-symmetric operator (row-major n x n).
+bool split_eig_dense(int64_t n, const std::vector<double>& A, double* lam, double* Q, FoldPlan& fp) {
+  const int64_t hh = n / 2, cc = n % 2, ne = hh + cc, no = hh;
+  if (hh == 0) return false;
+  auto a = [&](int64_t i, int64_t j) {  // reflection average
+    return 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)((n - 1 - i) * n + (n - 1 - j))]);
+  };
+  std::vector<double> He((size_t)(ne * ne)), Ho((size_t)(no * no));
+  for (int64_t i = 0; i < hh; ++i)
+    for (int64_t j = 0; j < hh; ++j) {
+      He[(size_t)(i * ne + j)] = a(i, j) + a(i, n - 1 - j);
+      Ho[(size_t)(i * no + j)] = a(i, j) - a(i, n - 1 - j);
+    }
+  if (cc) {
+    for (int64_t i = 0; i < hh; ++i) He[(size_t)(i * ne + hh)] = He[(size_t)(hh * ne + i)] = std::sqrt(2.0) * a(i, hh);
+    He[(size_t)(hh * ne + hh)] = a(hh, hh);
+  }
+  std::vector<double> le(ne), Ue((size_t)(ne * ne)), lo(no), Uo((size_t)(no * no));
+  for (int64_t i = 0; i < ne; ++i)  // exact symmetry of the blocks
+    for (int64_t j = 0; j < i; ++j) He[(size_t)(i * ne + j)] = He[(size_t)(j * ne + i)] = 0.5 * (He[(size_t)(i * ne + j)] + He[(size_t)(j * ne + i)]);
+  for (int64_t i = 0; i < no; ++i)
+    for (int64_t j = 0; j < i; ++j) Ho[(size_t)(i * no + j)] = Ho[(size_t)(j * no + i)] = 0.5 * (Ho[(size_t)(i * no + j)] + Ho[(size_t)(j * no + i)]);
+  if (!dense_sym_eig(ne, He, le.data(), Ue.data())) return false;
+  if (!dense_sym_eig(no, Ho, lo.data(), Uo.data())) return false;
+  assemble_split(n, le, Ue, lo, Uo, lam, Q, fp);
+  return true;
 }
 
 // Upload one factor set.  Fwd and Bwd are row-major n x n with the pass
@@ -217,12 +308,15 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
   for (int64_t i = 0; i + 1 < n; ++i) off[i] = -ih2;
   F->lam_h.resize(n);
   F->Q_h.resize((size_t)(n * n));
-  if (!tridiag_eig(n, dg.data(), off.data(), F->lam_h.data(), F->Q_h.data())) {
+  FoldPlan fp;
+  const bool split = n >= 2 && symmetric_samples(n, f);
+  const bool ok = split ? split_eig_tridiag(n, dg.data(), off.data(), F->lam_h.data(), F->Q_h.data(), fp)
+                        : tridiag_eig(n, dg.data(), off.data(), F->lam_h.data(), F->Q_h.data());
+  if (!ok) {
     set_error("tridiagonal eigensolver did not converge");
     return TS_ERR_INVALID;
   }
-  int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, std::vector<double>(n, h), false,
-                         plan_fold(n, F->Q_h, f));
+  int rc = upload_factor(*F, f, F->Q_h, transpose(F->Q_h, n), nullptr, std::vector<double>(n, h), false, fp);
   if (rc) return rc;
   F->x_h.resize(n);
   for (int64_t j = 0; j < n; ++j) F->x_h[j] = -L + h * (double)(j + 1);
@@ -260,14 +354,18 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
   S->L = L;
   S->lam_h.resize(n);
   S->Q_h.resize((size_t)(n * n));
-  if (!dense_sym_eig(n, A, S->lam_h.data(), S->Q_h.data())) {
+  FoldPlan fp;
+  // the mesh is symmetric; with symmetric f the operator is reflection-symmetric
+  const bool split = n >= 2 && symmetric_samples(n, f);
+  const bool ok = split ? split_eig_dense(n, A, S->lam_h.data(), S->Q_h.data(), fp)
+                        : dense_sym_eig(n, A, S->lam_h.data(), S->Q_h.data());
+  if (!ok) {
     set_error("symmetric eigensolver did not converge");
     return TS_ERR_INVALID;
   }
   S->bw = k;
   S->m_h = ax.m;
   S->x_h = ax.x;
-  const FoldPlan fp = plan_fold(n, S->Q_h, f);
   int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, ax.m, true, fp);
   if (rc) return rc;
   auto P = std::make_shared<AxisFactor>();
@@ -775,6 +873,17 @@ int ts_eigvecs(const ts_plan* plan, int axis, double* out) {
 int ts_tridiag_eig(int64_t n, const double* diag, const double* off, double* lam, double* Q) {
   if (n < 1 || !diag || !lam || !Q || (n > 1 && !off)) { set_error("bad argument"); return TS_ERR_INVALID; }
   if (!tridiag_eig(n, diag, off, lam, Q)) { set_error("QL iteration limit reached"); return TS_ERR_NOCONV; }
+  return TS_OK;
+}
+
+int ts_tridiag_eig_even_odd(int64_t n, const double* diag, const double* off, double* lam, double* Q) {
+  if (n < 2 || !diag || !off || !lam || !Q) { set_error("bad argument"); return TS_ERR_INVALID; }
+  for (int64_t i = 0; i < n; ++i)
+    if (diag[i] != diag[n - 1 - i]) { set_error("diagonal is not reflection-symmetric"); return TS_ERR_INVALID; }
+  for (int64_t i = 0; i + 1 < n; ++i)
+    if (off[i] != off[n - 2 - i]) { set_error("off-diagonal is not reflection-symmetric"); return TS_ERR_INVALID; }
+  FoldPlan fp;
+  if (!split_eig_tridiag(n, diag, off, lam, Q, fp)) { set_error("QL iteration limit reached"); return TS_ERR_NOCONV; }
   return TS_OK;
 }
 

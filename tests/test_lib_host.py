@@ -143,3 +143,29 @@ def test_dense_symmetric_eig_on_sem_axis(k, cells):
     lam, Q = ts.ts_sym_eig(A)
     w, _ = oracle.jacobi_eigh(0.5 * (A + A.T))
     assert np.max(np.abs(lam - w)) < 1e-13 * np.max(np.abs(w)) * np.sqrt(len(w))
+
+
+@pytest.mark.parametrize("n", [2, 3, 64, 65, 200, 501])
+def test_even_odd_tridiagonal_eig(n):
+    """ts_tridiag_eig_even_odd on a reflection-symmetric FD operator: eigenvalues
+    against LAPACK, orthonormality, residual, and exact parity of every column
+    (including the nearly degenerate top pairs, where a plain solver may mix
+    the two parities)."""
+    L = 6.0
+    x = W.grid_nodes(n, L)
+    xs = 0.5 * (x - x[::-1])
+    f = xs * xs + 0.5 * np.cos(2 * xs)
+    h = 2 * L / (n + 1)
+    d = 2 / h**2 + f
+    o = -np.ones(n - 1) / h**2
+    lam, Q = ts.ts_tridiag_eig_even_odd(d, o)
+    T = np.diag(d) + np.diag(o, 1) + np.diag(o, -1)
+    ref = np.linalg.eigvalsh(T)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(lam - ref)) < 1e-14 * scale
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) < 1e-14 * max(1, n ** 0.5)
+    assert np.max(np.abs(T @ Q - Q * lam)) < 1e-14 * scale
+    par = np.einsum("ij,ij->j", Q, Q[::-1, :])
+    assert np.max(1 - np.abs(par)) < 1e-13
+    with pytest.raises(ts.TSError):
+        ts.ts_tridiag_eig_even_odd(d + np.arange(n) * 1e-3, o)
