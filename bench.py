@@ -587,8 +587,15 @@ def main():
     resid = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
     del r
 
-    flops_pass = 2.0 * N * n
-    t_pass = ms / 6.0
+    # dominant kernel: the forward pass on axis 1 (a column pass, half extent on a symmetric axis),
+    # timed on its own with HIP events on the stream the library launches on
+    folded = bool(ts.ts_fold_axes(plan) & 2)
+    hh, cc = n // 2, n % 2
+    flops_pass = 2.0 * (N / n) * ((hh + cc) ** 2 + hh ** 2) if folded else 2.0 * N * n
+    work = torch.empty_like(b)
+    t_pass, _ = timed(lambda: ts.ts_mode_pass(plan, 1, True, b, work), args.steps, 1)
+    t_back, _ = timed(lambda: ts.ts_mode_pass(plan, 1, False, b, work), args.steps, 1)
+    del work
     achieved = flops_pass / (t_pass * 1e-3) / 1e12
     traffic, tinfo = measured_traffic()
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
@@ -597,8 +604,11 @@ def main():
                 "traffic_note": (tinfo if isinstance(tinfo, str) else
                                  (None if tinfo is None else {k: tinfo[k] for k in ("fetch_bytes", "write_bytes",
                                                                                      "copy_scale", "profile")})),
-                "kernel": "k_mode_mfma<double> (FP64 16x16x4 MFMA mode-product pass)",
-                "per_launch_flops": flops_pass, "avg_launch_ms": t_pass}
+                "kernel": ("k_mode_mfma<double, cols, FOLD=1>: FP64 16x16x4 MFMA forward pass over half the extent "
+                           "(even/odd halves of a symmetric axis)" if folded else
+                           "k_mode_mfma<double, cols>: FP64 16x16x4 MFMA forward pass"),
+                "per_launch_flops": flops_pass, "avg_launch_ms": t_pass,
+                "backward_pass_ms": t_back, "apply_ms": ms, "folded": folded}
 
     extra = {"setup_s": setup_s, "fp64_relres": resid, "wall_s_timed": wall}
     if not args.no_extras:

@@ -111,6 +111,15 @@ int ts_destroy(ts_plan* plan);
  * ts_set_fold(plan, 0) turns this off for the plan (1 turns it back on);
  * ts_fold_axes reports the axes that qualify as a bit mask (bit k = axis k). */
 int ts_set_fold(ts_plan* plan, int enable);
+
+/* One pass of the apply (Sec. 2.1 step 2 or 4) on one axis, without the
+ * scaling: forward out = in x_axis T_axis^{-1}, backward out = in x_axis
+ * T_axis (spectral index in the plan's internal order, see ts_set_fold).
+ * For measuring and checking the pass kernels on their own.  in, out: device
+ * arrays of the grid (must not alias); dtype any of ts_dtype; prec FP64 (FP64
+ * data) or FP32.  Errors: TS_ERR_INVALID, TS_ERR_DEVICE. */
+int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out, int dtype, int prec,
+                 void* hip_stream);
 int ts_fold_axes(const ts_plan* plan, int* folded);
 
 /* Plan of the Q^k spectral-element discretisation (Sec. 2, eq. (eigen_decomp)):

@@ -52,6 +52,7 @@ def lib():
                          ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
             "ts_destroy": [_vp],
             "ts_set_fold": [_vp, ctypes.c_int],
+            "ts_mode_pass": [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_fold_axes": [_vp, _ip],
             "ts_setup_sem": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
@@ -223,6 +224,15 @@ def ts_mass(plan: Plan, axis: int) -> np.ndarray:
 
 def ts_set_fold(plan: Plan, enable: bool):
     _check(lib().ts_set_fold(plan.handle, int(bool(enable))), "ts_set_fold")
+
+
+def ts_mode_pass(plan: Plan, axis: int, forward: bool, x, out=None, prec="fp64", stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().ts_mode_pass(plan.handle, int(axis), int(bool(forward)), _dev(x, plan, "x"), _dev(out, plan, "out"),
+                              _dtype_code(x), _prec(prec), _stream(stream)), "ts_mode_pass")
+    return out
 
 
 def ts_fold_axes(plan: Plan) -> int:

@@ -40,6 +40,38 @@ constexpr int BM = 128, BN = 128, BK = 16, NT = 256;
 constexpr int LDS_LD = BM + 4;  // padded LDS row length (elements)
 
 
+// 8 consecutive elements through 16-byte accesses (16-byte aligned addresses).
+__device__ __forceinline__ void load8(const double* src, double* d) {
+  const double2* s2 = (const double2*)src;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 v = s2[i];
+    d[2 * i] = v.x;
+    d[2 * i + 1] = v.y;
+  }
+}
+__device__ __forceinline__ void load8(const float* src, float* d) {
+  const float4* s4 = (const float4*)src;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float4 v = s4[i];
+    d[4 * i] = v.x;
+    d[4 * i + 1] = v.y;
+    d[4 * i + 2] = v.z;
+    d[4 * i + 3] = v.w;
+  }
+}
+__device__ __forceinline__ void store8(double* dst, const double* v) {
+  double2* d2 = (double2*)dst;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) d2[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+__device__ __forceinline__ void store8(float* dst, const float* v) {
+  float4* d4 = (float4*)dst;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) d4[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+}
+
 template <typename TC, typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD>
 __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   if (a.skip && *a.skip) return;
@@ -84,30 +116,39 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   TIn rdat[8];
 
   // ---- global -> registers for k-tile kt ----
+  // Factor tiles and column-pass data tiles: thread t owns row t >> 4 of the
+  // 16-row tile and 8 consecutive columns 8 (t & 15) .. +7, moved with 16-byte
+  // loads and stores.  Data rows need R % (16 / sizeof) == 0 for that (always
+  // true for the factor); otherwise those loads fall back to single elements.
+  const int vr = t >> 4, vc = 8 * (t & 15);
+  const bool vec_data = !ROWS && (a.R % (16 / (int)sizeof(TIn)) == 0) && ((((uintptr_t)a.X) & 15) == 0);
   auto load_tile = [&](int64_t k0) {
-    // resident factor tile: rows k0..k0+BK-1, columns f0..f0+127 (always in bounds)
     const int64_t f0 = ROWS ? n0 : m0;
-    const int c = t & 127, r0 = t >> 7;
-#pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      int r = r0 + 2 * it;
-      rres[it] = S[(k0 + r) * ldS + f0 + c];
-    }
+    load8(S + (k0 + vr) * ldS + f0 + vc, rres);  // resident factor tile, always in bounds
     if (!ROWS) {
-      // B = X[p] rows k, columns n0..n0+127
+      // B = X[p] row k, columns n0 + vc .. +7
+      const int64_t k = k0 + vr, col = n0 + vc;
+      if (k < K && vec_data && col + 8 <= a.R) {
+        load8(X + (p * a.n + koff + k) * a.R + col, rdat);
+        if (FOLD == 1 && k < a.hh) {
+          TIn w[8];
+          load8(X + (p * a.n + (a.n - 1 - k)) * a.R + col, w);
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        int r = r0 + 2 * it;
-        int64_t k = k0 + r, col = n0 + c;
-        TIn v = (TIn)0;
-        if (k < K && col < a.R) {
-          v = X[(p * a.n + koff + k) * a.R + col];
-          if (FOLD == 1 && k < a.hh) {
-            const TIn w = X[(p * a.n + (a.n - 1 - k)) * a.R + col];
-            v = odd ? v - w : v + w;
-          }
+          for (int e = 0; e < 8; ++e) rdat[e] = odd ? rdat[e] - w[e] : rdat[e] + w[e];
         }
-        rdat[it] = v;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          TIn v = (TIn)0;
+          if (k < K && col + e < a.R) {
+            v = X[(p * a.n + koff + k) * a.R + col + e];
+            if (FOLD == 1 && k < a.hh) {
+              const TIn w = X[(p * a.n + (a.n - 1 - k)) * a.R + col + e];
+              v = odd ? v - w : v + w;
+            }
+          }
+          rdat[e] = v;
+        }
       }
     } else if (!CPLX) {
       const int kk = t & 15, mr = t >> 4;
@@ -143,13 +184,13 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
     }
   };
   auto store_tile = [&](int buf) {
-    const int c = t & 127, r0 = t >> 7;
     TC(*Res)[LDS_LD] = ROWS ? Bs[buf] : As[buf];
-#pragma unroll
-    for (int it = 0; it < 8; ++it) Res[r0 + 2 * it][c] = rres[it];
+    store8(&Res[vr][vc], rres);
     if (!ROWS) {
+      TC cv[8];
 #pragma unroll
-      for (int it = 0; it < 8; ++it) Bs[buf][r0 + 2 * it][c] = cvt_in<TIn, TC>(rdat[it]);
+      for (int e = 0; e < 8; ++e) cv[e] = cvt_in<TIn, TC>(rdat[e]);
+      store8(&Bs[buf][vr][vc], cv);
     } else if (!CPLX) {
       const int kk = t & 15, mr = t >> 4;
 #pragma unroll

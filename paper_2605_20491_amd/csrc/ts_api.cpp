@@ -816,6 +816,34 @@ int ts_mass(const ts_plan* plan, int axis, double* out) {
   return TS_OK;
 }
 
+int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out, int dtype, int prec,
+                 void* hip_stream) {
+  if (!plan || !in || !out || axis < 0 || axis >= plan->d) { set_error("bad argument"); return TS_ERR_INVALID; }
+  if (in == out) { set_error("in and out must not alias"); return TS_ERR_INVALID; }
+  if (dtype != TS_F64 && dtype != TS_F32 && dtype != TS_C128 && dtype != TS_C64) { set_error("bad dtype"); return TS_ERR_INVALID; }
+  if (prec != TS_PREC_FP64 && prec != TS_PREC_FP32) { set_error("the single pass runs FP64 or FP32 transforms"); return TS_ERR_INVALID; }
+  const bool f64 = dtype == TS_F64 || dtype == TS_C128;
+  if (prec == TS_PREC_FP64 && !f64) { set_error("FP64 transforms need FP64 data"); return TS_ERR_INVALID; }
+  const bool cplx = dtype == TS_C128 || dtype == TS_C64;
+  PassArgs pa;
+  pa.X = in;
+  pa.Y = out;
+  pa.tin = pa.tout = f64 ? DT::F64 : DT::F32;
+  pa.prec = prec;
+  pa.fac = plan->ax[axis].get();
+  pa.forward = forward != 0;
+  pa.n = plan->n[axis];
+  pa.P = 1;
+  for (int m = 0; m < axis; ++m) pa.P *= plan->n[m];
+  pa.R = cplx ? 2 : 1;
+  for (int m = axis + 1; m < plan->d; ++m) pa.R *= plan->n[m];
+  pa.cplx = cplx;
+  pa.fold = pa.fac->fold && plan->fold_enabled;
+  hipError_t e = launch_pass(pa, (hipStream_t)hip_stream);
+  if (e != hipSuccess) { set_error(std::string("mode pass launch failed: ") + hipGetErrorString(e)); return TS_ERR_DEVICE; }
+  return TS_OK;
+}
+
 int ts_set_fold(ts_plan* plan, int enable) {
   if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
   plan->fold_enabled = enable != 0;

@@ -80,3 +80,19 @@ def test_fold_in_solvers_and_sem():
     assert rel(to_host(ts.ts_apply_inverse(sp, to_dev(b))), oracle.apply_inverse(osp, b, 1.0)) <= 1e-12
     u16 = to_host(ts.ts_apply_inverse(sp, to_dev(b).float(), prec="bf16")).astype(np.float64)
     assert rel(u16, oracle.apply_inverse(osp, b, 1.0)) <= 3e-2
+
+
+@pytest.mark.parametrize("shape", [(100, 99, 130), (70, 81)])
+def test_single_pass_round_trip(shape):
+    """ts_mode_pass: backward after forward is the identity on every axis,
+    folded or not, and the folded forward pass equals the plain one."""
+    plan, _, _ = make_pair(shape, 6.0, "cos", sigma=1.0)
+    x = to_dev(W.rhs_normal(shape, 4))
+    for axis in range(len(shape)):
+        y = ts.ts_mode_pass(plan, axis, True, x)
+        z = ts.ts_mode_pass(plan, axis, False, y)
+        assert rel(to_host(z), to_host(x)) <= 1e-13
+        ts.ts_set_fold(plan, False)
+        y0 = ts.ts_mode_pass(plan, axis, True, x)
+        ts.ts_set_fold(plan, True)
+        assert rel(to_host(y), to_host(y0)) <= 1e-14
