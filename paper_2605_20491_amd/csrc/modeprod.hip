@@ -122,6 +122,10 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   // true for the factor); otherwise those loads fall back to single elements.
   const int vr = t >> 4, vc = 8 * (t & 15);
   const bool vec_data = !ROWS && (a.R % (16 / (int)sizeof(TIn)) == 0) && ((((uintptr_t)a.X) & 15) == 0);
+  // row passes: rows of n (real) or 2n (complex) elements, starting k offsets multiples of 4
+  const int64_t VW = 16 / (int64_t)sizeof(TIn);
+  const bool vec_rows = ROWS && ((((uintptr_t)a.X) & 15) == 0) &&
+                        ((CPLX ? 2 * a.n : a.n) % VW == 0) && ((CPLX ? 2 * koff : koff) % VW == 0);
   auto load_tile = [&](int64_t k0) {
     const int64_t f0 = ROWS ? n0 : m0;
     load8(S + (k0 + vr) * ldS + f0 + vc, rres);  // resident factor tile, always in bounds
@@ -151,35 +155,77 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
         }
       }
     } else if (!CPLX) {
-      const int kk = t & 15, mr = t >> 4;
+      // A = X rows: thread t owns row m0 + (t >> 1) and k0 + 8 (t & 1) .. +7
+      const int64_t m = m0 + (t >> 1), kb = k0 + 8 * (t & 1);
+      const TIn* row = X + m * a.n;
+      if (vec_rows && m < a.M && kb + 8 <= K) {
+        load8(row + koff + kb, rdat);
+        if (FOLD == 1 && kb + 8 <= a.hh) {
+          TIn w[8];  // row[n-1-kb-7 .. n-1-kb], reversed below
+          load8(row + (a.n - 8 - kb), w);
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        int64_t m = m0 + mr + 16 * it, k = k0 + kk;
-        TIn v = (TIn)0;
-        if (m < a.M && k < K) {
-          v = X[m * a.n + koff + k];
-          if (FOLD == 1 && k < a.hh) {
-            const TIn w = X[m * a.n + (a.n - 1 - k)];
-            v = odd ? v - w : v + w;
-          }
+          for (int e = 0; e < 8; ++e) rdat[e] = odd ? rdat[e] - w[7 - e] : rdat[e] + w[7 - e];
+        } else if (FOLD == 1) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (kb + e < a.hh) rdat[e] = odd ? rdat[e] - row[a.n - 1 - kb - e] : rdat[e] + row[a.n - 1 - kb - e];
         }
-        rdat[it] = v;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t k = kb + e;
+          TIn v = (TIn)0;
+          if (m < a.M && k < K) {
+            v = row[koff + k];
+            if (FOLD == 1 && k < a.hh) {
+              const TIn w = row[a.n - 1 - k];
+              v = odd ? v - w : v + w;
+            }
+          }
+          rdat[e] = v;
+        }
       }
     } else {
-      const int kk = (t & 31) >> 1, cc = t & 1, pr = t >> 5;
-      const int64_t pb = m0 >> 1;
+      // A rows 2 pp (re) and 2 pp + 1 (im): thread t owns pp = m0 / 2 + (t >> 2) and
+      // k0 + 4 (t & 3) .. +3, i.e. 8 consecutive interleaved values
+      const int64_t pp = (m0 >> 1) + (t >> 2), kb = k0 + 4 * (t & 3);
+      const TIn* row = X + ((pp * a.n) << 1);
+      if (vec_rows && pp < a.P && kb + 4 <= K) {
+        load8(row + ((koff + kb) << 1), rdat);
+        if (FOLD == 1 && kb + 4 <= a.hh) {
+          TIn w[8];  // complex elements n-1-kb-3 .. n-1-kb, reversed below
+          load8(row + ((a.n - 4 - kb) << 1), w);
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        int64_t pp = pb + pr + 8 * it, k = k0 + kk;
-        TIn v = (TIn)0;
-        if (pp < a.P && k < K) {
-          v = X[((pp * a.n + koff + k) << 1) + cc];
-          if (FOLD == 1 && k < a.hh) {
-            const TIn w = X[((pp * a.n + (a.n - 1 - k)) << 1) + cc];
-            v = odd ? v - w : v + w;
+          for (int e = 0; e < 4; ++e) {
+            rdat[2 * e] = odd ? rdat[2 * e] - w[6 - 2 * e] : rdat[2 * e] + w[6 - 2 * e];
+            rdat[2 * e + 1] = odd ? rdat[2 * e + 1] - w[7 - 2 * e] : rdat[2 * e + 1] + w[7 - 2 * e];
           }
+        } else if (FOLD == 1) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (kb + e < a.hh) {
+              const int64_t mk = (a.n - 1 - kb - e) << 1;
+              rdat[2 * e] = odd ? rdat[2 * e] - row[mk] : rdat[2 * e] + row[mk];
+              rdat[2 * e + 1] = odd ? rdat[2 * e + 1] - row[mk + 1] : rdat[2 * e + 1] + row[mk + 1];
+            }
         }
-        rdat[it] = v;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t k = kb + e;
+          TIn vr0 = (TIn)0, vi0 = (TIn)0;
+          if (pp < a.P && k < K) {
+            vr0 = row[(koff + k) << 1];
+            vi0 = row[((koff + k) << 1) + 1];
+            if (FOLD == 1 && k < a.hh) {
+              const TIn wr = row[(a.n - 1 - k) << 1], wi = row[((a.n - 1 - k) << 1) + 1];
+              vr0 = odd ? vr0 - wr : vr0 + wr;
+              vi0 = odd ? vi0 - wi : vi0 + wi;
+            }
+          }
+          rdat[2 * e] = vr0;
+          rdat[2 * e + 1] = vi0;
+        }
       }
     }
   };
@@ -192,13 +238,16 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
       for (int e = 0; e < 8; ++e) cv[e] = cvt_in<TIn, TC>(rdat[e]);
       store8(&Bs[buf][vr][vc], cv);
     } else if (!CPLX) {
-      const int kk = t & 15, mr = t >> 4;
+      const int ml = t >> 1, kl = 8 * (t & 1);
 #pragma unroll
-      for (int it = 0; it < 8; ++it) As[buf][kk][mr + 16 * it] = cvt_in<TIn, TC>(rdat[it]);
+      for (int e = 0; e < 8; ++e) As[buf][kl + e][ml] = cvt_in<TIn, TC>(rdat[e]);
     } else {
-      const int kk = (t & 31) >> 1, cc = t & 1, pr = t >> 5;
+      const int pl = t >> 2, kl = 4 * (t & 3);
 #pragma unroll
-      for (int it = 0; it < 8; ++it) As[buf][kk][2 * (pr + 8 * it) + cc] = cvt_in<TIn, TC>(rdat[it]);
+      for (int e = 0; e < 4; ++e) {
+        As[buf][kl + e][2 * pl] = cvt_in<TIn, TC>(rdat[2 * e]);
+        As[buf][kl + e][2 * pl + 1] = cvt_in<TIn, TC>(rdat[2 * e + 1]);
+      }
     }
   };
 
