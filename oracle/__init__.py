@@ -145,7 +145,8 @@ class Plan:
     (the paper's x).  ``Q[k]`` columns are eigenvectors, ``lam[k]`` ascending.
     For a Q^k SEM plan (``sem_k`` >= 1) ``m[k]`` is the lumped mass and
     ``K[k]`` the dense M^{-1} S of each axis, and ``Q[k]`` diagonalises the
-    symmetric M^{-1/2} S M^{-1/2} + F of eq. (eigen_decomp).
+    symmetric M^{-1/2} S M^{-1/2} + F of eq. (eigen_decomp).  A generic plan
+    (``make_plan_general``) carries any K[k] with its weights m[k] the same way.
     """
     shape: tuple
     L: float
@@ -161,6 +162,12 @@ class Plan:
     @property
     def d(self):
         return len(self.shape)
+
+    @property
+    def massed(self):
+        """SEM and generic plans: H_k = K_k + F_k is self-adjoint in the mass
+        inner product (m non-empty); FD plans use the Euclidean one."""
+        return len(self.m) > 0
 
     @property
     def N(self):
@@ -246,6 +253,71 @@ def sem_nodes(k: int, n_cells: int, L: float) -> np.ndarray:
     return sem_axis(k, n_cells, L)[0]
 
 
+# --------------------------------------------------------------------------
+# Generic per-axis operators (Appendix app:hermite: the solver needs only a
+# diagonalisable 1D operator per axis); Hermite spectral collocation
+# --------------------------------------------------------------------------
+
+def hermite_functions(kmax: int, x: np.ndarray) -> np.ndarray:
+    """Rows 0..kmax: the normalised Hermite functions psi_k(x) by the three-term
+    recurrence psi_{k+1} = sqrt(2/(k+1)) x psi_k - sqrt(k/(k+1)) psi_{k-1},
+    psi_0 = pi^{-1/4} exp(-x^2/2) (which underflows for |x| beyond about 37)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros((kmax + 1,) + x.shape)
+    out[0] = np.pi ** -0.25 * np.exp(-0.5 * x * x)
+    if kmax >= 1:
+        out[1] = np.sqrt(2.0) * x * out[0]
+    for k in range(1, kmax):
+        out[k + 1] = np.sqrt(2.0 / (k + 1)) * x * out[k] - np.sqrt(k / (k + 1.0)) * out[k - 1]
+    return out
+
+
+def hermite_axis(n: int):
+    """(x, m, K) of n-point Hermite spectral collocation on the real line
+    (Appendix app:hermite).  Nodes: eigenvalues of the symmetric tridiagonal
+    J with zero diagonal and J[k-1, k] = sqrt(k/2) (numpy's eigvalsh).
+    D[i, j] = psi_{n-1}(x_i) / (psi_{n-1}(x_j) (x_i - x_j)), D[i, i] = 0, and
+    K = -D^2.  m[j] = 1 / (n psi_{n-1}(x_j)^2), the Gauss weights of the
+    Hermite functions, in which K is self-adjoint (diag(m) K symmetric)."""
+    n = int(n)
+    J = np.diag(np.sqrt(np.arange(1, n) / 2.0), 1)
+    x = np.linalg.eigvalsh(J + J.T)
+    psi = hermite_functions(n - 1, x)[n - 1]
+    D = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                D[i, j] = psi[i] / (psi[j] * (x[i] - x[j]))
+    K = -(D @ D)
+    m = 1.0 / (n * psi * psi)
+    return x, m, K
+
+
+def make_plan_general(K_list, m_list, f_list, x_list=None) -> Plan:
+    """Plan of arbitrary per-axis operators H_k = K_k + diag(f_k), with K_k
+    self-adjoint in the weights m_k (diag(m_k) K_k symmetric; None = unit
+    weights).  As for SEM, the symmetric M^{1/2} H_k M^{-1/2} is diagonalised
+    (Jacobi) and T = M^{-1/2} Q, T^{-1} = Q^T M^{1/2}."""
+    K_list = [np.ascontiguousarray(K, dtype=np.float64) for K in K_list]
+    shape = tuple(K.shape[0] for K in K_list)
+    f_list = [np.ascontiguousarray(f, dtype=np.float64) for f in f_list]
+    m_list = [np.ones(K.shape[0]) if m is None else np.ascontiguousarray(m, dtype=np.float64)
+              for K, m in zip(K_list, m_list)]
+    p = Plan(shape=shape, L=float("nan"), f=f_list)
+    for a, (K, m, f) in enumerate(zip(K_list, m_list, f_list)):
+        sq = np.sqrt(m)
+        A = sq[:, None] * K / sq[None, :] + np.diag(f)
+        w, V = jacobi_eigh(0.5 * (A + A.T))
+        p.h.append(float("nan"))
+        p.Q.append(V)
+        p.lam.append(w)
+        p.m.append(m)
+        p.K.append(K)
+        p.x.append(np.arange(K.shape[0], dtype=np.float64) if x_list is None
+                   else np.ascontiguousarray(x_list[a], dtype=np.float64))
+    return p
+
+
 def make_plan_sem(k: int, cells, L, f_list) -> Plan:
     """Q^k SEM plan: H_k = M^{-1} S + F = M^{-1/2} (M^{-1/2} S M^{-1/2} + F) M^{1/2}
     (eq. (eigen_decomp)); the symmetric middle factor is diagonalised by Jacobi."""
@@ -297,7 +369,7 @@ def apply_inverse(plan: Plan, b: np.ndarray, sigma: float) -> np.ndarray:
     """u = (H1 + sigma I)^{-1} b by the four-step solve (real FP64).  For SEM,
     T^{-1} = Q^T M^{1/2} and T = M^{-1/2} Q: the orthogonal solve between the
     two diagonal mass scalings."""
-    if plan.sem_k:
+    if plan.massed:
         b = np.asarray(b, dtype=np.float64).reshape(plan.shape) * _mass_root(plan, 0.5)
         return _apply_inverse_q(plan, b, sigma) * _mass_root(plan, -0.5)
     return _apply_inverse_q(plan, b, sigma)
@@ -314,7 +386,7 @@ def _apply_inverse_q(plan: Plan, b: np.ndarray, sigma: float) -> np.ndarray:
 
 def apply_exp(plan: Plan, psi: np.ndarray, tau: float) -> np.ndarray:
     """psi' = exp(-i tau H1) psi (eq. (exact_prop)), complex128; SEM as apply_inverse."""
-    if plan.sem_k:
+    if plan.massed:
         x = np.asarray(psi, dtype=np.complex128).reshape(plan.shape) * _mass_root(plan, 0.5)
         return _apply_exp_q(plan, x, tau) * _mass_root(plan, -0.5)
     return _apply_exp_q(plan, psi, tau)
@@ -349,7 +421,7 @@ def operator_apply(plan: Plan, u: np.ndarray, V2=None, sigma: float = 0.0) -> np
     """(H1 + diag V2 + sigma I) u of eq. (general_system): the stencil for FD
     plans; for SEM plans sum_k (I x .. x K_k x .. x I) u by mode products with
     the dense K_k = M_k^{-1} S_k, plus (sum_k f_k + V2 + sigma) u."""
-    if not plan.sem_k:
+    if not plan.massed:
         return stencil_apply(plan, u, V2, sigma)
     u = np.asarray(u).reshape(plan.shape)
     out = np.zeros_like(u)
@@ -368,7 +440,7 @@ def dense_operator(plan: Plan, V2=None, sigma: float = 0.0) -> np.ndarray:
     """Dense N x N matrix of H1 + diag V2 + sigma I: from the stencil rule for FD
     plans; for SEM plans the Kronecker sum of eq. (general_system) assembled
     with np.kron from the per-axis K_k + F_k."""
-    if plan.sem_k:
+    if plan.massed:
         N = plan.N
         H = np.zeros((N, N))
         for k in range(plan.d):
@@ -433,7 +505,7 @@ def inner(plan: Plan, x: np.ndarray, y: np.ndarray) -> float:
     """Inner product in which H1 is self-adjoint: Euclidean for FD plans, the
     mass-weighted sum_p (prod_k m_k) x_p y_p for SEM plans (H_k = M^{-1} S + F
     is symmetric with respect to M, not in the plain dot product)."""
-    if plan.sem_k:
+    if plan.massed:
         return float(np.sum(_mass_root(plan, 1.0) * np.asarray(x).reshape(plan.shape)
                             * np.asarray(y).reshape(plan.shape)))
     return float(np.vdot(x, y))
@@ -484,7 +556,7 @@ def separable_ground_state(plan: Plan) -> np.ndarray:
     u = np.ones(())
     for k in range(plan.d):
         v = plan.Q[k][:, 0]
-        if plan.sem_k:
+        if plan.massed:
             v = v / np.sqrt(plan.m[k])
         u = np.multiply.outer(u, v)
     return np.ascontiguousarray(u / norm(plan, u))
@@ -666,7 +738,7 @@ def qhop_propagate(plan: Plan, V2, psi0, dt, nsteps, M: int, yoshida: bool = Fal
 def l2_weights(plan: Plan) -> np.ndarray:
     """Quadrature weights of the discrete L^2 inner product on the grid:
     prod_k m_k (Gauss-Lobatto mass) for SEM plans, h^d for FD plans."""
-    if plan.sem_k:
+    if plan.massed:
         return _mass_root(plan, 1.0)
     return np.full(plan.shape, float(np.prod(plan.h)))
 

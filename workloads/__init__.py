@@ -61,6 +61,17 @@ def f_test_potential(n: int, L: float, c: float, x=None) -> np.ndarray:
     return 1600.0 * np.sin(np.pi * x / 4.0) ** 2 + c * x * x
 
 
+def rational_sine(c: float, t: np.ndarray):
+    """(g, g'') for g(t) = sin(c (t + 1)) / (1 + t^2): one factor of the exact
+    solution of the Hermite test problem on R^3 (Appendix app:hermite)."""
+    t = np.asarray(t, dtype=np.float64)
+    s, sp, spp = np.sin(c * (t + 1)), c * np.cos(c * (t + 1)), -c * c * np.sin(c * (t + 1))
+    q, qp = 1.0 + t * t, 2.0 * t
+    g = s / q
+    gpp = spp / q - 2.0 * sp * qp / q**2 - 2.0 * s / q**2 + 2.0 * s * qp**2 / q**3
+    return g, gpp
+
+
 # ---- random data -------------------------------------------------------------
 
 def rhs_normal(shape, seed: int) -> np.ndarray:
