@@ -104,7 +104,7 @@ int ts_destroy(ts_plan* plan);
 
 /* Half-extent passes on reflection-symmetric axes.  When f_k is symmetric
  * (f_k(x_j) = f_k(x_{n-1-j}) to 1e-13 relative) every eigenvector of H_k is
- * even or odd; the passes on that axis (n_k >= 64, FP64 and FP32 transforms)
+ * even or odd; the passes on that axis (n_k >= 64, every transform precision)
  * then fold x into x_i +- x_{n-1-i} and contract half the extent against the
  * even and odd halves of the factor (half the MFMA work), with a butterfly
  * after each backward pass.  The result is the same up to rounding.
@@ -117,7 +117,8 @@ int ts_set_fold(ts_plan* plan, int enable);
  * T_axis (spectral index in the plan's internal order, see ts_set_fold).
  * For measuring and checking the pass kernels on their own.  in, out: device
  * arrays of the grid (must not alias); dtype any of ts_dtype; prec FP64 (FP64
- * data) or FP32.  Errors: TS_ERR_INVALID, TS_ERR_DEVICE. */
+ * data), FP32, or BF16 (operands rounded to BF16, FP32 accumulation, result
+ * stored in the data type).  Errors: TS_ERR_INVALID, TS_ERR_DEVICE. */
 int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out, int dtype, int prec,
                  void* hip_stream);
 int ts_fold_axes(const ts_plan* plan, int* folded);
@@ -142,6 +143,43 @@ int ts_fold_axes(const ts_plan* plan, int* folded);
  * Errors: TS_ERR_INVALID, TS_ERR_NONFINITE, TS_ERR_NOMEM, TS_ERR_DEVICE. */
 int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* const* f, double sigma,
                  ts_plan** out);
+
+/* Plan of arbitrary per-axis operators (Appendix app:hermite: the solver needs
+ * only a diagonalisable 1D operator K_a per axis).  Per axis a:
+ *   K[a]: host FP64 n[a] x n[a], row-major: the 1D operator without the
+ *         potential (for instance -D^2 of ts_hermite_axis)
+ *   m[a]: host FP64 n[a] positive weights in which K[a] is self-adjoint
+ *         (diag(m) K symmetric to 1e-10 relative); m == NULL or m[a] == NULL
+ *         means unit weights (K symmetric)
+ *   x[a]: host FP64 n[a] nodes, kept for reporting; x may be NULL
+ *   f[a]: host FP64 n[a], the separable potential at the nodes
+ * H_a = K_a + diag(f_a) is diagonalised through the symmetric
+ * M^{1/2} H_a M^{-1/2} = Q Lambda Q^T (host FP64 Householder and QL), so
+ * T = M^{-1/2} Q and T^{-1} = Q^T M^{1/2}, exactly as for ts_setup_sem; every
+ * entry point then works on the nodal values, the solvers in the inner
+ * product sum_p (prod_a m_a) x_p y_p.  The operator apply (PCG, GPE flows)
+ * reads each K_a as a band whose half-width is the largest |i - j| with
+ * K_a[i][j] != 0 over all axes (a dense K is a band of half-width n - 1).
+ * An axis whose K, m and f are reflection-symmetric (to 1e-11 / 1e-13
+ * relative) gets the half-extent passes (ts_set_fold).  The plan has no
+ * interval [-L, L]: ts_interpolate and the multi-level iteration reject it.
+ * n[a] in [1, 8192].  The caller's arrays are copied; nothing is kept.
+ * Errors: TS_ERR_INVALID (also for K not self-adjoint in m),
+ * TS_ERR_NONFINITE, TS_ERR_NOMEM, TS_ERR_DEVICE. */
+int ts_setup_general(int d, const int64_t* n, const double* const* K, const double* const* m,
+                     const double* const* x, const double* const* f, double sigma, ts_plan** out);
+
+/* Host: n-point Hermite spectral collocation on the real line (Appendix
+ * app:hermite), the input of ts_setup_general for unbounded domains.
+ *   x (n): the Gauss-Hermite nodes, the zeros of the degree-n Hermite
+ *          polynomial (ascending, x[n-1-j] = -x[j] exactly)
+ *   m (n): the Gauss weights of the Hermite functions, 1 / (n psi_{n-1}(x_j)^2)
+ *   K (n x n, row-major): -D^2, with the differentiation matrix of the
+ *          Hermite functions D_ij = psi_{n-1}(x_i) / (psi_{n-1}(x_j) (x_i - x_j)),
+ *          D_ii = 0; diag(m) K is symmetric
+ * psi_{n-1} comes from a rescaled three-term recurrence, so the outer nodes
+ * do not underflow.  n in [1, 8192].  Errors: TS_ERR_INVALID. */
+int ts_hermite_axis(int64_t n, double* x, double* m, double* K);
 
 /* Host: the k cells - 1 interior nodes of Q^k SEM on [-L, L] (ascending),
  * the points at which f_a and V2 are sampled.  x: host array of k cells - 1

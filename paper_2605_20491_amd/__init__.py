@@ -57,6 +57,10 @@ def lib():
             "ts_setup_sem": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
             "ts_sem_nodes": [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _dp],
+            "ts_setup_general": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_dp),
+                                 ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.c_double,
+                                 ctypes.POINTER(_vp)],
+            "ts_hermite_axis": [ctypes.c_int64, _dp, _dp, _dp],
             "ts_mass": [_vp, ctypes.c_int, _dp],
             "ts_apply_inverse": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_apply_inverse_shift": [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
@@ -208,6 +212,39 @@ def ts_setup_sem(k: int, cells, L: float, f_list, sigma: float) -> Plan:
     h = _vp()
     _check(lib().ts_setup_sem(d, cc, int(k), float(L), fp, float(sigma), ctypes.byref(h)), "ts_setup_sem")
     return Plan(h, shape, L, sigma)
+
+
+def ts_setup_general(K_list, m_list, f_list, sigma: float, x_list=None) -> Plan:
+    """Plan of arbitrary per-axis operators: K_list[a] (n x n) self-adjoint in
+    the weights m_list[a] (None: unit weights), f_list[a] the potential at the
+    nodes x_list[a] (optional).  The plan has no interval: its L is 0."""
+    d = len(K_list)
+    Ks = [np.ascontiguousarray(K, dtype=np.float64) for K in K_list]
+    shape = tuple(K.shape[0] for K in Ks)
+    if any(K.ndim != 2 or K.shape[0] != K.shape[1] for K in Ks):
+        raise ValueError("every K must be square")
+    ms = [None if m is None else np.ascontiguousarray(m, dtype=np.float64) for m in (m_list or [None] * d)]
+    fs = [np.ascontiguousarray(f, dtype=np.float64) for f in f_list]
+    xs = None if x_list is None else [np.ascontiguousarray(x, dtype=np.float64) for x in x_list]
+    for a, n in enumerate(shape):
+        if fs[a].shape != (n,) or (ms[a] is not None and ms[a].shape != (n,)) or (xs is not None and xs[a].shape != (n,)):
+            raise ValueError("axis %d: f, m and x must hold n = %d samples" % (a, n))
+    nn = (ctypes.c_int64 * d)(*shape)
+    Kp = (_dp * d)(*[_dptr(K) for K in Ks])
+    mp = (_dp * d)(*[_dptr(m) if m is not None else None for m in ms])
+    fp = (_dp * d)(*[_dptr(f) for f in fs])
+    xp = None if xs is None else (_dp * d)(*[_dptr(x) for x in xs])
+    h = _vp()
+    _check(lib().ts_setup_general(d, nn, Kp, mp, xp, fp, float(sigma), ctypes.byref(h)), "ts_setup_general")
+    return Plan(h, shape, 0.0, sigma)
+
+
+def ts_hermite_axis(n: int):
+    """(x, m, K) of n-point Hermite spectral collocation (host)."""
+    n = int(n)
+    x, m, K = np.empty(n), np.empty(n), np.empty((n, n))
+    _check(lib().ts_hermite_axis(n, _dptr(x), _dptr(m), _dptr(K)), "ts_hermite_axis")
+    return x, m, K
 
 
 def ts_sem_nodes(k: int, cells: int, L: float) -> np.ndarray:

@@ -54,7 +54,7 @@ GpeGrid gpe_grid(const ts_plan* p) {
     g.ih2[k] = F.ih2;
     g.band[k] = F.band;
   }
-  g.bw = p->sem_k ? p->ax[0]->bw : 0;
+  g.bw = p->massed ? p->ax[0]->bw : 0;
   return g;
 }
 

@@ -11,6 +11,8 @@
 // Q), stored in HBM as BF16 with the same zero padding.  Data tiles are
 // converted to BF16 on the way into LDS (FP64 -> FP32 -> BF16, each round to
 // nearest even); the column operand is transposed there.
+#include <algorithm>
+
 #include "modeprod_common.h"
 #include "ts_internal.h"
 
@@ -59,7 +61,17 @@ __device__ __forceinline__ void load_vec8(const uint16_t* src, uint16_t* dst) {
   }
 }
 
-template <typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI>
+template <typename TIn> __device__ __forceinline__ TIn fold_add(TIn x, TIn y, bool sub) {
+  return sub ? x - y : x + y;
+}
+template <> __device__ __forceinline__ uint16_t fold_add<uint16_t>(uint16_t x, uint16_t y, bool sub) {
+  const float r = sub ? bf16_to_f32(x) - bf16_to_f32(y) : bf16_to_f32(x) + bf16_to_f32(y);
+  return f32_to_bf16(r);
+}
+
+// FOLD as in modeprod.hip: 1 = forward half-extent pass (x_i +- x_{n-1-i} folded while
+// loading), 2 = backward half-extent pass (halves written apart, butterfly afterwards).
+template <typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD>
 __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][LDK];
@@ -81,10 +93,21 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
     ntile = rest % a.nt;
     p = rest / a.nt;
   }
-  const int64_t m0 = mtile * BM, n0 = ntile * BN;
-  const int64_t K = a.n;
-  const TIn* X = (const TIn*)a.X;
+  bool odd = false;
+  int64_t K = a.n;
   const uint16_t* S = (const uint16_t*)a.S;
+  int64_t ldS = a.ld;
+  if (FOLD) {
+    int64_t& split = ROWS ? ntile : mtile;
+    odd = split >= a.te;
+    if (odd) split -= a.te;
+    K = FOLD == 1 ? (odd ? a.hh : a.hh + a.cc) : (odd ? a.no : a.ne);
+    S = (const uint16_t*)(odd ? a.So : a.Se);
+    ldS = a.fld;
+  }
+  const int64_t koff = (FOLD == 2 && odd) ? a.ne : 0;
+  const int64_t m0 = mtile * BM, n0 = ntile * BN;
+  const TIn* X = (const TIn*)a.X;
 
   // resident factor tile: 128 rows (free index) x 64 k; 4 x 16 bytes per thread
   uint4 rres0, rres1, rres2, rres3;
@@ -96,7 +119,7 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
   auto load_tile = [&](int64_t k0) {
     {
       const int row = t >> 1, half = t & 1;  // 32 k per thread
-      const uint4* src = (const uint4*)(S + (f0 + row) * a.ld + k0 + 32 * half);
+      const uint4* src = (const uint4*)(S + (f0 + row) * ldS + k0 + 32 * half);
       rres0 = src[0];
       rres1 = src[1];
       rres2 = src[2];
@@ -106,42 +129,104 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
       // X[p] rows k0 + 4*kq .. +3, columns n0 + 8*oc .. +7
       const int oc = t & 15, kq = t >> 4;
       const int64_t col0 = n0 + 8 * oc;
-      const bool vec = base_aligned && (a.R % 8 == 0) && (col0 + 8 <= a.R);
+      const bool vec = base_aligned && (a.R % (16 / (int)sizeof(TIn)) == 0) && (col0 + 8 <= a.R);
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
         const int64_t k = k0 + 4 * kq + rr;
-        const TIn* src = X + (p * a.n + k) * a.R + col0;
+        const TIn* src = X + (p * a.n + koff + k) * a.R + col0;
+        const TIn* mir = X + (p * a.n + (a.n - 1 - k)) * a.R + col0;
+        const bool fold_k = FOLD == 1 && k < a.hh;
         if (k < K && vec) {
           load_vec8(src, &rdat[rr * 8]);
+          if (fold_k) {
+            TIn w[8];
+            load_vec8(mir, w);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) rdat[rr * 8 + c] = fold_add(rdat[rr * 8 + c], w[c], odd);
+          }
         } else {
 #pragma unroll
-          for (int c = 0; c < 8; ++c) rdat[rr * 8 + c] = (k < K && col0 + c < a.R) ? src[c] : (TIn)0;
+          for (int c = 0; c < 8; ++c) {
+            TIn v = (k < K && col0 + c < a.R) ? src[c] : (TIn)0;
+            if (fold_k && col0 + c < a.R) v = fold_add(v, mir[c], odd);
+            rdat[rr * 8 + c] = v;
+          }
         }
       }
     } else if (!CPLX) {
       const int row = t >> 1, half = t & 1;
       const int64_t m = m0 + row;
       const int64_t kb = k0 + 32 * half;
-      const TIn* src = X + m * a.n + kb;
-      if (base_aligned && m < a.M && kb + 32 <= K && (a.n % 8) == 0) {
+      const TIn* rowp = X + m * a.n;
+      const TIn* src = rowp + koff + kb;
+      const int64_t VW = 16 / (int64_t)sizeof(TIn);
+      if (base_aligned && m < a.M && kb + 32 <= K && (a.n % VW) == 0 && (koff % VW) == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) load_vec8(src + 8 * c, &rdat[8 * c]);
+        if (FOLD == 1 && kb + 32 <= a.hh) {
+          // mirror elements n-1-kb-31 .. n-1-kb, reversed
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            TIn w[8];
+            load_vec8(rowp + (a.n - 32 - kb) + 8 * c, w);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) rdat[31 - 8 * c - e] = fold_add(rdat[31 - 8 * c - e], w[e], odd);
+          }
+        } else if (FOLD == 1) {
+#pragma unroll
+          for (int c = 0; c < 32; ++c)
+            if (kb + c < a.hh) rdat[c] = fold_add(rdat[c], rowp[a.n - 1 - kb - c], odd);
+        }
       } else {
 #pragma unroll
-        for (int c = 0; c < 32; ++c) rdat[c] = (m < a.M && kb + c < K) ? src[c] : (TIn)0;
+        for (int c = 0; c < 32; ++c) {
+          TIn v = (m < a.M && kb + c < K) ? src[c] : (TIn)0;
+          if (FOLD == 1 && m < a.M && kb + c < a.hh) v = fold_add(v, rowp[a.n - 1 - kb - c], odd);
+          rdat[c] = v;
+        }
       }
     } else {
       // rows 2p (re) and 2p+1 (im): p = pl, 16 consecutive k, both components
       const int pl = t >> 2, quarter = t & 3;
       const int64_t pp = (m0 >> 1) + pl;
       const int64_t kb = k0 + 16 * quarter;
-      const TIn* src = X + ((pp * a.n + kb) << 1);
-      if (base_aligned && pp < a.P && kb + 16 <= K && (a.n % 8) == 0) {
+      const TIn* rowp = X + ((pp * a.n) << 1);
+      const TIn* src = rowp + ((koff + kb) << 1);
+      // 2n values per row: 16-byte alignment of every row start needs 2n % VW == 0
+      const int64_t VW = 16 / (int64_t)sizeof(TIn);
+      if (base_aligned && pp < a.P && kb + 16 <= K && ((2 * a.n) % VW) == 0 && ((2 * koff) % VW) == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) load_vec8(src + 8 * c, &rdat[8 * c]);
+        if (FOLD == 1 && kb + 16 <= a.hh) {
+          // complex elements n-1-kb-15 .. n-1-kb, reversed
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            TIn w[8];
+            load_vec8(rowp + ((a.n - 16 - kb) << 1) + 8 * c, w);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int d = 15 - 4 * c - e;  // complex element within this thread's 16
+              rdat[2 * d] = fold_add(rdat[2 * d], w[2 * e], odd);
+              rdat[2 * d + 1] = fold_add(rdat[2 * d + 1], w[2 * e + 1], odd);
+            }
+          }
+        } else if (FOLD == 1) {
+#pragma unroll
+          for (int d = 0; d < 16; ++d)
+            if (kb + d < a.hh) {
+              const int64_t mk = (a.n - 1 - kb - d) << 1;
+              rdat[2 * d] = fold_add(rdat[2 * d], rowp[mk], odd);
+              rdat[2 * d + 1] = fold_add(rdat[2 * d + 1], rowp[mk + 1], odd);
+            }
+        }
       } else {
 #pragma unroll
-        for (int c = 0; c < 32; ++c) rdat[c] = (pp < a.P && kb + (c >> 1) < K) ? src[c] : (TIn)0;
+        for (int c = 0; c < 32; ++c) {
+          const int64_t k = kb + (c >> 1);
+          TIn v = (pp < a.P && k < K) ? src[c] : (TIn)0;
+          if (FOLD == 1 && pp < a.P && k < a.hh) v = fold_add(v, rowp[((a.n - 1 - k) << 1) + (c & 1)], odd);
+          rdat[c] = v;
+        }
       }
     }
   };
@@ -232,31 +317,108 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
         double v = (double)acc[i][j][r];
         double partner = 0.0;
         if (EPI == (int)Epi::Exp) partner = __shfl_xor(v, 1);
-        if (ROWS) store_rows<TOut, CPLX>(a, Y, m, col, v);
-        else store_cols<TOut, CPLX, EPI>(a, Y, p, m, col, v, partner);
+        if (FOLD) {
+          const int64_t loc = ROWS ? col : m;
+          const int64_t cnt = FOLD == 1 ? (odd ? a.no : a.ne) : (odd ? a.hh : a.hh + a.cc);
+          if (loc >= cnt) continue;
+          const int64_t dst = FOLD == 1 ? (odd ? a.ne + loc : loc) : (odd ? a.n - 1 - loc : loc);
+          if (ROWS) store_rows<TOut, CPLX>(a, Y, m, dst, v);
+          else store_cols<TOut, CPLX, EPI>(a, Y, p, dst, col, v, partner);
+        } else if (ROWS) {
+          store_rows<TOut, CPLX>(a, Y, m, col, v);
+        } else {
+          store_cols<TOut, CPLX, EPI>(a, Y, p, m, col, v, partner);
+        }
       }
+}
+
+template <typename TIn, typename TOut, int FOLD>
+hipError_t launch_bf16_fold(const KArgs& a, const PassArgs& pa, hipStream_t st) {
+  dim3 grid((unsigned)a.nblocks), block(NT);
+  if (a.rows) {
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, true, 0, FOLD>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, false, 0, FOLD>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Exp) {
+    if (!pa.cplx) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Exp, FOLD>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Inv) {
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, 0, FOLD>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+// Butterfly of a backward half-extent pass, x_i, x_{n-1-i} <- x_i + x_{n-1-i}, x_i - x_{n-1-i}
+// for i < hh over [P][n][R]; BF16 values are combined in FP32 and rounded once.
+__device__ __forceinline__ void butterfly(double& x, double& y) {
+  const double s = x + y, d = x - y;
+  x = s;
+  y = d;
+}
+__device__ __forceinline__ void butterfly(float& x, float& y) {
+  const float s = x + y, d = x - y;
+  x = s;
+  y = d;
+}
+__device__ __forceinline__ void butterfly(uint16_t& x, uint16_t& y) {
+  const float a = bf16_to_f32(x), b = bf16_to_f32(y);
+  x = f32_to_bf16(a + b);
+  y = f32_to_bf16(a - b);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_unfold_any(T* Y, int64_t P, int64_t n, int64_t R, int64_t hh) {
+  const int64_t total = P * hh * R;
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t r = e % R;
+    const int64_t q = e / R;
+    const int64_t i = q % hh, p = q / hh;
+    T* lo = Y + (p * n + i) * R + r;
+    T* hi = Y + (p * n + (n - 1 - i)) * R + r;
+    T x = *lo, y = *hi;
+    butterfly(x, y);
+    *lo = x;
+    *hi = y;
+  }
 }
 
 template <typename TIn, typename TOut>
 hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
   KArgs a{};
-  fill_kargs(pa, a, pa.forward ? (const void*)pa.fac->QT16 : (const void*)pa.fac->Q16, BM, BN);
+  const AxisFactor* F = pa.fac;
+  fill_kargs(pa, a, pa.forward ? (const void*)F->QT16 : (const void*)F->Q16, BM, BN);
+  const int fold = pa.fold ? (pa.forward ? 1 : 2) : 0;
+  if (fold) {
+    a.ne = F->ne;
+    a.no = F->no;
+    a.hh = F->hh;
+    a.cc = F->cc;
+    a.fld = F->fkp;
+    a.Se = pa.forward ? (const void*)F->Fe16 : (const void*)F->Be16;
+    a.So = pa.forward ? (const void*)F->Fo16 : (const void*)F->Bo16;
+    const int64_t me = fold == 1 ? F->ne : F->hh + F->cc, mo = fold == 1 ? F->no : F->hh;
+    const int64_t tb = a.rows ? BN : BM;
+    a.te = (me + tb - 1) / tb;
+    const int64_t tsplit = a.te + (mo + tb - 1) / tb;
+    if (a.rows) {
+      a.nt = tsplit;
+      a.nblocks = a.mt * a.nt;
+    } else {
+      a.mt = tsplit;
+      a.nblocks = a.mt * a.nt * pa.P;
+    }
+  }
   if (a.nblocks <= 0) return hipSuccess;
   if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)a.nblocks), block(NT);
-  const bool rows = a.rows;
-  if (rows) {
-    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, true, 0>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, false, 0>), grid, block, 0, st, a);
-  } else if (pa.epi == Epi::Exp) {
-    if (!pa.cplx) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Exp>), grid, block, 0, st, a);
-  } else if (pa.epi == Epi::Inv) {
-    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Inv>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, (int)Epi::Inv>), grid, block, 0, st, a);
-  } else {
-    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, 0>), grid, block, 0, st, a);
-  }
+  hipError_t e;
+  if (fold == 1) e = launch_bf16_fold<TIn, TOut, 1>(a, pa, st);
+  else if (fold == 2) e = launch_bf16_fold<TIn, TOut, 2>(a, pa, st);
+  else e = launch_bf16_fold<TIn, TOut, 0>(a, pa, st);
+  if (e != hipSuccess || fold != 2 || F->hh == 0) return e;
+  const int64_t total = pa.P * F->hh * pa.R;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL((k_unfold_any<TOut>), dim3(blocks), dim3(256), 0, st, (TOut*)pa.Y, pa.P, pa.n, pa.R, F->hh);
   return hipGetLastError();
 }
 

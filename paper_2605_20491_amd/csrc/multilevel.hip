@@ -120,6 +120,7 @@ inline unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>((n + kT
 int interpolate_run(const ts_plan* c, const ts_plan* f, const double* uc, double* uf, hipStream_t st) {
   if (!c || !f || !uc || !uf) { set_error("null argument"); return TS_ERR_INVALID; }
   if (c->d != f->d) { set_error("plans differ in dimension"); return TS_ERR_INVALID; }
+  if (!(c->L > 0.0) || !(f->L > 0.0)) { set_error("interpolation needs FD or SEM plans (nodes on [-L, L])"); return TS_ERR_INVALID; }
   if (std::fabs(c->L - f->L) > 1e-12 * c->L) { set_error("plans differ in L"); return TS_ERR_INVALID; }
   const int d = c->d;
   Scratch S;
@@ -176,7 +177,7 @@ int separable_ground_state(const ts_plan* p, double* u, hipStream_t st) {
     std::vector<double> v(F.n);
     for (int64_t i = 0; i < F.n; ++i) {
       const double q = F.Q_h[(size_t)(i * F.n)];
-      v[i] = p->sem_k ? q / std::sqrt(F.m_h[i]) : q;
+      v[i] = p->massed ? q / std::sqrt(F.m_h[i]) : q;
     }
     double* dv = S.get<double>(F.n);
     if (!dv) { set_error("allocation failed"); return TS_ERR_NOMEM; }

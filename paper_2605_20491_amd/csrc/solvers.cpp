@@ -34,7 +34,7 @@ StencilArgs stencil_args(const ts_plan* p, const double* V2, double s, const dou
     a.f[k] = ax[k]->f;
     a.band[k] = ax[k]->band;
   }
-  a.bw = p->sem_k ? ax[0]->bw : 0;
+  a.bw = p->massed ? ax[0]->bw : 0;
   a.V2 = V2;
   a.s = s;
   a.u = u;
@@ -42,11 +42,11 @@ StencilArgs stencil_args(const ts_plan* p, const double* V2, double s, const dou
   return a;
 }
 
-// SEM plans: the solvers run on the symmetric form M^{-1/2} S M^{-1/2} + F in
+// SEM and generic plans: the solvers run on the symmetric form M^{-1/2} S M^{-1/2} + F in
 // the variables M^{1/2} u (Euclidean inner products there are the mass inner
 // products of u).  Scale x by M^{1/2} (up) or M^{-1/2} (down); no-op for FD.
 hipError_t mass_scale(const ts_plan* p, const double* x, double* y, bool up, hipStream_t st) {
-  if (!p->sem_k) {
+  if (!p->massed) {
     if (x != y) return hipMemcpyAsync(y, x, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToDevice, st);
     return hipSuccess;
   }
@@ -120,7 +120,7 @@ class PcgTask : public Task {
   PcgTask(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f, double* x, double rtol,
           int maxit, int prec, bool scale_io, ExecCtx& c)
       : p_(p), V2_(V2), s_op_(s_op), s_pc_(s_pc), f_(f), x_(x), rtol_(rtol), maxit_(maxit), prec_(prec),
-        scale_(scale_io && p->sem_k), c_(c) {}
+        scale_(scale_io && p->massed), c_(c) {}
 
   int start(hipStream_t st) override {
     TS_RC(solver_buffers(c_, p_, scale_ ? 5 : 4, b_));
@@ -236,7 +236,7 @@ class RefineTask : public Task {
  public:
   RefineTask(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, bool scale_io,
              ExecCtx& c)
-      : p_(p), f_(f), u_(u), inner_(inner), rtol_(rtol), maxit_(maxit), scale_(scale_io && p->sem_k), c_(c) {}
+      : p_(p), f_(f), u_(u), inner_(inner), rtol_(rtol), maxit_(maxit), scale_(scale_io && p->massed), c_(c) {}
 
   int start(hipStream_t st) override {
     // vector 4 holds the scaled right-hand side: the CG fallback uses 0..3

@@ -38,6 +38,10 @@ AxisFactor::~AxisFactor() {
   hipFree(Fo32);
   hipFree(Be32);
   hipFree(Bo32);
+  hipFree(Fe16);
+  hipFree(Fo16);
+  hipFree(Be16);
+  hipFree(Bo16);
   hipFree(mass);
   hipFree(msq);
   hipFree(imsq);
@@ -269,12 +273,15 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
       }
     double** d64[4] = {&F.Fe64, &F.Fo64, &F.Be64, &F.Bo64};
     float** d32[4] = {&F.Fe32, &F.Fo32, &F.Be32, &F.Bo32};
+    uint16_t** d16[4] = {&F.Fe16, &F.Fo16, &F.Be16, &F.Bo16};
     const size_t cnt = (size_t)(kp * kp);
     for (int q = 0; q < 4 && e == hipSuccess; ++q) {
       e = hipMalloc(d64[q], sizeof(double) * cnt);
       if (e == hipSuccess) e = hipMalloc(d32[q], sizeof(float) * cnt);
+      if (e == hipSuccess) e = hipMalloc(d16[q], sizeof(uint16_t) * cnt);
       if (e == hipSuccess) e = hipMemcpyAsync(*d64[q], H[q].data(), sizeof(double) * cnt, hipMemcpyHostToDevice, st);
       if (e == hipSuccess) e = launch_cast_f64_to_f32(*d64[q], *d32[q], (int64_t)cnt, st);
+      if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(*d64[q], *d16[q], kp, st);
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -324,9 +331,67 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
   return TS_OK;
 }
 
-// Q^k SEM axis (eq. (eigen_decomp)): Q diagonalises A = M^{-1/2} S M^{-1/2} + F.
-// sym: factors (Q, Q^T), band of M^{-1/2} S M^{-1/2}, mass roots.
-// phys: T^{-1} = Q^T M^{1/2}, T = M^{-1/2} Q, band of M^{-1} S.
+// Axis of a mass-weighted operator H = K + diag(f) with K self-adjoint in the
+// weights m (diag(m) K symmetric; Q^k SEM: K = M^{-1} S).  Q diagonalises the
+// symmetric A = M^{1/2} K M^{-1/2} + F (eq. (eigen_decomp)).
+//   A: dense M^{1/2} K M^{-1/2} (row-major; f is added here)
+//   bsym, bphys: bands [n][2 bw + 1] of M^{1/2} K M^{-1/2} and of K
+//   reflect: K, m and f are reflection-symmetric (even/odd eigensolve, fold)
+// sym: factors (Q, Q^T), band bsym, mass roots; the solvers use it.
+// phys: T^{-1} = Q^T M^{1/2}, T = M^{-1/2} Q, band bphys; the public applies use it.
+static int build_axis_massed(int64_t n, double L, std::vector<double>& A, const std::vector<double>& bsym,
+                             const std::vector<double>& bphys, int bw, const std::vector<double>& m,
+                             const std::vector<double>& x, const double* f, bool reflect,
+                             std::shared_ptr<AxisFactor>& phys, std::shared_ptr<AxisFactor>& sym) {
+  std::vector<double> ms(n);
+  for (int64_t i = 0; i < n; ++i) ms[i] = std::sqrt(m[i]);
+  for (int64_t i = 0; i < n; ++i) A[(size_t)(i * n + i)] += f[i];
+  for (int64_t i = 0; i < n; ++i)  // exact symmetry (the input is symmetric up to rounding)
+    for (int64_t j = 0; j < i; ++j) {
+      const double a = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
+      A[(size_t)(i * n + j)] = A[(size_t)(j * n + i)] = a;
+    }
+  auto S = std::make_shared<AxisFactor>();
+  S->n = n;
+  S->L = L;
+  S->lam_h.resize(n);
+  S->Q_h.resize((size_t)(n * n));
+  FoldPlan fp;
+  const bool split = n >= 2 && reflect;
+  const bool ok = split ? split_eig_dense(n, A, S->lam_h.data(), S->Q_h.data(), fp)
+                        : dense_sym_eig(n, A, S->lam_h.data(), S->Q_h.data());
+  if (!ok) {
+    set_error("symmetric eigensolver did not converge");
+    return TS_ERR_INVALID;
+  }
+  S->bw = bw;
+  S->m_h = m;
+  S->x_h = x;
+  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, m, true, fp);
+  if (rc) return rc;
+  auto P = std::make_shared<AxisFactor>();
+  P->n = n;
+  P->L = L;
+  P->lam_h = S->lam_h;
+  P->Q_h = S->Q_h;
+  P->bw = bw;
+  P->m_h = m;
+  P->x_h = x;
+  std::vector<double> Fwd((size_t)(n * n)), Bwd((size_t)(n * n));
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double q = S->Q_h[(size_t)(i * n + j)];
+      Fwd[(size_t)(i * n + j)] = ms[i] * q;   // (T^{-1})^T = M^{1/2} Q
+      Bwd[(size_t)(j * n + i)] = q / ms[i];   // T^T = Q^T M^{-1/2}
+    }
+  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, m, true, fp);
+  if (rc) return rc;
+  phys = P;
+  sym = S;
+  return TS_OK;
+}
+
+// Q^k SEM axis: K = M^{-1} S from the Gauss-Lobatto mass and stiffness band.
 static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::shared_ptr<AxisFactor>& phys,
                           std::shared_ptr<AxisFactor>& sym) {
   SemAxis ax;
@@ -343,51 +408,49 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
       bphys[(size_t)(i * w + t)] = sij / ax.m[i];
       A[(size_t)(i * n + j)] = sij / (ms[i] * ms[j]);
     }
-  for (int64_t i = 0; i < n; ++i) A[(size_t)(i * n + i)] += f[i];
-  for (int64_t i = 0; i < n; ++i)  // exact symmetry (S is symmetric up to the rounding of its entries)
-    for (int64_t j = 0; j < i; ++j) {
-      const double a = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
-      A[(size_t)(i * n + j)] = A[(size_t)(j * n + i)] = a;
-    }
-  auto S = std::make_shared<AxisFactor>();
-  S->n = n;
-  S->L = L;
-  S->lam_h.resize(n);
-  S->Q_h.resize((size_t)(n * n));
-  FoldPlan fp;
   // the mesh is symmetric; with symmetric f the operator is reflection-symmetric
-  const bool split = n >= 2 && symmetric_samples(n, f);
-  const bool ok = split ? split_eig_dense(n, A, S->lam_h.data(), S->Q_h.data(), fp)
-                        : dense_sym_eig(n, A, S->lam_h.data(), S->Q_h.data());
-  if (!ok) {
-    set_error("symmetric eigensolver did not converge");
-    return TS_ERR_INVALID;
+  return build_axis_massed(n, L, A, bsym, bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym);
+}
+
+// Generic axis from a dense K and weights m (NULL: unit weights); bw is the
+// band half-width of every axis of the plan (the largest over the axes).
+static int build_axis_general(int64_t n, const double* K, const double* m_in, const double* x_in, const double* f,
+                              int bw, std::shared_ptr<AxisFactor>& phys, std::shared_ptr<AxisFactor>& sym) {
+  std::vector<double> m(n, 1.0), x(n), ms(n);
+  if (m_in) std::memcpy(m.data(), m_in, sizeof(double) * (size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(m[i] > 0.0) || !std::isfinite(m[i])) { set_error("weights must be positive and finite"); return TS_ERR_INVALID; }
+    ms[i] = std::sqrt(m[i]);
+    x[i] = x_in ? x_in[i] : (double)i;
   }
-  S->bw = k;
-  S->m_h = ax.m;
-  S->x_h = ax.x;
-  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, ax.m, true, fp);
-  if (rc) return rc;
-  auto P = std::make_shared<AxisFactor>();
-  P->n = n;
-  P->L = L;
-  P->lam_h = S->lam_h;
-  P->Q_h = S->Q_h;
-  P->bw = k;
-  P->m_h = ax.m;
-  P->x_h = ax.x;
-  std::vector<double> Fwd((size_t)(n * n)), Bwd((size_t)(n * n));
+  const int64_t w = 2 * (int64_t)bw + 1;
+  std::vector<double> A((size_t)(n * n)), bsym((size_t)(n * w), 0.0), bphys((size_t)(n * w), 0.0);
+  double amax = 0.0, asym = 0.0, arefl = 0.0;
   for (int64_t i = 0; i < n; ++i)
     for (int64_t j = 0; j < n; ++j) {
-      const double q = S->Q_h[(size_t)(i * n + j)];
-      Fwd[(size_t)(i * n + j)] = ms[i] * q;   // (T^{-1})^T = M^{1/2} Q
-      Bwd[(size_t)(j * n + i)] = q / ms[i];   // T^T = Q^T M^{-1/2}
+      const double kij = K[(size_t)(i * n + j)];
+      if (!std::isfinite(kij)) { set_error("K has a non-finite entry"); return TS_ERR_NONFINITE; }
+      A[(size_t)(i * n + j)] = ms[i] * kij / ms[j];
+      amax = std::max(amax, std::fabs(A[(size_t)(i * n + j)]));
     }
-  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, ax.m, true, fp);
-  if (rc) return rc;
-  phys = P;
-  sym = S;
-  return TS_OK;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      asym = std::max(asym, std::fabs(A[(size_t)(i * n + j)] - A[(size_t)(j * n + i)]));
+      arefl = std::max(arefl, std::fabs(A[(size_t)(i * n + j)] - A[(size_t)((n - 1 - i) * n + (n - 1 - j))]));
+    }
+  if (asym > 1e-10 * amax) {
+    set_error("K is not self-adjoint in the weights m (diag(m) K not symmetric to 1e-10)");
+    return TS_ERR_INVALID;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t t = 0; t < w; ++t) {
+      const int64_t j = i - bw + t;
+      if (j < 0 || j >= n) continue;
+      bsym[(size_t)(i * w + t)] = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
+      bphys[(size_t)(i * w + t)] = K[(size_t)(i * n + j)];
+    }
+  const bool reflect = arefl <= 1e-11 * amax && symmetric_samples(n, m.data()) && symmetric_samples(n, f);
+  return build_axis_massed(n, 0.0, A, bsym, bphys, bw, m, x, f, reflect, phys, sym);
 }
 
 ExecCtx::~ExecCtx() {
@@ -485,7 +548,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     for (int m = k + 1; m < d; ++m) pa.R *= p->n[m];
     pa.cplx = cplx;
     pa.skip = ap.skip;
-    pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
+    pa.fold = pa.fac->fold && p->fold_enabled;
     if (fwd && t == d) {
       pa.epi = ap.epi;
       pa.Lp = p->Lp;
@@ -774,6 +837,7 @@ int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* con
   p->L = L;
   p->sigma = sigma;
   p->sem_k = k;
+  p->massed = true;
   hipGetDevice(&p->device);
   std::map<std::pair<int64_t, std::string>, std::pair<std::shared_ptr<AxisFactor>, std::shared_ptr<AxisFactor>>> cache;
   for (int a = 0; a < d; ++a) {
@@ -796,6 +860,57 @@ int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* con
   return TS_OK;
 }
 
+int ts_setup_general(int d, const int64_t* n, const double* const* K, const double* const* m,
+                     const double* const* x, const double* const* f, double sigma, ts_plan** out) {
+  set_error("");
+  if (!out || !n || !K || !f) { set_error("null argument"); return TS_ERR_INVALID; }
+  *out = nullptr;
+  if (d < 1 || d > TS_MAX_D) { set_error("d must be in [1, 12]"); return TS_ERR_INVALID; }
+  if (!std::isfinite(sigma)) { set_error("sigma must be finite"); return TS_ERR_INVALID; }
+  int64_t N = 1;
+  int bw = 1;  // at least 1: the band path serves every generic plan
+  for (int a = 0; a < d; ++a) {
+    if (n[a] < 1 || n[a] > 8192) { set_error("n[a] must be in [1, 8192]"); return TS_ERR_INVALID; }
+    if (!K[a] || !f[a]) { set_error("K[a] or f[a] is null"); return TS_ERR_INVALID; }
+    for (int64_t j = 0; j < n[a]; ++j)
+      if (!std::isfinite(f[a][j])) { set_error("f[a] has a non-finite sample"); return TS_ERR_NONFINITE; }
+    for (int64_t i = 0; i < n[a]; ++i)
+      for (int64_t j = 0; j < n[a]; ++j)
+        if (K[a][(size_t)(i * n[a] + j)] != 0.0) bw = std::max<int>(bw, (int)std::llabs(i - j));
+    N *= n[a];
+    if (N >= (int64_t(1) << 40)) { set_error("grid too large"); return TS_ERR_INVALID; }
+  }
+  auto p = std::unique_ptr<ts_plan>(new ts_plan());
+  p->d = d;
+  p->N = N;
+  p->L = 0.0;
+  p->sigma = sigma;
+  p->massed = true;
+  hipGetDevice(&p->device);
+  for (int a = 0; a < d; ++a) {
+    p->n[a] = n[a];
+    int b;  // reuse the factors of an earlier identical axis
+    for (b = 0; b < a; ++b) {
+      if (n[b] != n[a] || K[b] != K[a] || (m ? m[b] : nullptr) != (m ? m[a] : nullptr)) continue;
+      if (std::memcmp(f[b], f[a], sizeof(double) * (size_t)n[a]) == 0) break;
+    }
+    if (b < a) {
+      p->ax.push_back(p->ax[b]);
+      p->ax_sym.push_back(p->ax_sym[b]);
+      continue;
+    }
+    std::shared_ptr<AxisFactor> P, S;
+    int rc = build_axis_general(n[a], K[a], m ? m[a] : nullptr, x ? x[a] : nullptr, f[a], bw, P, S);
+    if (rc) return rc;
+    p->ax.push_back(P);
+    p->ax_sym.push_back(S);
+  }
+  int rc = finish_plan(p.get());
+  if (rc) return rc;
+  *out = p.release();
+  return TS_OK;
+}
+
 int ts_sem_nodes(int k, int64_t cells, double L, double* x) {
   if (!x) { set_error("null argument"); return TS_ERR_INVALID; }
   SemAxis ax;
@@ -807,7 +922,7 @@ int ts_sem_nodes(int k, int64_t cells, double L, double* x) {
 int ts_mass(const ts_plan* plan, int axis, double* out) {
   if (!plan || !out || axis < 0 || axis >= plan->d) { set_error("bad argument"); return TS_ERR_INVALID; }
   const auto& F = *plan->ax[axis];
-  if (plan->sem_k) {
+  if (plan->massed) {
     std::memcpy(out, F.m_h.data(), sizeof(double) * (size_t)F.n);
   } else {
     const double h = 2.0 * plan->L / (double)(F.n + 1);
@@ -821,7 +936,7 @@ int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out
   if (!plan || !in || !out || axis < 0 || axis >= plan->d) { set_error("bad argument"); return TS_ERR_INVALID; }
   if (in == out) { set_error("in and out must not alias"); return TS_ERR_INVALID; }
   if (dtype != TS_F64 && dtype != TS_F32 && dtype != TS_C128 && dtype != TS_C64) { set_error("bad dtype"); return TS_ERR_INVALID; }
-  if (prec != TS_PREC_FP64 && prec != TS_PREC_FP32) { set_error("the single pass runs FP64 or FP32 transforms"); return TS_ERR_INVALID; }
+  if (prec != TS_PREC_FP64 && prec != TS_PREC_FP32 && prec != TS_PREC_BF16) { set_error("bad prec"); return TS_ERR_INVALID; }
   const bool f64 = dtype == TS_F64 || dtype == TS_C128;
   if (prec == TS_PREC_FP64 && !f64) { set_error("FP64 transforms need FP64 data"); return TS_ERR_INVALID; }
   const bool cplx = dtype == TS_C128 || dtype == TS_C64;

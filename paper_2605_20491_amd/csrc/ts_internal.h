@@ -68,6 +68,8 @@ struct AxisFactor {
   int64_t ne = 0, no = 0, hh = 0, cc = 0, fkp = 0;
   double *Fe64 = nullptr, *Fo64 = nullptr, *Be64 = nullptr, *Bo64 = nullptr;
   float *Fe32 = nullptr, *Fo32 = nullptr, *Be32 = nullptr, *Bo32 = nullptr;
+  // BF16, K-contiguous (transposed) copies of Fe, Fo, Be, Bo for the BF16 passes
+  uint16_t *Fe16 = nullptr, *Fo16 = nullptr, *Be16 = nullptr, *Bo16 = nullptr;
   std::vector<double> lam_int_h;  // eigenvalues in the internal spectral order
   ~AxisFactor();
 };
@@ -155,7 +157,8 @@ struct ts_plan {
   int device = 0;
   std::vector<std::shared_ptr<ts::AxisFactor>> ax;      // factors of the public applies
   std::vector<std::shared_ptr<ts::AxisFactor>> ax_sym;  // orthogonal factors of the solvers (FD: = ax)
-  int sem_k = 0;               // 0: FD; k >= 1: Q^k SEM
+  int sem_k = 0;               // 0: FD or generic; k >= 1: Q^k SEM
+  bool massed = false;         // SEM or generic: mass inner product, banded operator
   bool fold_enabled = true;    // use the half-extent passes on symmetric axes
   int s = 0;                   // axis whose forward pass carries the scaling
   int64_t Ps = 1, Rs = 1;      // products of the extents before / after axis s

@@ -32,17 +32,26 @@ def test_fold_matches_plain_and_oracle(shape):
                      to_host(ts.ts_apply_inverse_shift(plan, 2.5, to_dev(b))),
                      to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi))),
                      to_host(ts.ts_apply_inverse(plan, to_dev(b).float(), prec="fp32")).astype(np.float64),
-                     to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi).to(torch.complex64), prec="fp32")))
+                     to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi).to(torch.complex64), prec="fp32")),
+                     to_host(ts.ts_apply_inverse(plan, to_dev(b).float(), prec="bf16")).astype(np.float64),
+                     to_host(ts.ts_apply_exp(plan, 0.05, to_dev(psi).to(torch.complex64), prec="bf16")))
     refs = (oracle.apply_inverse(oplan, b, 1.0), oracle.apply_inverse(oplan, b, 2.5), oracle.apply_exp(oplan, psi, 0.05))
     d = [rel(a, c) for a, c in zip(out[True], out[False])]
     e = [rel(out[True][i], refs[i]) for i in range(3)]
     e32 = rel(out[True][3], refs[0])
     e64c = rel(out[True][4].astype(np.complex128), refs[2])
-    announce("fold %s mask %d: fold vs plain %s; vs oracle %s; fp32 %.2e c64 %.2e"
-             % (shape, mask, ["%.1e" % x for x in d], ["%.1e" % x for x in e], e32, e64c))
-    assert max(d[:3]) <= 1e-13 and max(d[3:]) <= 2e-6
+    # BF16 transforms: both variants at the BF16 rounding level of the oracle
+    e16 = [rel(out[fold][5], refs[0]) for fold in (True, False)]
+    e16c = [rel(out[fold][6].astype(np.complex128), refs[2]) for fold in (True, False)]
+    announce("fold %s mask %d: fold vs plain %s; vs oracle %s; fp32 %.2e c64 %.2e; bf16 fold/plain %s, c64 %s"
+             % (shape, mask, ["%.1e" % x for x in d], ["%.1e" % x for x in e], e32, e64c,
+                ["%.2e" % x for x in e16], ["%.2e" % x for x in e16c]))
+    assert max(d[:3]) <= 1e-13 and max(d[3:5]) <= 2e-6
     assert e[0] <= 1e-12 and e[1] <= 1e-12 and e[2] <= exp_tol(oplan, 0.05)
     assert e32 <= 2e-6 and e64c <= 2e-6
+    # (the two variants round different quantities, so their errors are two samples
+    # of the BF16 rounding noise; in 1D a few low modes dominate and the ratio varies)
+    assert max(e16 + e16c) <= 3e-2
 
 
 def test_non_symmetric_axes_are_not_folded():
@@ -96,3 +105,23 @@ def test_single_pass_round_trip(shape):
         y0 = ts.ts_mode_pass(plan, axis, True, x)
         ts.ts_set_fold(plan, True)
         assert rel(to_host(y), to_host(y0)) <= 1e-14
+
+
+@pytest.mark.parametrize("shape", [(100, 99, 130), (70, 81), (64, 96)])
+def test_single_pass_bf16_fold(shape):
+    """BF16 single passes (FP64 data in and out), folded and plain, against the
+    FP64 pass: relative error at the BF16 rounding level on every axis and
+    direction; the folded BF16 backward pass includes the butterfly."""
+    plan, _, _ = make_pair(shape, 6.0, "cos", sigma=1.0)
+    x = to_dev(W.rhs_normal(shape, 5))
+    for axis in range(len(shape)):
+        for fwd in (True, False):
+            ref = to_host(ts.ts_mode_pass(plan, axis, fwd, x))
+            errs = []
+            for fold in (True, False):
+                ts.ts_set_fold(plan, fold)
+                errs.append(rel(to_host(ts.ts_mode_pass(plan, axis, fwd, x, prec="bf16")), ref))
+            ts.ts_set_fold(plan, True)
+            announce("bf16 pass %s axis %d %s: fold %.2e plain %.2e"
+                     % (shape, axis, "fwd" if fwd else "bwd", errs[0], errs[1]))
+            assert max(errs) <= 1e-2

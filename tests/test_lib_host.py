@@ -169,3 +169,38 @@ def test_even_odd_tridiagonal_eig(n):
     assert np.max(1 - np.abs(par)) < 1e-13
     with pytest.raises(ts.TSError):
         ts.ts_tridiag_eig_even_odd(d + np.arange(n) * 1e-3, o)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 41, 120, 199])
+def test_hermite_axis_matches_oracle_and_gauss_hermite(n):
+    """ts_hermite_axis (Sturm bisection + Newton, rescaled recurrence, Gram form
+    of -D^2) against numpy's Gauss-Hermite nodes and weights and the oracle's
+    eigvalsh / plain-recurrence construction."""
+    x, m, K = ts.ts_hermite_axis(n)
+    xo, mo, Ko = oracle.hermite_axis(n)
+    xr, wr = np.polynomial.hermite.hermgauss(n)
+    assert np.max(np.abs(x - xr)) <= 1e-14 * max(1.0, np.abs(xr).max())
+    assert np.all(x == -x[::-1])
+    assert np.max(np.abs(m / (wr * np.exp(xr * xr)) - 1)) <= 1e-12
+    assert np.max(np.abs(x - xo)) <= 1e-12 * max(1.0, np.abs(xo).max())
+    assert np.max(np.abs(m / mo - 1)) <= 1e-10
+    assert np.max(np.abs(K - Ko)) <= 1e-11 * max(np.abs(Ko).max(), 1e-300)
+    MK = m[:, None] * K
+    assert np.max(np.abs(MK - MK.T)) <= 1e-13 * max(np.abs(MK).max(), 1e-300)
+
+
+def test_hermite_axis_past_the_underflow_of_the_plain_recurrence():
+    """n = 1200: e^{-x^2/2} underflows at the outer nodes (x > 38), the rescaled
+    recurrence does not; the weights still match numpy's rule where numpy's own
+    weights are finite, and K + x^2 keeps the oscillator eigenvalues 1, 3, 5."""
+    n = 1200
+    x, m, K = ts.ts_hermite_axis(n)
+    assert np.all(np.isfinite(m)) and np.all(m > 0) and np.all(np.isfinite(K))
+    lam = np.linalg.eigvalsh(np.sqrt(m)[:, None] * (K + np.diag(x * x)) / np.sqrt(m)[None, :])
+    assert np.max(np.abs(lam[:3] - np.array([1.0, 3.0, 5.0]))) <= 1e-8
+
+
+def test_hermite_axis_rejects_bad_n():
+    for n in (0, 8193):
+        with pytest.raises(ts.TSError):
+            ts.ts_hermite_axis(n)
