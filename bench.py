@@ -328,6 +328,49 @@ def accuracy_section(ts, W, torch, dev, steps=3):
     return out
 
 
+HERMITE_ROWS = [(199, 1.53e-5, 6.31e-5, 2.7, 0.002), (399, 4.05e-6, 2.20e-5, 3.2, 0.024),
+                (599, 1.87e-6, 1.20e-5, 3.2, 0.117)]
+
+
+def hermite_section(ts, W, torch, dev, steps=3):
+    """Table tab:hermite_accuracy: (-Delta + V)^{-1} of eq. (test_potential)
+    on R^3 by Hermite collocation (ts_hermite_axis + ts_setup_general), exact
+    solution prod sin(c (t + 1)) / (1 + t^2); setup and per-solve time, the
+    l2 relative error and the weighted L2 error (Gauss-Hermite weights of
+    e^{-|x|^2}) beside the printed values."""
+    import numpy as np
+    out = {}
+    for n, p_w, p_l2, p_setup, p_solve in HERMITE_ROWS:
+        t0 = time.perf_counter()
+        x, m, K = ts.ts_hermite_axis(n)
+        fs = [W.f_test_potential(0, 0.0, c, x=x) for c in (3.0, 2.0, 1.0)]
+        plan = ts.ts_setup_general([K] * 3, [m] * 3, fs, 0.0, [x] * 3)
+        setup = time.perf_counter() - t0
+        G = [W.rational_sine(c, x) for c in (1.5 * np.pi, np.pi, 0.5 * np.pi)]
+        gd = [torch.from_numpy(g).to(dev) for g, _ in G]
+        rhs = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)
+        for a in range(3):
+            fac = list(gd)
+            fac[a] = torch.from_numpy(-G[a][1] + fs[a] * G[a][0]).to(dev)
+            rhs += fac[0][:, None, None] * fac[1][None, :, None] * fac[2][None, None, :]
+        ustar = gd[0][:, None, None] * gd[1][None, :, None] * gd[2][None, None, :]
+        u = torch.empty_like(rhs)
+        ms, _ = timed(lambda: ts.ts_apply_inverse(plan, rhs, u), steps, 1)
+        e = u - ustar
+        wd = torch.from_numpy(m * np.exp(-x * x)).to(dev)
+        w3 = wd[:, None, None] * wd[None, :, None] * wd[None, None, :]
+        l2 = float(torch.linalg.norm(e) / torch.linalg.norm(ustar))
+        weighted = float(torch.sqrt(torch.sum(w3 * e * e)))
+        out["n%d" % n] = {"n": n, "dofs": n ** 3, "setup_s": setup, "solve_s": ms * 1e-3, "l2_rel_err": l2,
+                          "weighted_l2_err": weighted, "paper_l2_rel_err": p_l2, "paper_weighted_l2_err": p_w,
+                          "paper_a100_setup_s": p_setup, "paper_a100_solve_s": p_solve}
+        log("hermite %d^3: setup %.2f s solve %.4f s l2 %.3e (printed %.2e) weighted %.3e (printed %.2e, A100 %.3f s)"
+            % (n, setup, ms * 1e-3, l2, p_l2, weighted, p_w, p_solve))
+        del plan, rhs, u, ustar, e, w3
+        torch.cuda.empty_cache()
+    return out
+
+
 def gpe_section(ts, W, torch, dev, betas=(10.0, 100.0), cells=30, k=20, tol=1e-14, maxit=3000):
     """Modified H^1 flow of Table tab:h1_flow: V1 of eq. (separable_V1) on
     [-8,8]^3, Q^20 SEM at 599^3, alpha = 20, tau = 0.1, linear-ground-state
@@ -651,6 +694,7 @@ def main():
         extra["qhop_separable_499"] = qhop_section(ts, W, torch, dev)
     if not args.no_table:
         extra["accuracy_table"] = accuracy_section(ts, W, torch, dev)
+        extra["hermite_table"] = hermite_section(ts, W, torch, dev)
     if not args.no_gpe:
         extra["gpe_h1_flow_599"] = gpe_section(ts, W, torch, dev)
         extra["multilevel_stirrer"] = multilevel_section(ts, W, torch, dev)

@@ -35,6 +35,15 @@ StencilArgs stencil_args(const ts_plan* p, const double* V2, double s, const dou
     a.band[k] = ax[k]->band;
   }
   a.bw = p->massed ? ax[0]->bw : 0;
+  if (p->massed && ax[0]->op_pass) {  // wide band: per-axis MFMA passes into two plan buffers
+    for (int k = 0; k < p->d; ++k) a.dense[k] = ax[k]->op_pass.get();
+    const size_t vb = (size_t)round_up((int64_t)(sizeof(double) * p->N), 256);
+    void* t = nullptr;
+    if (ctx_get(const_cast<ts_plan*>(p)->ctx, kSlotOp, 2 * vb, &t) == TS_OK) {
+      a.tmp0 = (double*)t;
+      a.tmp1 = (double*)((char*)t + vb);
+    }
+  }
   a.V2 = V2;
   a.s = s;
   a.u = u;

@@ -412,6 +412,28 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
   return build_axis_massed(n, L, A, bsym, bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym);
 }
 
+// FP64 pass factor of a dense operator B (row-major n x n): the pass computes
+// y = B x along its axis (W[i][j] = B[j][i], zero-padded to [ld][ld]).
+static int upload_op_pass(int64_t n, const std::vector<double>& B, std::shared_ptr<AxisFactor>& out) {
+  auto F = std::make_shared<AxisFactor>();
+  F->n = n;
+  F->ld = round_up(n, kTileF);
+  F->kpad = F->ld;
+  std::vector<double> W((size_t)(F->kpad * F->ld), 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) W[(size_t)(i * F->ld + j)] = B[(size_t)(j * n + i)];
+  if (hipMalloc(&F->Q64, sizeof(double) * W.size()) != hipSuccess) {
+    set_error("operator factor allocation failed");
+    return TS_ERR_NOMEM;
+  }
+  if (hipMemcpy(F->Q64, W.data(), sizeof(double) * W.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("operator factor upload failed");
+    return TS_ERR_DEVICE;
+  }
+  out = F;
+  return TS_OK;
+}
+
 // Generic axis from a dense K and weights m (NULL: unit weights); bw is the
 // band half-width of every axis of the plan (the largest over the axes).
 static int build_axis_general(int64_t n, const double* K, const double* m_in, const double* x_in, const double* f,
@@ -450,7 +472,18 @@ static int build_axis_general(int64_t n, const double* K, const double* m_in, co
       bphys[(size_t)(i * w + t)] = K[(size_t)(i * n + j)];
     }
   const bool reflect = arefl <= 1e-11 * amax && symmetric_samples(n, m.data()) && symmetric_samples(n, f);
-  return build_axis_massed(n, 0.0, A, bsym, bphys, bw, m, x, f, reflect, phys, sym);
+  std::vector<double> A0;
+  if (bw > kBandMax) {  // the operator apply runs as MFMA passes: keep M^{1/2} K M^{-1/2} before f is added
+    A0 = A;
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < i; ++j)
+        A0[(size_t)(i * n + j)] = A0[(size_t)(j * n + i)] = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
+  }
+  int rc = build_axis_massed(n, 0.0, A, bsym, bphys, bw, m, x, f, reflect, phys, sym);
+  if (rc || bw <= kBandMax) return rc;
+  rc = upload_op_pass(n, A0, sym->op_pass);
+  if (rc) return rc;
+  return upload_op_pass(n, std::vector<double>(K, K + n * n), phys->op_pass);
 }
 
 ExecCtx::~ExecCtx() {
@@ -548,7 +581,9 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     for (int m = k + 1; m < d; ++m) pa.R *= p->n[m];
     pa.cplx = cplx;
     pa.skip = ap.skip;
-    pa.fold = pa.fac->fold && p->fold_enabled;
+    // BF16 passes are bandwidth-bound: the butterfly after a folded backward pass
+    // costs more than the MFMA work it saves, so BF16 folds the forward passes only
+    pa.fold = pa.fac->fold && p->fold_enabled && (fwd || ap.prec != TS_PREC_BF16);
     if (fwd && t == d) {
       pa.epi = ap.epi;
       pa.Lp = p->Lp;

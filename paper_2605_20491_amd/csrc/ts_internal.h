@@ -21,6 +21,7 @@ void set_error(const std::string& msg);
 
 // Tile geometry shared by launchers and the plan's padded matrix storage.
 constexpr int kTileF = 128;   // free-index tile width of the MFMA kernels
+constexpr int kBandMax = 32;  // widest operator band read by the band loop; wider: MFMA passes
 constexpr int kTileK = 32;    // K padding granularity (covers BK of every kernel)
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -71,6 +72,10 @@ struct AxisFactor {
   // BF16, K-contiguous (transposed) copies of Fe, Fo, Be, Bo for the BF16 passes
   uint16_t *Fe16 = nullptr, *Fo16 = nullptr, *Be16 = nullptr, *Bo16 = nullptr;
   std::vector<double> lam_int_h;  // eigenvalues in the internal spectral order
+  // Generic plans whose operator band is wide: the axis operator itself as an
+  // FP64 pass factor (Q64 holds W with y_j = sum_i W[i][j] x_i, i.e. y = B x),
+  // so that the operator apply runs on the matrix cores instead of the band loop
+  std::shared_ptr<AxisFactor> op_pass;
   ~AxisFactor();
 };
 
@@ -99,7 +104,7 @@ struct PassArgs {
   const double2* Er = nullptr;
   const double2* es = nullptr;
   const int* skip = nullptr;   // if non-null and *skip != 0 the kernel returns
-  bool fold = false;           // half-extent pass of a symmetric axis (FP64 / FP32 only)
+  bool fold = false;           // half-extent pass of a symmetric axis
 };
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);
@@ -130,7 +135,7 @@ hipError_t launch_cast_f64_to_bf16_t(const double* x, uint16_t* y, int64_t ld, h
 // solvers' vectors, plus a pinned host mirror of the solver scalars.  A plan
 // owns a growable context for the plain entry points; the serving loop hands
 // each admitted request a fixed context carved from its memory arena.
-enum CtxSlot : int { kSlotWork = 0, kSlotPhase = 1, kSlotTab = 2, kSlotSolver = 3, kSlots = 4 };
+enum CtxSlot : int { kSlotWork = 0, kSlotPhase = 1, kSlotTab = 2, kSlotSolver = 3, kSlotOp = 4, kSlots = 5 };
 struct ExecCtx {
   bool growable = true;
   void* buf[kSlots] = {};

@@ -33,6 +33,12 @@ struct StencilArgs {
   // replace the h^-2 (-1, 2, -1) stencil when bw > 0
   int bw = 0;
   const double* band[TS_MAX_D] = {};
+  // Generic plans with a wide band: the per-axis operators as FP64 pass
+  // factors (the band is then not read), and two N-sized FP64 buffers for the
+  // per-axis products
+  const AxisFactor* dense[TS_MAX_D] = {};
+  double* tmp0 = nullptr;
+  double* tmp1 = nullptr;
 };
 
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st);

@@ -116,6 +116,43 @@ __global__ __launch_bounds__(RT) void k_band(StencilArgs a) {
   }
 }
 
+// Dense per-axis operators (generic plans with a wide band): the per-axis
+// products sum_k (I x .. x B_k x .. x I) u come from MFMA passes, summed in
+// tmp0 (+ tmp1); this kernel adds the diagonal (sum_k f_k + V2 + s) u and
+// forms the output and its dot product exactly as k_band does.
+__global__ __launch_bounds__(RT) void k_add_to(double* y, const double* x, int64_t N, const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = blockIdx.x * (int64_t)RT + threadIdx.x; i < N; i += (int64_t)gridDim.x * RT) y[i] += x[i];
+}
+
+template <int MODE, int DOT>
+__global__ __launch_bounds__(RT) void k_combine(StencilArgs a) {
+  if (a.skip && *a.skip) {
+    if (DOT && threadIdx.x == 0 && blockIdx.x < kRedBlocks) a.partial[blockIdx.x] = 0.0;
+    return;
+  }
+  double dsum = 0.0;
+  for (int64_t idx = blockIdx.x * (int64_t)RT + threadIdx.x; idx < a.N; idx += (int64_t)gridDim.x * RT) {
+    double diag = a.s + (a.V2 ? a.V2[idx] : 0.0);
+    int64_t rem = idx;
+    for (int k = a.d - 1; k >= 0; --k) {
+      diag += a.f[k][rem % a.n[k]];
+      rem /= a.n[k];
+    }
+    const double acc = a.tmp0[idx] + (a.d > 1 ? a.tmp1[idx] : 0.0);
+    const double uc = a.u[idx];
+    double v = acc + diag * uc;
+    if (MODE == (int)StOut::FminusAx) v = a.rhs[idx] - v;
+    a.out[idx] = v;
+    if (DOT == (int)StDot::UdotOut) dsum += uc * v;
+    if (DOT == (int)StDot::OutdotOut) dsum += v * v;
+  }
+  if (DOT) {
+    double s = block_sum(dsum);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+  }
+}
+
 struct ScaleArgs {
   int d;
   int64_t n[TS_MAX_D];
@@ -273,8 +310,45 @@ inline int red_grid(int64_t n) { (void)n; return kRedBlocks; }
 
 }  // namespace
 
+// Dense operators: d FP64 passes (axis k into tmp0 for k = 0, else tmp1, with
+// tmp1 added into tmp0 before the next pass overwrites it), then k_combine.
+static hipError_t launch_dense_operator(const StencilArgs& a, hipStream_t st) {
+  if (!a.tmp0 || !a.tmp1) return hipErrorOutOfMemory;
+  const unsigned g = (unsigned)std::min<int64_t>((a.N + RT - 1) / RT, 1 << 20);
+  for (int k = 0; k < a.d; ++k) {
+    PassArgs pa;
+    pa.X = a.u;
+    pa.Y = k == 0 ? a.tmp0 : a.tmp1;
+    pa.tin = pa.tout = DT::F64;
+    pa.prec = 0;
+    pa.fac = a.dense[k];
+    pa.forward = true;
+    pa.n = a.n[k];
+    pa.P = 1;
+    pa.R = 1;
+    for (int m = 0; m < k; ++m) pa.P *= a.n[m];
+    for (int m = k + 1; m < a.d; ++m) pa.R *= a.n[m];
+    pa.skip = a.skip;
+    hipError_t e = launch_pass(pa, st);
+    if (e != hipSuccess) return e;
+    if (k >= 1 && k + 1 < a.d) {
+      hipLaunchKernelGGL(k_add_to, dim3(g), dim3(RT), 0, st, a.tmp0, a.tmp1, a.N, a.skip);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  const unsigned gc = a.dot != StDot::None ? kRedBlocks : g;
+  const int m = (int)a.mode, dt = (int)a.dot;
+#define TS_CB(M, D) \
+  if (m == M && dt == D) { hipLaunchKernelGGL((k_combine<M, D>), dim3(gc), dim3(RT), 0, st, a); return hipGetLastError(); }
+  TS_CB(0, 0) TS_CB(0, 1) TS_CB(0, 2) TS_CB(1, 0) TS_CB(1, 1) TS_CB(1, 2)
+#undef TS_CB
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
+  if (a.dense[0]) return launch_dense_operator(a, st);
   if (a.bw > 0) {
     const unsigned g = a.dot != StDot::None ? kRedBlocks
                                             : (unsigned)std::min<int64_t>((a.N + RT - 1) / RT, 1 << 20);

@@ -114,6 +114,30 @@ def test_hermite_operator_pcg_and_gpe_step():
     assert rel(to_host(ud), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("shape", [(70,), (40, 90), (36, 50, 41)])
+def test_hermite_dense_operator_and_pcg(shape):
+    """Hermite axes with n > 33: the operator apply runs as per-axis FP64 MFMA
+    passes plus a combine kernel (the band would be n - 1 wide); both the
+    public operator and PCG (symmetric form) against the oracle."""
+    plan, oplan = hermite_pair(shape, seed=13, sigma=1.0)
+    V2 = 2.0 * W.rhs_normal(shape, 14) ** 2
+    u = W.rhs_normal(shape, 15)
+    got = to_host(ts.ts_operator_apply(plan, to_dev(V2), 0.25, to_dev(u)))
+    e_op = rel(got, oracle.operator_apply(oplan, u, V2, 0.25))
+    got0 = to_host(ts.ts_operator_apply(plan, None, 0.0, to_dev(u)))
+    e_op0 = rel(got0, oracle.operator_apply(oplan, u, None, 0.0))
+    rhs = W.rhs_normal(shape, 16)
+    ref = oracle.pcg(oplan, V2, 1.0, rhs, rtol=1e-13)
+    x = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    _, its, rr, _ = ts.ts_pcg_solve(plan, to_dev(V2), to_dev(rhs), x, rtol=1e-10, maxit=300)
+    xh = to_host(x)
+    true = oracle.norm(oplan, rhs - oracle.operator_apply(oplan, xh, V2, 1.0)) / oracle.norm(oplan, rhs)
+    announce("hermite dense %s: operator %.2e / %.2e, pcg %d its relres %.2e true %.2e err %.2e"
+             % (shape, e_op, e_op0, its, rr, true, rel(xh, ref.x)))
+    assert e_op <= 1e-13 and e_op0 <= 1e-13
+    assert true <= 2e-10 and rel(xh, ref.x) <= 1e-8
+
+
 def test_symmetric_hermite_axes_fold():
     shape = (80, 66, 30)
     plan, oplan = hermite_pair(shape, symmetric=True)
