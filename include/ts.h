@@ -160,9 +160,12 @@ int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* con
  * M^{1/2} H_a M^{-1/2} = Q Lambda Q^T (host FP64 Householder and QL), so
  * T = M^{-1/2} Q and T^{-1} = Q^T M^{1/2}, exactly as for ts_setup_sem; every
  * entry point then works on the nodal values, the solvers in the inner
- * product sum_p (prod_a m_a) x_p y_p.  The operator apply (PCG, GPE flows)
- * reads each K_a as a band whose half-width is the largest |i - j| with
- * K_a[i][j] != 0 over all axes (a dense K is a band of half-width n - 1).
+ * product sum_p (prod_a m_a) x_p y_p.  The operator apply (ts_operator_apply,
+ * PCG, GPE flows) reads each K_a as a band whose half-width b is the largest
+ * |i - j| with K_a[i][j] != 0 over all axes; for b > 32 (for instance a dense
+ * K, b = n - 1) it runs instead as one FP64 matrix-core pass per axis with
+ * K_a as the factor, in two N-sized FP64 buffers the plan allocates on first
+ * use and keeps until ts_destroy.
  * An axis whose K, m and f are reflection-symmetric (to 1e-11 / 1e-13
  * relative) gets the half-extent passes (ts_set_fold).  The plan has no
  * interval [-L, L]: ts_interpolate and the multi-level iteration reject it.

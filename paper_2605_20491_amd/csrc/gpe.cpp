@@ -58,6 +58,19 @@ GpeGrid gpe_grid(const ts_plan* p) {
   return g;
 }
 
+// E'(u) and its two sums; plans with dense per-axis operators first form
+// (sum_k B_k + F) u by the MFMA passes of the operator apply.
+int gpe_op(const ts_plan* p, GpeOpArgs& op, double* Hu, hipStream_t st) {
+  if (Hu) {
+    StencilArgs sa = stencil_args(p, nullptr, 0.0, op.u, Hu, false);
+    sa.skip = op.skip;
+    TS_TRY(launch_stencil(sa, st));
+    op.Hu = Hu;
+  }
+  TS_TRY(launch_gpe_op(op, st));
+  return TS_OK;
+}
+
 // Device buffers of one flow call, released on scope exit.
 struct GpeBufs {
   std::vector<void*> ptrs;
@@ -108,9 +121,10 @@ int gpe_h1_flow(ts_plan* p, const double* V, double beta, double alpha, double t
   if (!(alpha + p->lam_min > 0.0)) { set_error("-Delta + alpha must be positive definite"); return TS_ERR_NOT_SPD; }
   const int64_t N = p->N;
   GpeBufs B;
-  double *Ep, *g, *gu, *part, *part2, *hist;
+  double *Ep, *g, *gu, *part, *part2, *hist, *Hu = nullptr;
   GpeScalars* sc;
   TS_RC(B.get(N, &Ep));
+  if (p->ax[0]->op_pass) TS_RC(B.get(N, &Hu));
   TS_RC(B.get(N, &g));
   TS_RC(B.get(N, &gu));
   TS_RC(B.get(kRedBlocks, &part));
@@ -139,7 +153,7 @@ int gpe_h1_flow(ts_plan* p, const double* V, double beta, double alpha, double t
   op.partial2 = part2;
   op.skip = done;
   auto step = [&]() -> int {
-    TS_TRY(launch_gpe_op(op, st));
+    TS_RC(gpe_op(p, op, Hu, st));
     TS_TRY(launch_gpe_scalar(GpeStep::Energy, sc, part, part2, hist, st));
     TS_RC(apply_inverse_impl(p, alpha, Ep, g, TS_F64, TS_PREC_FP64, st, p->ctx, done));
     TS_RC(apply_inverse_impl(p, alpha, u, gu, TS_F64, TS_PREC_FP64, st, p->ctx, done));
@@ -173,9 +187,10 @@ int gpe_au_flow(ts_plan* p, const double* V2, double beta, double tau, double* u
   if (!(pcg_rtol > 0.0) || pcg_maxit < 1) { set_error("bad PCG tolerance or limit"); return TS_ERR_INVALID; }
   const int64_t N = p->N;
   GpeBufs B;
-  double *Ep, *z, *W, *part, *part2, *hist;
+  double *Ep, *z, *W, *part, *part2, *hist, *Hu = nullptr;
   GpeScalars* sc;
   TS_RC(B.get(N, &Ep));
+  if (p->ax[0]->op_pass) TS_RC(B.get(N, &Hu));
   TS_RC(B.get(N, &z));
   TS_RC(B.get(N, &W));
   TS_RC(B.get(kRedBlocks, &part));
@@ -206,7 +221,7 @@ int gpe_au_flow(ts_plan* p, const double* V2, double beta, double tau, double* u
   int total_its = 0;
   GpeScalars s;
   for (int k = 0; k <= maxit; ++k) {
-    TS_TRY(launch_gpe_op(op, st));
+    TS_RC(gpe_op(p, op, Hu, st));
     TS_TRY(launch_gpe_scalar(GpeStep::Energy, sc, part, part2, hist, st));
     TS_TRY(hipMemcpyAsync(hs, sc, sizeof(GpeScalars), hipMemcpyDeviceToHost, st));
     TS_TRY(hipStreamSynchronize(st));

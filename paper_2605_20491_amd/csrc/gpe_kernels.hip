@@ -42,7 +42,8 @@ __global__ __launch_bounds__(RT) void k_gpe_op(GpeOpArgs a) {
     const double w = point_weight(g, idx, c);
     const double uc = a.u[idx];
     double acc = 0.0, diag = a.V2 ? a.V2[idx] : 0.0;
-    for (int k = 0; k < g.d; ++k) {
+    if (a.Hu) acc = a.Hu[idx];
+    for (int k = 0; k < g.d && !a.Hu; ++k) {
       const int64_t i = c[k], nk = g.n[k], st = g.stride[k];
       diag += g.f[k][i];
       if (g.bw == 0) {  // FD: h^-2 (2u - u_lo - u_hi), zero ghosts

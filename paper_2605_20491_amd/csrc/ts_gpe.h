@@ -29,6 +29,9 @@ struct GpeOpArgs {
   double* partial = nullptr;   // [kRedBlocks] shares of (u, out)
   double* partial2 = nullptr;  // [kRedBlocks] shares of (u^4, 1)
   const int* skip = nullptr;
+  // generic plans with a wide band: (sum_k B_k + F) u precomputed by the dense
+  // operator passes; the kernel then adds only (V2 + beta u^2) u
+  const double* Hu = nullptr;
 };
 
 // Device scalar block of a flow.  status: 0 running / converged, 2 non-finite, 3 iteration limit.

@@ -43,6 +43,10 @@ struct StencilArgs {
 
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st);
 
+// Operator arguments of a plan: (H1 + V2 + s) on u into out, from the
+// symmetric-form factors (sym: the solvers) or the public ones (defined in solvers.cpp).
+StencilArgs stencil_args(const ts_plan* p, const double* V2, double s, const double* u, double* out, bool sym);
+
 // y = x * prod_k w_k(i_k) pointwise (x may equal y); w_k device vectors of n_k.
 hipError_t launch_axis_scale(const double* x, double* y, int d, const int64_t* n, const double* const* w,
                              hipStream_t st);

@@ -138,6 +138,34 @@ def test_hermite_dense_operator_and_pcg(shape):
     assert true <= 2e-10 and rel(xh, ref.x) <= 1e-8
 
 
+def test_hermite_dense_gpe_steps():
+    """One step of each GPE flow on Hermite axes with n > 33 (E'(u) from the
+    dense operator passes) against the oracle's steps."""
+    shape = (36, 40, 34)
+    axes = [oracle.hermite_axis(n) for n in shape]
+    Ks, ms, xs = [a[2] for a in axes], [a[1] for a in axes], [a[0] for a in axes]
+    zeros = [np.zeros(n) for n in shape]
+    v = [x * x for x in xs]
+    lap = ts.ts_setup_general(Ks, ms, zeros, 1.0, xs)
+    pv1 = ts.ts_setup_general(Ks, ms, v, 1.0, xs)
+    olap = oracle.make_plan_general(Ks, ms, zeros, xs)
+    opv1 = oracle.make_plan_general(Ks, ms, v, xs)
+    V = np.ascontiguousarray(v[0][:, None, None] + v[1][None, :, None] + v[2][None, None, :])
+    w = oracle.l2_weights(olap)
+    u0 = oracle.separable_ground_state(opv1) * (1.0 + 0.2 * np.cos(W.outer(xs)))
+    u0 = u0 / np.sqrt(np.sum(w * u0 * u0))
+    ref = oracle.h1_flow_step(olap, V, 80.0, 10.0, 0.1, u0)
+    ud = to_dev(u0)
+    r = ts.ts_gpe_h1_flow(lap, to_dev(V), 80.0, ud, alpha=10.0, tau=0.1, maxit=1, tol=0.0, raise_on_noconv=False)
+    e_h1 = rel(to_host(ud), ref)
+    ref_a, _ = oracle.au_flow_step(opv1, None, 80.0, 1.0, u0)
+    ud = to_dev(u0)
+    ts.ts_gpe_au_flow(pv1, None, 80.0, ud, tau=1.0, maxit=1, tol=0.0, pcg_rtol=1e-13, raise_on_noconv=False)
+    e_au = rel(to_host(ud), ref_a)
+    announce("hermite dense gpe: h1 step %.2e, au step %.2e, E %.10f" % (e_h1, e_au, r.energy))
+    assert r.iters == 1 and e_h1 <= 1e-12 and e_au <= 1e-10
+
+
 def test_symmetric_hermite_axes_fold():
     shape = (80, 66, 30)
     plan, oplan = hermite_pair(shape, symmetric=True)
