@@ -328,6 +328,47 @@ def accuracy_section(ts, W, torch, dev, steps=3):
     return out
 
 
+def small_section(ts, W, torch, dev, reps=200, per_graph=10):
+    """Latency-bound case: 3D n = 64 (2.6e5 DoFs, 2 MB; L = 8, f = x^2,
+    sigma = 1, N(0,1) right-hand side seed 1, complex128 wavepacket seed 1,
+    tau = 0.01): microseconds per FP64 inverse and complex128 propagator apply,
+    launched one by one and replayed from a HIP graph of per_graph applies."""
+    n, L = 64, 8.0
+    shape = (n,) * 3
+    plan = ts.ts_setup(shape, L, [W.f_harmonic(n, L)] * 3, 1.0)
+    b = torch.from_numpy(W.rhs_normal(shape, 1)).to(dev)
+    u = torch.empty_like(b)
+    psi = torch.from_numpy(W.gaussian_wavepacket(shape, L, 1)).to(dev)
+    out = torch.empty_like(psi)
+    res = {"n": n, "dofs": n ** 3}
+    for name, fn, y in (("inverse_fp64", lambda: ts.ts_apply_inverse(plan, b, u), u),
+                        ("exp_c128", lambda: ts.ts_apply_exp(plan, 0.01, psi, out), out)):
+        ms, _ = timed(fn, reps, 5)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(per_graph):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        got = y.clone()
+        fn()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(got, y))
+        ms_g, _ = timed(g.replay, max(1, reps // per_graph), 2)
+        res[name] = {"us_per_apply_eager": ms * 1e3, "us_per_apply_graph": ms_g * 1e3 / per_graph,
+                     "graph_equals_eager": same}
+        log("64^3 %s: %.1f us/apply eager, %.1f us/apply from a graph (replay == eager: %s)"
+            % (name, ms * 1e3, ms_g * 1e3 / per_graph, same))
+        del g
+    return res
+
+
 HERMITE_ROWS = [(199, 1.53e-5, 6.31e-5, 2.7, 0.002), (399, 4.05e-6, 2.20e-5, 3.2, 0.024),
                 (599, 1.87e-6, 1.20e-5, 3.2, 0.117)]
 
@@ -682,6 +723,8 @@ def main():
         extra["exp_c64_fp32_ms"] = msx
         log("c64 exp %.2f ms/apply" % msx)
         del psi64, out64
+    if not args.no_extras:
+        extra["small_64"] = small_section(ts, W, torch, dev)
     if not args.no_pcg:
         precs = ["fp64", "fp32", "bf16"]
         extra["pcg_n256"] = pcg_section(ts, W, torch, dev, 256, precs)

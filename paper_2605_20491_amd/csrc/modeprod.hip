@@ -28,6 +28,8 @@
 //            x_{n-1-i} = E_i - O_i by the in-place butterfly k_unfold.
 // Tiles of the output dimension are split between the two halves, so each
 // tile runs one half-size GEMM: half the MFMA work of the plain pass.
+#include <type_traits>
+
 #include "ts_internal.h"
 #include "modeprod_common.h"
 
@@ -112,8 +114,8 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   // input row (along the pass axis) feeding GEMM index k; FOLD = 1 adds the mirror
   const int64_t koff = (FOLD == 2 && odd) ? a.ne : 0;
 
-  TC rres[8];
-  TIn rdat[8];
+  TC rres0[8], rres1[8];
+  TIn rdat0[8], rdat1[8];
 
   // ---- global -> registers for k-tile kt ----
   // Factor tiles and column-pass data tiles: thread t owns row t >> 4 of the
@@ -126,8 +128,13 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   const int64_t VW = 16 / (int64_t)sizeof(TIn);
   const bool vec_rows = ROWS && ((((uintptr_t)a.X) & 15) == 0) &&
                         ((CPLX ? 2 * a.n : a.n) % VW == 0) && ((CPLX ? 2 * koff : koff) % VW == 0);
-  auto load_tile = [&](int64_t k0) {
+  // FOLD = 1: the mirror values of the 16-byte paths wait in rmir until the
+  // tile is stored, so the loads stay in flight during the MFMA work
+  TIn rmir[8];
+  bool mpend = false;
+  auto load_tile = [&](int64_t k0, TC (&rres)[8], TIn (&rdat)[8]) {
     const int64_t f0 = ROWS ? n0 : m0;
+    if (FOLD == 1) mpend = false;
     load8(S + (k0 + vr) * ldS + f0 + vc, rres);  // resident factor tile, always in bounds
     if (!ROWS) {
       // B = X[p] row k, columns n0 + vc .. +7
@@ -135,10 +142,8 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
       if (k < K && vec_data && col + 8 <= a.R) {
         load8(X + (p * a.n + koff + k) * a.R + col, rdat);
         if (FOLD == 1 && k < a.hh) {
-          TIn w[8];
-          load8(X + (p * a.n + (a.n - 1 - k)) * a.R + col, w);
-#pragma unroll
-          for (int e = 0; e < 8; ++e) rdat[e] = odd ? rdat[e] - w[e] : rdat[e] + w[e];
+          load8(X + (p * a.n + (a.n - 1 - k)) * a.R + col, rmir);
+          mpend = true;
         }
       } else {
 #pragma unroll
@@ -161,10 +166,11 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
       if (vec_rows && m < a.M && kb + 8 <= K) {
         load8(row + koff + kb, rdat);
         if (FOLD == 1 && kb + 8 <= a.hh) {
-          TIn w[8];  // row[n-1-kb-7 .. n-1-kb], reversed below
+          TIn w[8];  // row[n-1-kb-7 .. n-1-kb], reversed
           load8(row + (a.n - 8 - kb), w);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) rdat[e] = odd ? rdat[e] - w[7 - e] : rdat[e] + w[7 - e];
+          for (int e = 0; e < 8; ++e) rmir[e] = w[7 - e];
+          mpend = true;
         } else if (FOLD == 1) {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
@@ -193,13 +199,14 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
       if (vec_rows && pp < a.P && kb + 4 <= K) {
         load8(row + ((koff + kb) << 1), rdat);
         if (FOLD == 1 && kb + 4 <= a.hh) {
-          TIn w[8];  // complex elements n-1-kb-3 .. n-1-kb, reversed below
+          TIn w[8];  // complex elements n-1-kb-3 .. n-1-kb, reversed
           load8(row + ((a.n - 4 - kb) << 1), w);
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            rdat[2 * e] = odd ? rdat[2 * e] - w[6 - 2 * e] : rdat[2 * e] + w[6 - 2 * e];
-            rdat[2 * e + 1] = odd ? rdat[2 * e + 1] - w[7 - 2 * e] : rdat[2 * e + 1] + w[7 - 2 * e];
+            rmir[2 * e] = w[6 - 2 * e];
+            rmir[2 * e + 1] = w[7 - 2 * e];
           }
+          mpend = true;
         } else if (FOLD == 1) {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
@@ -229,7 +236,11 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
       }
     }
   };
-  auto store_tile = [&](int buf) {
+  auto store_tile = [&](int buf, TC (&rres)[8], TIn (&rdat)[8]) {
+    if (FOLD == 1 && mpend) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rdat[e] = odd ? rdat[e] - rmir[e] : rdat[e] + rmir[e];
+    }
     TC(*Res)[LDS_LD] = ROWS ? Bs[buf] : As[buf];
     store8(&Res[vr][vc], rres);
     if (!ROWS) {
@@ -259,12 +270,7 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
     for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
 
   const int64_t nk = (K + BK - 1) / BK;
-  load_tile(0);
-  store_tile(0);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       const int krow = kk * 4 + lk;
@@ -278,8 +284,36 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
     }
-    if (kt + 1 < nk) store_tile(cur ^ 1);
+  };
+  load_tile(0, rres0, rdat0);
+  store_tile(0, rres0, rdat0);
+  // Two k-tiles in flight in registers (the tile stored at the end of stage kt
+  // was loaded at the start of stage kt - 1), except in the folding forward
+  // pass, whose mirror loads leave no registers for a second set.
+  constexpr bool kDeep = FOLD != 1;
+  if (kDeep) {
+    if (nk > 1) load_tile(BK, rres0, rdat0);
     __syncthreads();
+    auto stage = [&](int64_t kt, TC (&ra)[8], TIn (&da)[8], TC (&rb)[8], TIn (&db)[8]) {
+      const int cur = (int)(kt & 1);
+      if (kt + 2 < nk) load_tile((kt + 2) * BK, rb, db);
+      compute(cur);
+      if (kt + 1 < nk) store_tile(cur ^ 1, ra, da);
+      __syncthreads();
+    };
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+      stage(kt, rres0, rdat0, rres1, rdat1);
+      if (kt + 1 < nk) stage(kt + 1, rres1, rdat1, rres0, rdat0);
+    }
+  } else {
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int cur = (int)(kt & 1);
+      if (kt + 1 < nk) load_tile((kt + 1) * BK, rres0, rdat0);
+      compute(cur);
+      if (kt + 1 < nk) store_tile(cur ^ 1, rres0, rdat0);
+      __syncthreads();
+    }
   }
 
   // ---- epilogue ----
@@ -348,6 +382,47 @@ __global__ __launch_bounds__(256) void k_unfold(T* Y, int64_t P, int64_t n, int6
   }
 }
 
+// The same with 16-byte accesses: V holds W consecutive r of one row (R % W == 0,
+// rows 16-byte aligned).
+template <typename V, int W>
+__global__ __launch_bounds__(256) void k_unfold_vec(V* Y, int64_t P, int64_t n, int64_t Rv, int64_t hh) {
+  const int64_t total = P * hh * Rv;
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t r = e % Rv;
+    const int64_t q = e / Rv;
+    const int64_t i = q % hh, p = q / hh;
+    V* lo = Y + (p * n + i) * Rv + r;
+    V* hi = Y + (p * n + (n - 1 - i)) * Rv + r;
+    const V a = *lo, b = *hi;
+    V s, d;
+    if constexpr (W == 2) {
+      s = V{a.x + b.x, a.y + b.y};
+      d = V{a.x - b.x, a.y - b.y};
+    } else {
+      s = V{a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w};
+      d = V{a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w};
+    }
+    *lo = s;
+    *hi = d;
+  }
+}
+
+template <typename T>
+hipError_t launch_unfold(T* Y, int64_t P, int64_t n, int64_t R, int64_t hh, hipStream_t st) {
+  constexpr int W = 16 / (int)sizeof(T);
+  const bool vec = (R % W == 0) && ((((uintptr_t)Y) & 15) == 0);
+  const int64_t Rv = vec ? R / W : R;
+  const int64_t total = P * hh * Rv;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  if (vec) {
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    hipLaunchKernelGGL((k_unfold_vec<V, W>), dim3(blocks), dim3(256), 0, st, (V*)Y, P, n, Rv, hh);
+  } else {
+    hipLaunchKernelGGL((k_unfold<T>), dim3(blocks), dim3(256), 0, st, Y, P, n, R, hh);
+  }
+  return hipGetLastError();
+}
+
 template <typename TC, typename TIn, typename TOut>
 hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   KArgs a{};
@@ -391,12 +466,8 @@ hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   else if (fold == 2) e = launch_fold<TC, TIn, TOut, 2>(a, pa, st);
   else e = launch_fold<TC, TIn, TOut, 0>(a, pa, st);
   if (e != hipSuccess || fold != 2 || F->hh == 0) return e;
-  // butterfly of the backward pass, in place on its output
-  const int64_t Rr = pa.R;  // real values per (p, i), complex included
-  const int64_t total = pa.P * F->hh * Rr;
-  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL((k_unfold<TOut>), dim3(blocks), dim3(256), 0, st, (TOut*)pa.Y, pa.P, pa.n, Rr, F->hh);
-  return hipGetLastError();
+  // butterfly of the backward pass, in place on its output (R: real values per (p, i))
+  return launch_unfold<TOut>((TOut*)pa.Y, pa.P, pa.n, pa.R, F->hh, st);
 }
 
 }  // namespace
