@@ -71,7 +71,12 @@ template <> __device__ __forceinline__ uint16_t fold_add<uint16_t>(uint16_t x, u
 
 // FOLD as in modeprod.hip: 1 = forward half-extent pass (x_i +- x_{n-1-i} folded while
 // loading), 2 = backward half-extent pass (halves written apart, butterfly afterwards).
-template <typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD>
+// COAL: the data in this pass allow no 16-byte access (odd extents); every
+// block then uses an element-wise mapping in which consecutive lanes read
+// consecutive elements of one row (cols: one k-row of the tile; rows: one data
+// row), so every load instruction is coalesced.  A separate instance keeps the
+// 16-byte paths free of its registers.
+template <typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD, bool COAL>
 __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][LDK];
@@ -116,6 +121,8 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
 
   const int64_t f0 = ROWS ? n0 : m0;
   const bool base_aligned = (((uintptr_t)a.X) & 15) == 0;
+  constexpr bool coal_cols = COAL && !ROWS;
+  constexpr bool coal_rows = COAL && ROWS && !CPLX;
   auto load_tile = [&](int64_t k0) {
     {
       const int row = t >> 1, half = t & 1;  // 32 k per thread
@@ -125,7 +132,33 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
       rres2 = src[2];
       rres3 = src[3];
     }
-    if (!ROWS) {
+    if (!ROWS && coal_cols) {
+      // element (k0 + 2c + (t >> 7), n0 + (t & 127)) for c = 0..31
+      const int64_t col = n0 + (t & 127);
+#pragma unroll
+      for (int c = 0; c < 32; ++c) {
+        const int64_t k = k0 + 2 * c + (t >> 7);
+        TIn v = (TIn)0;
+        if (k < K && col < a.R) {
+          v = X[(p * a.n + koff + k) * a.R + col];
+          if (FOLD == 1 && k < a.hh) v = fold_add(v, X[(p * a.n + (a.n - 1 - k)) * a.R + col], odd);
+        }
+        rdat[c] = v;
+      }
+    } else if (ROWS && coal_rows) {
+      // element (m0 + 4c + (t >> 6), k0 + (t & 63)) for c = 0..31
+      const int64_t k = k0 + (t & 63);
+#pragma unroll
+      for (int c = 0; c < 32; ++c) {
+        const int64_t m = m0 + 4 * c + (t >> 6);
+        TIn v = (TIn)0;
+        if (m < a.M && k < K) {
+          v = X[m * a.n + koff + k];
+          if (FOLD == 1 && k < a.hh) v = fold_add(v, X[m * a.n + (a.n - 1 - k)], odd);
+        }
+        rdat[c] = v;
+      }
+    } else if (!ROWS) {
       // X[p] rows k0 + 4*kq .. +3, columns n0 + 8*oc .. +7
       const int oc = t & 15, kq = t >> 4;
       const int64_t col0 = n0 + 8 * oc;
@@ -240,7 +273,13 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
       dst[2] = rres2;
       dst[3] = rres3;
     }
-    if (!ROWS) {
+    if (!ROWS && coal_cols) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) Bs[buf][t & 127][2 * c + (t >> 7)] = to_bf16(rdat[c]);
+    } else if (ROWS && coal_rows) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) As[buf][4 * c + (t >> 6)][t & 63] = to_bf16(rdat[c]);
+    } else if (!ROWS) {
       // transpose: Bs[col][4 kq .. 4 kq + 3] for each of 8 columns
       const int oc = t & 15, kq = t >> 4;
 #pragma unroll
@@ -332,20 +371,38 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
       }
 }
 
+// Whether a pass's data allow no 16-byte access at all (then the element-wise,
+// coalesced instance runs; such passes do not fold).
+template <typename TIn>
+bool bf16_coalesced(const KArgs& a, const PassArgs& pa) {
+  constexpr int64_t VW = 16 / (int64_t)sizeof(TIn);
+  const bool aligned = (((uintptr_t)a.X) & 15) == 0;
+  return !pa.cplx && (a.rows ? !(aligned && a.n % VW == 0) : !(aligned && a.R % VW == 0));
+}
+
 template <typename TIn, typename TOut, int FOLD>
 hipError_t launch_bf16_fold(const KArgs& a, const PassArgs& pa, hipStream_t st) {
   dim3 grid((unsigned)a.nblocks), block(NT);
+  constexpr bool kCoal = FOLD == 0;  // element-wise instances exist only without the fold
+  const bool coal = kCoal && bf16_coalesced<TIn>(a, pa);
   if (a.rows) {
-    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, true, 0, FOLD>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, false, 0, FOLD>), grid, block, 0, st, a);
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, true, 0, FOLD, false>), grid, block, 0, st, a);
+    else if (coal) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, false, 0, FOLD, kCoal>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, true, false, 0, FOLD, false>), grid, block, 0, st, a);
   } else if (pa.epi == Epi::Exp) {
     if (!pa.cplx) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Exp, FOLD>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Exp, FOLD, false>), grid, block, 0, st, a);
   } else if (pa.epi == Epi::Inv) {
-    if (pa.cplx) hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
+    if (pa.cplx)
+      hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, true, (int)Epi::Inv, FOLD, false>), grid, block, 0, st, a);
+    else if (coal)
+      hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, (int)Epi::Inv, FOLD, kCoal>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, (int)Epi::Inv, FOLD, false>), grid, block, 0, st, a);
+  } else if (coal) {
+    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, 0, FOLD, kCoal>), grid, block, 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, 0, FOLD>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16<TIn, TOut, false, false, 0, FOLD, false>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -388,7 +445,7 @@ hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
   KArgs a{};
   const AxisFactor* F = pa.fac;
   fill_kargs(pa, a, pa.forward ? (const void*)F->QT16 : (const void*)F->Q16, BM, BN);
-  const int fold = pa.fold ? (pa.forward ? 1 : 2) : 0;
+  const int fold = (pa.fold && !bf16_coalesced<TIn>(a, pa)) ? (pa.forward ? 1 : 2) : 0;
   if (fold) {
     a.ne = F->ne;
     a.no = F->no;
