@@ -74,7 +74,12 @@ __device__ __forceinline__ void store8(float* dst, const float* v) {
   for (int i = 0; i < 2; ++i) d4[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
 }
 
-template <typename TC, typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD>
+// COAL: the data of this pass allow no 16-byte access (odd extents); the data
+// tiles then move element by element with consecutive lanes on consecutive
+// elements of one row (cols: one k-row of the tile; rows: one data row), so
+// every load instruction is coalesced.  A separate instance keeps the 16-byte
+// paths free of its registers.
+template <typename TC, typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD, bool COAL>
 __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ TC As[2][BK][LDS_LD];
@@ -136,7 +141,37 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
     const int64_t f0 = ROWS ? n0 : m0;
     if (FOLD == 1) mpend = false;
     load8(S + (k0 + vr) * ldS + f0 + vc, rres);  // resident factor tile, always in bounds
-    if (!ROWS) {
+    if constexpr (COAL && !ROWS) {
+      // element (k0 + 2e + (t >> 7), n0 + (t & 127)), e = 0..7
+      const int64_t col = n0 + (t & 127);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t k = k0 + 2 * e + (t >> 7);
+        TIn v = (TIn)0, w = (TIn)0;
+        if (k < K && col < a.R) {
+          v = X[(p * a.n + koff + k) * a.R + col];
+          if (FOLD == 1 && k < a.hh) w = X[(p * a.n + (a.n - 1 - k)) * a.R + col];
+        }
+        rdat[e] = v;
+        if (FOLD == 1) rmir[e] = w;
+      }
+      if (FOLD == 1) mpend = true;
+    } else if constexpr (COAL && ROWS && !CPLX) {
+      // element (m0 + 16e + (t >> 4), k0 + (t & 15)), e = 0..7
+      const int64_t k = k0 + (t & 15);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t m = m0 + 16 * e + (t >> 4);
+        TIn v = (TIn)0, w = (TIn)0;
+        if (m < a.M && k < K) {
+          v = X[m * a.n + koff + k];
+          if (FOLD == 1 && k < a.hh) w = X[m * a.n + (a.n - 1 - k)];
+        }
+        rdat[e] = v;
+        if (FOLD == 1) rmir[e] = w;
+      }
+      if (FOLD == 1) mpend = true;
+    } else if (!ROWS) {
       // B = X[p] row k, columns n0 + vc .. +7
       const int64_t k = k0 + vr, col = n0 + vc;
       if (k < K && vec_data && col + 8 <= a.R) {
@@ -243,7 +278,13 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
     }
     TC(*Res)[LDS_LD] = ROWS ? Bs[buf] : As[buf];
     store8(&Res[vr][vc], rres);
-    if (!ROWS) {
+    if constexpr (COAL && !ROWS) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[buf][2 * e + (t >> 7)][t & 127] = cvt_in<TIn, TC>(rdat[e]);
+    } else if constexpr (COAL && ROWS && !CPLX) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[buf][t & 15][16 * e + (t >> 4)] = cvt_in<TIn, TC>(rdat[e]);
+    } else if (!ROWS) {
       TC cv[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) cv[e] = cvt_in<TIn, TC>(rdat[e]);
@@ -289,8 +330,9 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   store_tile(0, rres0, rdat0);
   // Two k-tiles in flight in registers (the tile stored at the end of stage kt
   // was loaded at the start of stage kt - 1), except in the folding forward
-  // pass, whose mirror loads leave no registers for a second set.
-  constexpr bool kDeep = FOLD != 1;
+  // pass, whose mirror loads leave no registers for a second set, and in the
+  // element-wise instance, whose per-element addresses do not either.
+  constexpr bool kDeep = FOLD != 1 && !COAL;
   if (kDeep) {
     if (nk > 1) load_tile(BK, rres0, rdat0);
     __syncthreads();
@@ -346,22 +388,22 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
       }
 }
 
-template <typename TC, typename TIn, typename TOut, int FOLD>
+template <typename TC, typename TIn, typename TOut, int FOLD, bool COAL>
 hipError_t launch_fold(const KArgs& a, const PassArgs& pa, hipStream_t st) {
   dim3 grid((unsigned)a.nblocks), block(NT);
   if (a.rows) {
-    if (pa.cplx) hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, true, 0, FOLD>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, false, 0, FOLD>), grid, block, 0, st, a);
+    if (pa.cplx) hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, true, 0, FOLD, false>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, true, false, 0, FOLD, COAL>), grid, block, 0, st, a);
   } else if (pa.epi == Epi::Exp) {
     if (!pa.cplx) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Exp, FOLD>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Exp, FOLD, false>), grid, block, 0, st, a);
   } else if (pa.epi == Epi::Inv) {
     if (pa.cplx)
-      hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, true, (int)Epi::Inv, FOLD, false>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, (int)Epi::Inv, FOLD>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, (int)Epi::Inv, FOLD, COAL>), grid, block, 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, 0, FOLD>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_mfma<TC, TIn, TOut, false, false, 0, FOLD, COAL>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -461,10 +503,21 @@ hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   }
   if (a.nblocks <= 0) return hipSuccess;
   if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  // real data that allow no 16-byte access at all: the element-wise instance
+  constexpr int64_t VW = 16 / (int64_t)sizeof(TIn);
+  const bool aligned = (((uintptr_t)pa.X) & 15) == 0;
+  const bool coal = !pa.cplx && (a.rows ? !(aligned && pa.n % VW == 0 && (fold != 2 || F->ne % VW == 0))
+                                        : !(aligned && pa.R % VW == 0));
   hipError_t e;
-  if (fold == 1) e = launch_fold<TC, TIn, TOut, 1>(a, pa, st);
-  else if (fold == 2) e = launch_fold<TC, TIn, TOut, 2>(a, pa, st);
-  else e = launch_fold<TC, TIn, TOut, 0>(a, pa, st);
+  if (coal) {
+    if (fold == 1) e = launch_fold<TC, TIn, TOut, 1, true>(a, pa, st);
+    else if (fold == 2) e = launch_fold<TC, TIn, TOut, 2, true>(a, pa, st);
+    else e = launch_fold<TC, TIn, TOut, 0, true>(a, pa, st);
+  } else {
+    if (fold == 1) e = launch_fold<TC, TIn, TOut, 1, false>(a, pa, st);
+    else if (fold == 2) e = launch_fold<TC, TIn, TOut, 2, false>(a, pa, st);
+    else e = launch_fold<TC, TIn, TOut, 0, false>(a, pa, st);
+  }
   if (e != hipSuccess || fold != 2 || F->hh == 0) return e;
   // butterfly of the backward pass, in place on its output (R: real values per (p, i))
   return launch_unfold<TOut>((TOut*)pa.Y, pa.P, pa.n, pa.R, F->hh, st);
