@@ -339,8 +339,8 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
 //   reflect: K, m and f are reflection-symmetric (even/odd eigensolve, fold)
 // sym: factors (Q, Q^T), band bsym, mass roots; the solvers use it.
 // phys: T^{-1} = Q^T M^{1/2}, T = M^{-1/2} Q, band bphys; the public applies use it.
-static int build_axis_massed(int64_t n, double L, std::vector<double>& A, const std::vector<double>& bsym,
-                             const std::vector<double>& bphys, int bw, const std::vector<double>& m,
+static int build_axis_massed(int64_t n, double L, std::vector<double>& A, const std::vector<double>* bsym,
+                             const std::vector<double>* bphys, int bw, const std::vector<double>& m,
                              const std::vector<double>& x, const double* f, bool reflect,
                              std::shared_ptr<AxisFactor>& phys, std::shared_ptr<AxisFactor>& sym) {
   std::vector<double> ms(n);
@@ -367,7 +367,7 @@ static int build_axis_massed(int64_t n, double L, std::vector<double>& A, const 
   S->bw = bw;
   S->m_h = m;
   S->x_h = x;
-  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), &bsym, m, true, fp);
+  int rc = upload_factor(*S, f, S->Q_h, transpose(S->Q_h, n), bsym, m, true, fp);
   if (rc) return rc;
   auto P = std::make_shared<AxisFactor>();
   P->n = n;
@@ -384,7 +384,7 @@ static int build_axis_massed(int64_t n, double L, std::vector<double>& A, const 
       Fwd[(size_t)(i * n + j)] = ms[i] * q;   // (T^{-1})^T = M^{1/2} Q
       Bwd[(size_t)(j * n + i)] = q / ms[i];   // T^T = Q^T M^{-1/2}
     }
-  rc = upload_factor(*P, f, Fwd, Bwd, &bphys, m, true, fp);
+  rc = upload_factor(*P, f, Fwd, Bwd, bphys, m, true, fp);
   if (rc) return rc;
   phys = P;
   sym = S;
@@ -409,7 +409,7 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
       A[(size_t)(i * n + j)] = sij / (ms[i] * ms[j]);
     }
   // the mesh is symmetric; with symmetric f the operator is reflection-symmetric
-  return build_axis_massed(n, L, A, bsym, bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym);
+  return build_axis_massed(n, L, A, &bsym, &bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym);
 }
 
 // FP64 pass factor of a dense operator B (row-major n x n): the pass computes
@@ -445,7 +445,9 @@ static int build_axis_general(int64_t n, const double* K, const double* m_in, co
     ms[i] = std::sqrt(m[i]);
     x[i] = x_in ? x_in[i] : (double)i;
   }
-  const int64_t w = 2 * (int64_t)bw + 1;
+  // bands only for the band loop; wider operators run as dense passes and keep none
+  const bool banded = bw <= kBandMax;
+  const int64_t w = banded ? 2 * (int64_t)bw + 1 : 0;
   std::vector<double> A((size_t)(n * n)), bsym((size_t)(n * w), 0.0), bphys((size_t)(n * w), 0.0);
   double amax = 0.0, asym = 0.0, arefl = 0.0;
   for (int64_t i = 0; i < n; ++i)
@@ -479,7 +481,8 @@ static int build_axis_general(int64_t n, const double* K, const double* m_in, co
       for (int64_t j = 0; j < i; ++j)
         A0[(size_t)(i * n + j)] = A0[(size_t)(j * n + i)] = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
   }
-  int rc = build_axis_massed(n, 0.0, A, bsym, bphys, bw, m, x, f, reflect, phys, sym);
+  int rc = build_axis_massed(n, 0.0, A, banded ? &bsym : nullptr, banded ? &bphys : nullptr, bw, m, x, f, reflect,
+                             phys, sym);
   if (rc || bw <= kBandMax) return rc;
   rc = upload_op_pass(n, A0, sym->op_pass);
   if (rc) return rc;

@@ -51,7 +51,8 @@ struct AxisFactor {
   uint16_t* Q16 = nullptr;
   uint16_t* QT16 = nullptr;
   double* mass = nullptr;     // device [n]: L^2 quadrature weights (FD: h; SEM: lumped mass)
-  // SEM only: operator band [n][2 bw + 1] (entry (i, i - bw + t)), M^{1/2} and M^{-1/2}
+  // SEM and generic plans: operator band [n][2 bw + 1] (entry (i, i - bw + t); null when
+  // bw > kBandMax, the operator then runs as op_pass), M^{1/2} and M^{-1/2}
   int bw = 0;
   double* band = nullptr;
   double* msq = nullptr;
