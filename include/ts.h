@@ -108,9 +108,9 @@ int ts_destroy(ts_plan* plan);
  * then fold x into x_i +- x_{n-1-i} and contract half the extent against the
  * even and odd halves of the factor (half the MFMA work), with a butterfly
  * after each backward pass.  The result is the same up to rounding.  Applies
- * with BF16 transforms fold their forward passes only (those passes are
- * bandwidth-bound and the butterfly would cost more than it saves);
- * ts_mode_pass folds both directions in every precision.
+ * with BF16 transforms do not fold (their passes are not bound by the matrix
+ * cores, and the mirror loads and the butterfly cost more than they save);
+ * ts_mode_pass folds in every precision.
  * ts_set_fold(plan, 0) turns this off for the plan (1 turns it back on);
  * ts_fold_axes reports the axes that qualify as a bit mask (bit k = axis k). */
 int ts_set_fold(ts_plan* plan, int enable);

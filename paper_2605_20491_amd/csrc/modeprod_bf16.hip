@@ -26,6 +26,12 @@ typedef short s8 __attribute__((ext_vector_type(8)));
 constexpr int BM = 128, BN = 128, BK = 64, NT = 256;
 constexpr int LDK = BK + 8;  // padded row: 144 B, fragment reads are bank-conflict free
 
+// Column passes store the data tile transposed (one k-run per column row), and
+// rows 8 apart share a bank under any 16-byte-multiple row length; their 16-byte
+// k-chunks are therefore XOR-swizzled by the row group.  Position of k-chunk
+// `chunk` (8 elements) of row `row`, in elements:
+__device__ __forceinline__ int swz8(int row, int chunk) { return 8 * (chunk ^ ((row >> 3) & 7)); }
+
 __device__ __forceinline__ uint16_t to_bf16(double x) { return f32_to_bf16((float)x); }
 __device__ __forceinline__ uint16_t to_bf16(float x) { return f32_to_bf16(x); }
 __device__ __forceinline__ uint16_t to_bf16(uint16_t x) { return x; }
@@ -275,7 +281,11 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
     }
     if (!ROWS && coal_cols) {
 #pragma unroll
-      for (int c = 0; c < 32; ++c) Bs[buf][t & 127][2 * c + (t >> 7)] = to_bf16(rdat[c]);
+      for (int q = 0; q < 8; ++q) {  // k = 2c + (t >> 7) with c = 4q + r lies in chunk q
+        uint16_t* dst = &Bs[buf][t & 127][swz8(t & 127, q) + (t >> 7)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[2 * r] = to_bf16(rdat[4 * q + r]);
+      }
     } else if (ROWS && coal_rows) {
 #pragma unroll
       for (int c = 0; c < 32; ++c) As[buf][4 * c + (t >> 6)][t & 63] = to_bf16(rdat[c]);
@@ -286,7 +296,8 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
       for (int c = 0; c < 8; ++c) {
         uint32_t lo = (uint32_t)to_bf16(rdat[0 * 8 + c]) | ((uint32_t)to_bf16(rdat[1 * 8 + c]) << 16);
         uint32_t hi = (uint32_t)to_bf16(rdat[2 * 8 + c]) | ((uint32_t)to_bf16(rdat[3 * 8 + c]) << 16);
-        *(uint2*)&Bs[buf][8 * oc + c][4 * kq] = make_uint2(lo, hi);
+        const int row = 8 * oc + c;
+        *(uint2*)&Bs[buf][row][swz8(row, kq >> 1) + 4 * (kq & 1)] = make_uint2(lo, hi);
       }
     } else if (!CPLX) {
       const int row = t >> 1, half = t & 1;
@@ -334,7 +345,10 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) av[i] = *(const s8*)&As[cur][wm * 64 + i * 16 + lr][ks * 32 + 8 * lg];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = *(const s8*)&Bs[cur][wn * 64 + j * 16 + lr][ks * 32 + 8 * lg];
+      for (int j = 0; j < 4; ++j) {
+        const int row = wn * 64 + j * 16 + lr;
+        bv[j] = *(const s8*)&Bs[cur][row][ROWS ? ks * 32 + 8 * lg : swz8(row, 4 * ks + lg)];
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll

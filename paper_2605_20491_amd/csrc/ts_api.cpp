@@ -584,9 +584,9 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     for (int m = k + 1; m < d; ++m) pa.R *= p->n[m];
     pa.cplx = cplx;
     pa.skip = ap.skip;
-    // BF16 passes are bandwidth-bound: the butterfly after a folded backward pass
-    // costs more than the MFMA work it saves, so BF16 folds the forward passes only
-    pa.fold = pa.fac->fold && p->fold_enabled && (fwd || ap.prec != TS_PREC_BF16);
+    // BF16 passes are not MFMA-bound: folding saves them no time (the butterfly and
+    // the mirror loads cost more than the halved MFMA work), so BF16 applies do not fold
+    pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
     if (fwd && t == d) {
       pa.epi = ap.epi;
       pa.Lp = p->Lp;
