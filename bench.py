@@ -446,6 +446,53 @@ def gpe_section(ts, W, torch, dev, betas=(10.0, 100.0), cells=30, k=20, tol=1e-1
     return out
 
 
+def gpe1600_section(ts, W, torch, dev, cells=30, k=20):
+    """Table tab:au_vs_h1: beta = 1600, V1 of eq. (separable_V1) on [-8,8]^3,
+    Q^20 SEM at 599^3, constant initial guess; the a_u flow (tau = 1, PCG with
+    (-Delta + V1)^{-1}) and the modified H^1 flow (alpha = 20, tau = 0.1).  The
+    flows run until the successive energy change is below 1e-15 (relative);
+    the iteration at which |E_k - E*| / E* < 1e-12 (the table's criterion,
+    E* = 33.80227900547423) is read off the energy history."""
+    import numpy as np
+    L, beta, Estar = 8.0, 1600.0, 33.80227900547423
+    x = ts.ts_sem_nodes(k, cells, L)
+    v = W.f_separable_v1(0, L, x=x)
+    lap = ts.ts_setup_sem(k, (cells,) * 3, L, [np.zeros_like(x)] * 3, 1.0)
+    pv1 = ts.ts_setup_sem(k, (cells,) * 3, L, [v] * 3, 1.0)
+    vd = torch.from_numpy(v).to(dev)
+    V = (vd[:, None, None] + vd[None, :, None] + vd[None, None, :]).contiguous()
+    shape = (x.size,) * 3
+    out = {"n": x.size, "beta": beta, "E_star": Estar,
+           "paper_gh200": {"au": {"iters": 66, "linear_solves": 790, "s": 72.8, "energy": 33.80227900550},
+                           "h1": {"iters": 272, "linear_solves": 544, "s": 42.6, "energy": 33.80227900551}}}
+    for method in ("au", "h1"):
+        u = torch.ones(shape, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if method == "au":
+            r = ts.ts_gpe_au_flow(pv1, None, beta, u, tau=1.0, maxit=300, tol=1e-15, pcg_rtol=1e-12,
+                                  raise_on_noconv=False)
+        else:
+            r = ts.ts_gpe_h1_flow(lap, V, beta, u, alpha=20.0, tau=0.1, maxit=800, tol=1e-15,
+                                  raise_on_noconv=False)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        err = np.abs(r.history - Estar) / Estar
+        hit = np.nonzero(err < 1e-12)[0]
+        k12 = int(hit[0]) if hit.size else None
+        res = {"iters": r.iters, "s": sec, "s_per_iter": sec / max(r.iters, 1), "energy": r.energy,
+               "iters_to_1e-12": k12, "s_to_1e-12": None if k12 is None else sec * k12 / max(r.iters, 1)}
+        if method == "au":
+            res["linear_solves"] = r.linear_iters
+        out[method] = res
+        log("gpe beta=1600 %s flow: %d steps %.2f s, E %.13f, |E-E*|/E* < 1e-12 after %s steps (~%s s)"
+            % (method, r.iters, sec, r.energy, k12, None if k12 is None else "%.1f" % res["s_to_1e-12"]))
+        del u
+    del lap, pv1, V
+    torch.cuda.empty_cache()
+    return out
+
+
 def multilevel_section(ts, W, torch, dev, k=20, cells=(5, 10, 25)):
     """Table tab:multilevel: the stirrer potential, Q^20 SEM 99^3 -> 199^3 -> 499^3."""
     import numpy as np
@@ -740,6 +787,7 @@ def main():
         extra["hermite_table"] = hermite_section(ts, W, torch, dev)
     if not args.no_gpe:
         extra["gpe_h1_flow_599"] = gpe_section(ts, W, torch, dev)
+        extra["gpe_beta1600_599"] = gpe1600_section(ts, W, torch, dev)
         extra["multilevel_stirrer"] = multilevel_section(ts, W, torch, dev)
     if args.serve_requests > 0:
         extra["serving"] = serve_section(ts, W, torch, dev, args.serve_requests)
