@@ -15,6 +15,7 @@ namespace ts {
 namespace {
 
 constexpr int kMarch = 32;       // stencil: points per thread along axis 0
+constexpr int kGroup = 4;        // stencil: points whose loads are issued together
 
 // Stencil: each thread owns one index r of the faster axes (1..d-1) and a run
 // of kMarch consecutive points along axis 0, keeping the axis-0 neighbours in
@@ -48,24 +49,45 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a) {
     const int64_t i_end = i_beg + kMarch < n0 ? i_beg + kMarch : n0;
     double um = i_beg > 0 ? a.u[(i_beg - 1) * rest + r] : 0.0;
     double uc = a.u[i_beg * rest + r];
-    for (int64_t i = i_beg; i < i_end; ++i) {
-      const int64_t idx = i * rest + r;
-      const double up = (i + 1 < n0) ? a.u[idx + rest] : 0.0;
-      double acc = a.ih2[0] * (2.0 * uc - um - up);
+    // groups of kGroup points along axis 0: every load of a group is issued
+    // before its arithmetic (the per-point operations and their order are
+    // those of one point at a time)
+    for (int64_t i = i_beg; i < i_end; i += kGroup) {
+      const int cnt = (int)(i_end - i < kGroup ? i_end - i : kGroup);
+      double uv[kGroup + 1];  // u at axis-0 index i .. i + kGroup
+      uv[0] = uc;
+#pragma unroll
+      for (int j = 1; j <= kGroup; ++j) uv[j] = (j <= cnt && i + j < n0) ? a.u[(i + j) * rest + r] : 0.0;
+      double acc[kGroup];
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) acc[j] = a.ih2[0] * (2.0 * uv[j] - (j == 0 ? um : uv[j - 1]) - uv[j + 1]);
       for (int k = 1; k < a.d; ++k) {
         const int64_t st = a.stride[k];
-        const double lo = ((lo_ok >> k) & 1u) ? a.u[idx - st] : 0.0;
-        const double hi = ((hi_ok >> k) & 1u) ? a.u[idx + st] : 0.0;
-        acc += a.ih2[k] * (2.0 * uc - lo - hi);
+        const bool lk = (lo_ok >> k) & 1u, hk = (hi_ok >> k) & 1u;
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+          if (j < cnt) {
+            const int64_t idx = (i + j) * rest + r;
+            const double lo = lk ? a.u[idx - st] : 0.0;
+            const double hi = hk ? a.u[idx + st] : 0.0;
+            acc[j] += a.ih2[k] * (2.0 * uv[j] - lo - hi);
+          }
+        }
       }
-      double diag = fsum + a.f[0][i] + (a.V2 ? a.V2[idx] : 0.0);
-      double v = acc + diag * uc;
-      if (MODE == (int)StOut::FminusAx) v = a.rhs[idx] - v;
-      a.out[idx] = v;
-      if (DOT == (int)StDot::UdotOut) dsum += uc * v;
-      if (DOT == (int)StDot::OutdotOut) dsum += v * v;
-      um = uc;
-      uc = up;
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j) {
+        if (j < cnt) {
+          const int64_t idx = (i + j) * rest + r;
+          double diag = fsum + a.f[0][i + j] + (a.V2 ? a.V2[idx] : 0.0);
+          double v = acc[j] + diag * uv[j];
+          if (MODE == (int)StOut::FminusAx) v = a.rhs[idx] - v;
+          a.out[idx] = v;
+          if (DOT == (int)StDot::UdotOut) dsum += uv[j] * v;
+          if (DOT == (int)StDot::OutdotOut) dsum += v * v;
+        }
+      }
+      um = uv[cnt - 1];
+      uc = uv[cnt];
     }
   }
   if (DOT) {
