@@ -752,6 +752,19 @@ def main():
                 log("%s inverse %.2f ms/apply" % (prec, msx))
             except ts.TSError as e:
                 extra["inverse_%s" % prec] = "unavailable: %s" % e.status
+        # mixed-precision direct inverse refined to 1e-10 (FP64 residuals, FP32 / BF16 inner applies)
+        for inner in ("fp32", "bf16"):
+            ur = torch.empty_like(b)
+            it_rr = {}
+
+            def run_refined():
+                _, it_rr["it"], it_rr["rr"] = ts.ts_solve_refined(plan, b, ur, inner=inner, rtol=1e-10, maxit=60)
+            msr, _ = timed(run_refined, max(1, args.steps // 4), 1)
+            extra["refined_%s" % inner] = {"ms": msr, "iters": it_rr["it"], "relres": it_rr["rr"],
+                                          "dof_s": N / (msr * 1e-3)}
+            log("%s inverse refined to 1e-10: %.1f ms, %d iterations, relres %.2e"
+                % (inner, msr, it_rr["it"], it_rr["rr"]))
+            del ur
         del u
         facs = W.wavepacket_factors(shape, L, 2)
         g = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in facs]
