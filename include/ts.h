@@ -142,7 +142,10 @@ int ts_fold_axes(const ts_plan* plan, int* folded);
  * ts_operator_apply applies M^{-1} S per axis (band of 2k+1 entries); the
  * solvers (PCG, refinement, inverse iteration) run in the mass inner product
  * sum_p (prod_a m_a) x_p y_p, in which H1 + V2 is self-adjoint, so their
- * residual norms and eigenvector normalisation are mass-weighted.
+ * residual norms and eigenvector normalisation are mass-weighted.  When an
+ * axis has n[a] >= 128 the operator apply runs as one FP64 matrix-core pass
+ * per axis restricted to the band |i - j| <= k, in two N-sized FP64 buffers
+ * the plan allocates on first use and keeps until ts_destroy.
  * Errors: TS_ERR_INVALID, TS_ERR_NONFINITE, TS_ERR_NOMEM, TS_ERR_DEVICE. */
 int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* const* f, double sigma,
                  ts_plan** out);

@@ -310,7 +310,16 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = V{0, 0, 0, 0};
 
-  const int64_t nk = (K + BK - 1) / BK;
+  // banded factor (a block-banded operator, |i - j| <= kband): only the k-tiles
+  // that meet the band of this tile's outputs contribute (the others are zero)
+  int64_t kbeg = 0, kend = K;
+  if (a.kband > 0) {
+    const int64_t o0 = ROWS ? n0 : m0, o1 = o0 + (ROWS ? BN : BM);
+    kbeg = o0 > a.kband ? o0 - a.kband : 0;
+    kbeg -= kbeg % BK;
+    kend = o1 + a.kband < K ? o1 + a.kband : K;
+  }
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   auto compute = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
@@ -326,7 +335,7 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
     }
   };
-  load_tile(0, rres0, rdat0);
+  load_tile(kbeg, rres0, rdat0);
   store_tile(0, rres0, rdat0);
   // Two k-tiles in flight in registers (the tile stored at the end of stage kt
   // was loaded at the start of stage kt - 1), except in the folding forward
@@ -334,11 +343,11 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   // element-wise instance, whose per-element addresses do not either.
   constexpr bool kDeep = FOLD != 1 && !COAL;
   if (kDeep) {
-    if (nk > 1) load_tile(BK, rres0, rdat0);
+    if (nk > 1) load_tile(kbeg + BK, rres0, rdat0);
     __syncthreads();
     auto stage = [&](int64_t kt, TC (&ra)[8], TIn (&da)[8], TC (&rb)[8], TIn (&db)[8]) {
       const int cur = (int)(kt & 1);
-      if (kt + 2 < nk) load_tile((kt + 2) * BK, rb, db);
+      if (kt + 2 < nk) load_tile(kbeg + (kt + 2) * BK, rb, db);
       compute(cur);
       if (kt + 1 < nk) store_tile(cur ^ 1, ra, da);
       __syncthreads();
@@ -351,7 +360,7 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
     __syncthreads();
     for (int64_t kt = 0; kt < nk; ++kt) {
       const int cur = (int)(kt & 1);
-      if (kt + 1 < nk) load_tile((kt + 1) * BK, rres0, rdat0);
+      if (kt + 1 < nk) load_tile(kbeg + (kt + 1) * BK, rres0, rdat0);
       compute(cur);
       if (kt + 1 < nk) store_tile(cur ^ 1, rres0, rdat0);
       __syncthreads();

@@ -71,6 +71,7 @@ struct KArgs {
   const void* Se;     // half factors, k-major [fld][fld]
   const void* So;
   int64_t fld;
+  int64_t kband;      // > 0: the factor vanishes for |k - output| > kband
 };
 
 // Map the hardware block id to a logical tile id so that consecutive logical
@@ -100,6 +101,7 @@ inline void fill_kargs(const PassArgs& pa, KArgs& a, const void* S, int bm, int 
   a.Er = pa.Er;
   a.es = pa.es;
   a.skip = pa.skip;
+  a.kband = pa.kband;
   a.rows = (pa.R == 1 || (pa.cplx && pa.R == 2)) && pa.epi == Epi::None;
   if (a.rows) {
     a.M = pa.P * (pa.cplx ? 2 : 1);

@@ -391,8 +391,24 @@ static int build_axis_massed(int64_t n, double L, std::vector<double>& A, const 
   return TS_OK;
 }
 
+static int upload_op_pass(int64_t n, const std::vector<double>& B, std::shared_ptr<AxisFactor>& out);
+
+// Dense row-major n x n matrix of a band [n][2 bw + 1] (entry (i, i - bw + t)).
+static std::vector<double> band_to_dense(int64_t n, int bw, const std::vector<double>& band) {
+  const int64_t w = 2 * (int64_t)bw + 1;
+  std::vector<double> B((size_t)(n * n), 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t t = 0; t < w; ++t) {
+      const int64_t j = i - bw + t;
+      if (j >= 0 && j < n) B[(size_t)(i * n + j)] = band[(size_t)(i * w + t)];
+    }
+  return B;
+}
+
 // Q^k SEM axis: K = M^{-1} S from the Gauss-Lobatto mass and stiffness band.
-static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::shared_ptr<AxisFactor>& phys,
+// op: also keep the operator as banded FP64 pass factors (the plan applies its
+// operator as matrix-core passes restricted to the band).
+static int build_axis_sem(int k, int64_t cells, double L, const double* f, bool op, std::shared_ptr<AxisFactor>& phys,
                           std::shared_ptr<AxisFactor>& sym) {
   SemAxis ax;
   if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis"); return TS_ERR_INVALID; }
@@ -409,7 +425,15 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, std::
       A[(size_t)(i * n + j)] = sij / (ms[i] * ms[j]);
     }
   // the mesh is symmetric; with symmetric f the operator is reflection-symmetric
-  return build_axis_massed(n, L, A, &bsym, &bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym);
+  int rc = build_axis_massed(n, L, A, &bsym, &bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym);
+  if (rc || !op) return rc;
+  rc = upload_op_pass(n, band_to_dense(n, k, bsym), sym->op_pass);
+  if (rc) return rc;
+  rc = upload_op_pass(n, band_to_dense(n, k, bphys), phys->op_pass);
+  if (rc) return rc;
+  sym->op_pass->bw = k;
+  phys->op_pass->bw = k;
+  return TS_OK;
 }
 
 // FP64 pass factor of a dense operator B (row-major n x n): the pass computes
@@ -878,6 +902,8 @@ int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* con
   p->massed = true;
   hipGetDevice(&p->device);
   std::map<std::pair<int64_t, std::string>, std::pair<std::shared_ptr<AxisFactor>, std::shared_ptr<AxisFactor>>> cache;
+  bool op = false;  // one decision for the whole plan: every axis or none has operator pass factors
+  for (int a = 0; a < d; ++a) op = op || (int64_t)k * cells[a] - 1 >= kOpPassMinN;
   for (int a = 0; a < d; ++a) {
     const int64_t n = (int64_t)k * cells[a] - 1;
     p->n[a] = n;
@@ -885,7 +911,7 @@ int ts_setup_sem(int d, const int64_t* cells, int k, double L, const double* con
     auto it = cache.find({cells[a], key});
     if (it == cache.end()) {
       std::shared_ptr<AxisFactor> P, S;
-      int rc = build_axis_sem(k, cells[a], L, f[a], P, S);
+      int rc = build_axis_sem(k, cells[a], L, f[a], op, P, S);
       if (rc) return rc;
       it = cache.insert({{cells[a], key}, {P, S}}).first;
     }

@@ -22,6 +22,7 @@ void set_error(const std::string& msg);
 // Tile geometry shared by launchers and the plan's padded matrix storage.
 constexpr int kTileF = 128;   // free-index tile width of the MFMA kernels
 constexpr int kBandMax = 32;  // widest operator band read by the band loop; wider: MFMA passes
+constexpr int64_t kOpPassMinN = 128;  // SEM plans with an axis this long apply the operator as banded MFMA passes
 constexpr int kTileK = 32;    // K padding granularity (covers BK of every kernel)
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -106,6 +107,7 @@ struct PassArgs {
   const double2* es = nullptr;
   const int* skip = nullptr;   // if non-null and *skip != 0 the kernel returns
   bool fold = false;           // half-extent pass of a symmetric axis
+  int64_t kband = 0;           // > 0: the factor is banded, |k - output| <= kband (FP64 passes)
 };
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);

@@ -351,6 +351,7 @@ static hipError_t launch_dense_operator(const StencilArgs& a, hipStream_t st) {
     for (int m = 0; m < k; ++m) pa.P *= a.n[m];
     for (int m = k + 1; m < a.d; ++m) pa.R *= a.n[m];
     pa.skip = a.skip;
+    pa.kband = a.dense[k]->bw;  // SEM: band half-width k; generic dense operators: 0 (all of K)
     hipError_t e = launch_pass(pa, st);
     if (e != hipSuccess) return e;
     if (k >= 1 && k + 1 < a.d) {

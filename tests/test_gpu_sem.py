@@ -215,3 +215,37 @@ def test_accuracy_table_full_size(name, d, k, cells, printed, tol):
         assert err <= FLOOR_BAR
     else:
         assert abs(err - printed) / printed <= tol
+
+
+def test_sem_banded_operator_passes():
+    """A plan with an axis of n >= 128 applies its operator as FP64 matrix-core
+    passes restricted to the band (|i - j| <= k): the public operator, the
+    symmetric-form operator inside PCG and the GPE step against the oracle."""
+    k, cells, L = 3, (50, 44, 12), 6.0  # n = 149, 131, 35
+    plan, oplan, f = sem_pair(k, cells, L=L, kind="rand", seed=9)
+    rng = np.random.default_rng(10)
+    V2 = rng.uniform(0.0, 3.0, plan.shape)
+    u = W.rhs_normal(plan.shape, 11)
+    got = to_host(ts.ts_operator_apply(plan, to_dev(V2), 0.5, to_dev(u)))
+    e_op = rel(got, oracle.operator_apply(oplan, u, V2, 0.5))
+    rhs = W.rhs_normal(plan.shape, 12)
+    x = torch.zeros(plan.shape, dtype=torch.float64, device=DEV)
+    _, its, rr, _ = ts.ts_pcg_solve(plan, to_dev(V2), to_dev(rhs), x, rtol=1e-10, maxit=300)
+    xh = to_host(x)
+    true = oracle.norm(oplan, rhs - oracle.operator_apply(oplan, xh, V2, 1.0)) / oracle.norm(oplan, rhs)
+    # GPE: one modified H^1 step on a -Delta plan of the same mesh
+    lap = ts.ts_setup_sem(k, cells, L, [np.zeros_like(a) for a in f], 1.0)
+    olap = oracle.make_plan_sem(k, cells, L, [np.zeros_like(a) for a in f])
+    Vg = V2
+    w = oracle.l2_weights(olap)
+    u0 = np.abs(W.rhs_normal(plan.shape, 13)) + 0.1
+    u0 = u0 / np.sqrt(np.sum(w * u0 * u0))
+    ref = oracle.h1_flow_step(olap, Vg, 30.0, 10.0, 0.1, u0)
+    ud = to_dev(u0)
+    ts.ts_gpe_h1_flow(lap, to_dev(Vg), 30.0, ud, alpha=10.0, tau=0.1, maxit=1, tol=0.0, raise_on_noconv=False)
+    e_gpe = rel(to_host(ud), ref)
+    announce("sem banded passes %s: operator %.2e, pcg %d its true %.2e, gpe step %.2e"
+             % (plan.shape, e_op, its, true, e_gpe))
+    assert e_op <= 1e-13
+    assert true <= 2e-10
+    assert e_gpe <= 1e-12
