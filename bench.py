@@ -718,14 +718,22 @@ def main():
     resid = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
     del r
 
-    # dominant kernel: the forward pass on axis 1 (a column pass, half extent on a symmetric axis),
-    # timed on its own with HIP events on the stream the library launches on
-    folded = bool(ts.ts_fold_axes(plan) & 2)
+    # dominant kernel: the forward pass on axis 1 (a column pass, half extent on a symmetric axis,
+    # on input folded beforehand as inside the apply), timed on its own with HIP events on the
+    # stream the library launches on
+    fmask = ts.ts_fold_axes(plan)
+    folded = bool(fmask & 2)
+    deferred = folded and bin(fmask).count("1") >= 2
     hh, cc = n // 2, n % 2
     flops_pass = 2.0 * (N / n) * ((hh + cc) ** 2 + hh ** 2) if folded else 2.0 * N * n
     work = torch.empty_like(b)
-    t_pass, _ = timed(lambda: ts.ts_mode_pass(plan, 1, True, b, work), args.steps, 1)
-    t_back, _ = timed(lambda: ts.ts_mode_pass(plan, 1, False, b, work), args.steps, 1)
+    t_pass, _ = timed(lambda: ts.ts_mode_pass(plan, 1, True, b, work, folded=deferred), args.steps, 1)
+    t_back, _ = timed(lambda: ts.ts_mode_pass(plan, 1, False, b, work, folded=deferred), args.steps, 1)
+    t_bfly = None
+    if deferred:
+        t_bfly, _ = timed(lambda: ts.ts_fold_butterfly(plan, fmask, b, work), args.steps, 1)
+        log("single launches: forward pass %.2f ms, backward pass %.2f ms, %d-axis butterfly %.2f ms"
+            % (t_pass, t_back, bin(fmask).count("1"), t_bfly))
     del work
     achieved = flops_pass / (t_pass * 1e-3) / 1e12
     traffic, tinfo = measured_traffic()
@@ -735,11 +743,13 @@ def main():
                 "traffic_note": (tinfo if isinstance(tinfo, str) else
                                  (None if tinfo is None else {k: tinfo[k] for k in ("fetch_bytes", "write_bytes",
                                                                                      "copy_scale", "profile")})),
-                "kernel": ("k_mode_mfma<double, cols, FOLD=1>: FP64 16x16x4 MFMA forward pass over half the extent "
+                "kernel": ("k_mode_mfma<double, cols, FOLD=3>: FP64 16x16x4 MFMA forward pass over half the extent "
+                           "on folded data (even/odd halves of a symmetric axis)" if deferred else
+                           "k_mode_mfma<double, cols, FOLD=1>: FP64 16x16x4 MFMA forward pass over half the extent "
                            "(even/odd halves of a symmetric axis)" if folded else
                            "k_mode_mfma<double, cols>: FP64 16x16x4 MFMA forward pass"),
                 "per_launch_flops": flops_pass, "avg_launch_ms": t_pass,
-                "backward_pass_ms": t_back, "apply_ms": ms, "folded": folded}
+                "backward_pass_ms": t_back, "butterfly_ms": t_bfly, "apply_ms": ms, "folded": folded}
 
     extra = {"setup_s": setup_s, "fp64_relres": resid, "wall_s_timed": wall}
     if not args.no_extras:

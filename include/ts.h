@@ -107,7 +107,9 @@ int ts_destroy(ts_plan* plan);
  * even or odd; the passes on that axis (n_k >= 64, every transform precision)
  * then fold x into x_i +- x_{n-1-i} and contract half the extent against the
  * even and odd halves of the factor (half the MFMA work), with a butterfly
- * after each backward pass.  The result is the same up to rounding.  Applies
+ * after each backward pass; with two or more such axes an apply folds its
+ * input and unfolds its output once for all of them (ts_fold_butterfly) and
+ * its passes run on folded data.  The result is the same up to rounding.  Applies
  * with BF16 transforms do not fold (their passes are not bound by the matrix
  * cores, and the mirror loads and the butterfly cost more than they save);
  * ts_mode_pass folds in every precision.
@@ -121,10 +123,30 @@ int ts_set_fold(ts_plan* plan, int enable);
  * For measuring and checking the pass kernels on their own.  in, out: device
  * arrays of the grid (must not alias); dtype any of ts_dtype; prec FP64 (FP64
  * data), FP32, or BF16 (operands rounded to BF16, FP32 accumulation, result
- * stored in the data type).  Errors: TS_ERR_INVALID, TS_ERR_DEVICE. */
+ * stored in the data type).
+ *   forward = 1: forward pass; 0: backward pass (with its butterfly on a
+ *   folding axis);
+ *   2: forward pass whose input is already folded along this axis
+ *      (ts_fold_butterfly), as inside an apply with several folded axes;
+ *   3: backward pass that leaves the butterfly out: E_i at row i (i < n - h)
+ *      and O_i at row n - 1 - i (i < h, h = floor(n / 2)).
+ * On an axis that does not fold, 2 and 3 are 1 and 0.  Modes 2 and 3 take
+ * FP64 or FP32 transforms.  Errors: TS_ERR_INVALID, TS_ERR_DEVICE. */
 int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out, int dtype, int prec,
                  void* hip_stream);
 int ts_fold_axes(const ts_plan* plan, int* folded);
+
+/* The butterfly of the half-extent passes along every axis k in the bit mask
+ * `axes` (bit k = axis k): out_i = in_i + in_{n-1-i} and out_{n-1-i} = in_i -
+ * in_{n-1-i} for i < floor(n_k / 2), the middle row of odd n_k copied (a
+ * linear map on one axis each, so the order of the axes does not matter; two
+ * applications give 2x the input per axis, except on the middle row).  It folds the input of the
+ * forward passes and unfolds the output of the backward passes; an apply with
+ * several folded axes runs it once before and once after its passes (up to
+ * four axes per sweep over the data).  in, out: device arrays of the grid,
+ * dtype any of ts_dtype (complex: on both components); out may equal in.
+ * Enqueued on hip_stream.  Errors: TS_ERR_INVALID, TS_ERR_DEVICE. */
+int ts_fold_butterfly(ts_plan* plan, int axes, const void* in, void* out, int dtype, void* hip_stream);
 
 /* Plan of the Q^k spectral-element discretisation (Sec. 2, eq. (eigen_decomp)):
  * each axis of [-L, L] is split into cells[a] equal elements carrying the

@@ -53,6 +53,7 @@ def lib():
             "ts_destroy": [_vp],
             "ts_set_fold": [_vp, ctypes.c_int],
             "ts_mode_pass": [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
+            "ts_fold_butterfly": [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp],
             "ts_fold_axes": [_vp, _ip],
             "ts_setup_sem": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
@@ -263,12 +264,24 @@ def ts_set_fold(plan: Plan, enable: bool):
     _check(lib().ts_set_fold(plan.handle, int(bool(enable))), "ts_set_fold")
 
 
-def ts_mode_pass(plan: Plan, axis: int, forward: bool, x, out=None, prec="fp64", stream=None):
+def ts_mode_pass(plan: Plan, axis: int, forward: bool, x, out=None, prec="fp64", stream=None, folded=False):
+    """folded=True: forward on input already folded along the axis (mode 2),
+    backward without the butterfly (mode 3)."""
     torch = _torch()
     if out is None:
         out = torch.empty_like(x)
-    _check(lib().ts_mode_pass(plan.handle, int(axis), int(bool(forward)), _dev(x, plan, "x"), _dev(out, plan, "out"),
+    mode = (2 if forward else 3) if folded else (1 if forward else 0)
+    _check(lib().ts_mode_pass(plan.handle, int(axis), mode, _dev(x, plan, "x"), _dev(out, plan, "out"),
                               _dtype_code(x), _prec(prec), _stream(stream)), "ts_mode_pass")
+    return out
+
+
+def ts_fold_butterfly(plan: Plan, axes: int, x, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().ts_fold_butterfly(plan.handle, int(axes), _dev(x, plan, "x"), _dev(out, plan, "out"),
+                                   _dtype_code(x), _stream(stream)), "ts_fold_butterfly")
     return out
 
 

@@ -25,7 +25,15 @@
 //            (the fold is applied as the data tile is loaded);
 //   backward (FOLD = 2): E = Be^T z_even, O = Bo^T z_odd, written with O's
 //            rows reversed (row n-1-i), then x_i = E_i + O_i and
-//            x_{n-1-i} = E_i - O_i by the in-place butterfly k_unfold.
+//            x_{n-1-i} = E_i - O_i by the in-place butterfly k_unfold;
+//   forward on folded data (FOLD = 3): the input already holds s_i at row i
+//            and d_i at row n-1-i (the same butterfly, applied beforehand to
+//            every folded axis at once by k_butterfly), so the pass reads
+//            rows [0, h + c) for the even half and [h + c, n) for the odd
+//            half against Fr, Fo with its rows reversed: no mirror loads.
+// The butterflies commute with the passes over the other axes, so an apply
+// with several folded axes folds its input once and unfolds its output once
+// (two data sweeps in place of one per folded axis).
 // Tiles of the output dimension are split between the two halves, so each
 // tile runs one half-size GEMM: half the MFMA work of the plain pass.
 #include <type_traits>
@@ -110,14 +118,14 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
     int64_t& split = ROWS ? ntile : mtile;
     odd = split >= a.te;
     if (odd) split -= a.te;
-    K = FOLD == 1 ? (odd ? a.hh : a.hh + a.cc) : (odd ? a.no : a.ne);
+    K = FOLD == 1 ? (odd ? a.hh : a.hh + a.cc) : (odd ? a.no : a.ne);  // FOLD 3: as 2
     S = (const TC*)(odd ? a.So : a.Se);
     ldS = a.fld;
   }
   const int64_t m0 = mtile * BM, n0 = ntile * BN;
   const TIn* X = (const TIn*)a.X;
   // input row (along the pass axis) feeding GEMM index k; FOLD = 1 adds the mirror
-  const int64_t koff = (FOLD == 2 && odd) ? a.ne : 0;
+  const int64_t koff = (FOLD >= 2 && odd) ? a.ne : 0;
 
   TC rres0[8], rres1[8];
   TIn rdat0[8], rdat1[8];
@@ -384,9 +392,9 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
         if (FOLD) {
           // index along the pass axis within this half, and its place in the output
           const int64_t loc = ROWS ? col : m;
-          const int64_t cnt = FOLD == 1 ? (odd ? a.no : a.ne) : (odd ? a.hh : a.hh + a.cc);
+          const int64_t cnt = FOLD != 2 ? (odd ? a.no : a.ne) : (odd ? a.hh : a.hh + a.cc);
           if (loc >= cnt) continue;
-          const int64_t dst = FOLD == 1 ? (odd ? a.ne + loc : loc) : (odd ? a.n - 1 - loc : loc);
+          const int64_t dst = FOLD != 2 ? (odd ? a.ne + loc : loc) : (odd ? a.n - 1 - loc : loc);
           if (ROWS) store_rows<TOut, CPLX>(a, Y, m, dst, v);
           else store_cols<TOut, CPLX, EPI>(a, Y, p, dst, col, v, partner);
         } else if (ROWS) {
@@ -474,6 +482,105 @@ hipError_t launch_unfold(T* Y, int64_t P, int64_t n, int64_t R, int64_t hh, hipS
   return hipGetLastError();
 }
 
+// The butterfly along NAX axes at once: thread e owns one point with i_a <= n_a - 1 - i_a
+// on every listed axis and the up to 2^NAX points of its orbit under the reflections.
+// An axis on which the point is its own mirror (the middle of odd n) is left as it is.
+template <typename T, int NAX>
+__global__ __launch_bounds__(256) void k_butterfly(const T* X, T* Y, ButterflyArgs a, int64_t total) {
+  if (a.skip && *a.skip) return;
+  constexpr int NV = 1 << NAX;
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    // coordinates of the representative point, fastest (the component) first
+    int64_t rest = e / a.ncomp;
+    int64_t off = e - rest * a.ncomp;
+    int64_t stride = a.ncomp;
+    int64_t delta[NAX];
+    bool act[NAX];
+#pragma unroll
+    for (int j = 0; j < NAX; ++j) {
+      delta[j] = 0;
+      act[j] = false;
+    }
+    for (int k = a.d - 1; k >= 0; --k) {
+      int jf = -1;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (a.ax[j] == k) jf = j;
+      const int64_t ext = jf >= 0 ? a.n[k] - a.hh[jf] : a.n[k];  // h + c representatives
+      const int64_t q = rest / ext;
+      const int64_t i = rest - q * ext;
+      rest = q;
+      off += i * stride;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (j == jf && i < a.hh[j]) {
+          act[j] = true;
+          delta[j] = (a.n[k] - 1 - 2 * i) * stride;
+        }
+      stride *= a.n[k];
+    }
+    T v[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      v[m] = ok ? X[o] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < NAX; ++j) {
+      if (!act[j]) continue;
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (!(m & (1 << j))) {
+          const T x0 = v[m], x1 = v[m | (1 << j)];
+          v[m] = x0 + x1;
+          v[m | (1 << j)] = x0 - x1;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      if (ok) Y[o] = v[m];
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_butterfly_t(const ButterflyArgs& a, hipStream_t st) {
+  int64_t total = a.ncomp;
+  for (int k = 0; k < a.d; ++k) {
+    int64_t ext = a.n[k];
+    for (int j = 0; j < a.nax; ++j)
+      if (a.ax[j] == k) ext = a.n[k] - a.hh[j];
+    total *= ext;
+  }
+  if (total <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  const T* X = (const T*)a.X;
+  T* Y = (T*)a.Y;
+  switch (a.nax) {
+    case 1: hipLaunchKernelGGL((k_butterfly<T, 1>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    case 2: hipLaunchKernelGGL((k_butterfly<T, 2>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    case 3: hipLaunchKernelGGL((k_butterfly<T, 3>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    case 4: hipLaunchKernelGGL((k_butterfly<T, 4>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename TC, typename TIn, typename TOut>
 hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   KArgs a{};
@@ -483,7 +590,7 @@ hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   if (dbl) S = pa.forward ? (const void*)F->Q64 : (const void*)F->QT64;
   else S = pa.forward ? (const void*)F->Q32 : (const void*)F->QT32;
   fill_kargs(pa, a, S, BM, BN);
-  const int fold = pa.fold ? (pa.forward ? 1 : 2) : 0;
+  const int fold = pa.fold ? (pa.forward ? (pa.deferred ? 3 : 1) : 2) : 0;
   if (fold) {
     a.ne = F->ne;
     a.no = F->no;
@@ -492,13 +599,14 @@ hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
     a.fld = F->fkp;
     if (pa.forward) {
       a.Se = dbl ? (const void*)F->Fe64 : (const void*)F->Fe32;
-      a.So = dbl ? (const void*)F->Fo64 : (const void*)F->Fo32;
+      if (fold == 3) a.So = dbl ? (const void*)F->Fr64 : (const void*)F->Fr32;
+      else a.So = dbl ? (const void*)F->Fo64 : (const void*)F->Fo32;
     } else {
       a.Se = dbl ? (const void*)F->Be64 : (const void*)F->Be32;
       a.So = dbl ? (const void*)F->Bo64 : (const void*)F->Bo32;
     }
     // outputs of each half along the pass axis
-    const int64_t me = fold == 1 ? F->ne : F->hh + F->cc, mo = fold == 1 ? F->no : F->hh;
+    const int64_t me = fold != 2 ? F->ne : F->hh + F->cc, mo = fold != 2 ? F->no : F->hh;
     const int64_t tb = a.rows ? BN : BM;
     a.te = (me + tb - 1) / tb;
     const int64_t tsplit = a.te + (mo + tb - 1) / tb;
@@ -515,24 +623,40 @@ hipError_t launch_typed(const PassArgs& pa, hipStream_t st) {
   // real data that allow no 16-byte access at all: the element-wise instance
   constexpr int64_t VW = 16 / (int64_t)sizeof(TIn);
   const bool aligned = (((uintptr_t)pa.X) & 15) == 0;
-  const bool coal = !pa.cplx && (a.rows ? !(aligned && pa.n % VW == 0 && (fold != 2 || F->ne % VW == 0))
+  const bool coal = !pa.cplx && (a.rows ? !(aligned && pa.n % VW == 0 && (fold < 2 || F->ne % VW == 0))
                                         : !(aligned && pa.R % VW == 0));
   hipError_t e;
   if (coal) {
     if (fold == 1) e = launch_fold<TC, TIn, TOut, 1, true>(a, pa, st);
     else if (fold == 2) e = launch_fold<TC, TIn, TOut, 2, true>(a, pa, st);
+    else if (fold == 3) e = launch_fold<TC, TIn, TOut, 3, true>(a, pa, st);
     else e = launch_fold<TC, TIn, TOut, 0, true>(a, pa, st);
   } else {
     if (fold == 1) e = launch_fold<TC, TIn, TOut, 1, false>(a, pa, st);
     else if (fold == 2) e = launch_fold<TC, TIn, TOut, 2, false>(a, pa, st);
+    else if (fold == 3) e = launch_fold<TC, TIn, TOut, 3, false>(a, pa, st);
     else e = launch_fold<TC, TIn, TOut, 0, false>(a, pa, st);
   }
-  if (e != hipSuccess || fold != 2 || F->hh == 0) return e;
+  if (e != hipSuccess || fold != 2 || pa.deferred || F->hh == 0) return e;
   // butterfly of the backward pass, in place on its output (R: real values per (p, i))
   return launch_unfold<TOut>((TOut*)pa.Y, pa.P, pa.n, pa.R, F->hh, st);
 }
 
 }  // namespace
+
+hipError_t launch_butterfly(const ButterflyArgs& a, hipStream_t st) {
+  if (a.nax < 1 || a.nax > 4 || a.d < 1 || a.d > TS_MAX_D || (a.ncomp != 1 && a.ncomp != 2))
+    return hipErrorInvalidValue;
+  if (!a.X || !a.Y) return hipErrorInvalidValue;
+  for (int j = 0; j < a.nax; ++j) {
+    if (a.ax[j] < 0 || a.ax[j] >= a.d || a.hh[j] != a.n[a.ax[j]] / 2) return hipErrorInvalidValue;
+    for (int i = 0; i < j; ++i)
+      if (a.ax[i] == a.ax[j]) return hipErrorInvalidValue;
+  }
+  if (a.t == DT::F64) return launch_butterfly_t<double>(a, st);
+  if (a.t == DT::F32) return launch_butterfly_t<float>(a, st);
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_pass(const PassArgs& pa, hipStream_t st) {
   if (pa.prec == 0) {

@@ -38,6 +38,8 @@ AxisFactor::~AxisFactor() {
   hipFree(Fo32);
   hipFree(Be32);
   hipFree(Bo32);
+  hipFree(Fr64);
+  hipFree(Fr32);
   hipFree(Fe16);
   hipFree(Fo16);
   hipFree(Be16);
@@ -251,7 +253,7 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
   if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(F.Q64, F.QT16, F.ld, st);
   if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(F.QT64, F.Q16, F.ld, st);
   // half factors of a symmetric axis
-  std::vector<double> H[4];
+  std::vector<double> H[5];
   if (e == hipSuccess && fp.on) {
     F.fold = true;
     F.ne = fp.ne;
@@ -269,6 +271,7 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
     for (int64_t i = 0; i < fp.hh; ++i)
       for (int64_t j = 0; j < fp.no; ++j) {
         H[1][(size_t)(i * kp + j)] = Fwd[(size_t)(i * n + fp.ne + j)];  // Fo[i][j'']
+        H[4][(size_t)((fp.hh - 1 - i) * kp + j)] = H[1][(size_t)(i * kp + j)];  // Fr
         H[3][(size_t)(j * kp + i)] = Bwd[(size_t)((fp.ne + j) * n + i)];  // Bo[j''][i]
       }
     double** d64[4] = {&F.Fe64, &F.Fo64, &F.Be64, &F.Bo64};
@@ -283,6 +286,10 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
       if (e == hipSuccess) e = launch_cast_f64_to_f32(*d64[q], *d32[q], (int64_t)cnt, st);
       if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(*d64[q], *d16[q], kp, st);
     }
+    if (e == hipSuccess) e = hipMalloc(&F.Fr64, sizeof(double) * cnt);
+    if (e == hipSuccess) e = hipMalloc(&F.Fr32, sizeof(float) * cnt);
+    if (e == hipSuccess) e = hipMemcpyAsync(F.Fr64, H[4].data(), sizeof(double) * cnt, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_cast_f64_to_f32(F.Fr64, F.Fr32, (int64_t)cnt, st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (st) hipStreamDestroy(st);
@@ -588,6 +595,45 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   const int T = 2 * d;
   const void* src = ap.in;
   DT src_t = ap.tin;
+  // Several folded axes: fold the input along all of them in one sweep (into
+  // the output buffer, which the last pass overwrites), run the forward passes
+  // on folded data and the backward passes without their butterflies, then
+  // unfold the output in one sweep.  The butterflies act on one axis each and
+  // so commute with the passes over the other axes.
+  int fax[TS_MAX_D];
+  int nf = 0;
+  if (p->fold_enabled && ap.prec != TS_PREC_BF16 && ap.tin == ap.tout)
+    for (int k = 0; k < d; ++k)
+      if ((ap.sym ? p->ax_sym : p->ax)[k]->fold) fax[nf++] = k;
+  const bool deferred = nf >= 2;
+  auto butterfly = [&](const void* X, void* Y, DT t) -> int {
+    for (int j0 = 0; j0 < nf; j0 += 4) {
+      ButterflyArgs b;
+      b.X = j0 == 0 ? X : Y;
+      b.Y = Y;
+      b.t = t;
+      b.d = d;
+      b.ncomp = ncomp;
+      for (int k = 0; k < d; ++k) b.n[k] = p->n[k];
+      b.nax = std::min(4, nf - j0);
+      for (int j = 0; j < b.nax; ++j) {
+        b.ax[j] = fax[j0 + j];
+        b.hh[j] = p->n[b.ax[j]] / 2;
+      }
+      b.skip = ap.skip;
+      hipError_t e = launch_butterfly(b, st);
+      if (e != hipSuccess) {
+        set_error(std::string("butterfly launch failed: ") + hipGetErrorString(e));
+        return TS_ERR_DEVICE;
+      }
+    }
+    return TS_OK;
+  };
+  if (deferred) {
+    int rc = butterfly(ap.in, ap.out, ap.tin);
+    if (rc) return rc;
+    src = ap.out;
+  }
   for (int t = 1; t <= T; ++t) {
     const bool fwd = t <= d;
     const int k = fwd ? order[t - 1] : (t == d + 1 ? p->s : order[t - d - 2]);
@@ -611,6 +657,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     // BF16 passes are not MFMA-bound: folding saves them no time (the butterfly and
     // the mirror loads cost more than the halved MFMA work), so BF16 applies do not fold
     pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
+    pa.deferred = deferred && pa.fold;
     if (fwd && t == d) {
       pa.epi = ap.epi;
       pa.Lp = p->Lp;
@@ -628,7 +675,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     src = dst;
     src_t = dst_t;
   }
-  return TS_OK;
+  return deferred ? butterfly(ap.out, ap.out, ap.tout) : TS_OK;
 }
 
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
@@ -1003,6 +1050,11 @@ int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out
   if (prec != TS_PREC_FP64 && prec != TS_PREC_FP32 && prec != TS_PREC_BF16) { set_error("bad prec"); return TS_ERR_INVALID; }
   const bool f64 = dtype == TS_F64 || dtype == TS_C128;
   if (prec == TS_PREC_FP64 && !f64) { set_error("FP64 transforms need FP64 data"); return TS_ERR_INVALID; }
+  if (forward < 0 || forward > 3) { set_error("forward must be 0, 1, 2 or 3"); return TS_ERR_INVALID; }
+  if (forward >= 2 && prec == TS_PREC_BF16) {
+    set_error("BF16 passes have no folded-data form (modes 2 and 3)");
+    return TS_ERR_INVALID;
+  }
   const bool cplx = dtype == TS_C128 || dtype == TS_C64;
   PassArgs pa;
   pa.X = in;
@@ -1010,7 +1062,7 @@ int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out
   pa.tin = pa.tout = f64 ? DT::F64 : DT::F32;
   pa.prec = prec;
   pa.fac = plan->ax[axis].get();
-  pa.forward = forward != 0;
+  pa.forward = forward == 1 || forward == 2;
   pa.n = plan->n[axis];
   pa.P = 1;
   for (int m = 0; m < axis; ++m) pa.P *= plan->n[m];
@@ -1018,8 +1070,38 @@ int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out
   for (int m = axis + 1; m < plan->d; ++m) pa.R *= plan->n[m];
   pa.cplx = cplx;
   pa.fold = pa.fac->fold && plan->fold_enabled;
+  pa.deferred = pa.fold && forward >= 2;
   hipError_t e = launch_pass(pa, (hipStream_t)hip_stream);
   if (e != hipSuccess) { set_error(std::string("mode pass launch failed: ") + hipGetErrorString(e)); return TS_ERR_DEVICE; }
+  return TS_OK;
+}
+
+int ts_fold_butterfly(ts_plan* plan, int axes, const void* in, void* out, int dtype, void* hip_stream) {
+  if (!plan || !in || !out) { set_error("null argument"); return TS_ERR_INVALID; }
+  if (dtype != TS_F64 && dtype != TS_F32 && dtype != TS_C128 && dtype != TS_C64) { set_error("bad dtype"); return TS_ERR_INVALID; }
+  if (axes <= 0 || axes >= (1 << plan->d)) { set_error("axes must be a non-empty mask of the plan's axes"); return TS_ERR_INVALID; }
+  int ax[TS_MAX_D];
+  int na = 0;
+  for (int k = 0; k < plan->d; ++k)
+    if (axes & (1 << k)) ax[na++] = k;
+  const void* src = in;
+  for (int j0 = 0; j0 < na; j0 += 4) {
+    ButterflyArgs b;
+    b.X = src;
+    b.Y = out;
+    b.t = (dtype == TS_F64 || dtype == TS_C128) ? DT::F64 : DT::F32;
+    b.d = plan->d;
+    b.ncomp = (dtype == TS_C128 || dtype == TS_C64) ? 2 : 1;
+    for (int k = 0; k < plan->d; ++k) b.n[k] = plan->n[k];
+    b.nax = std::min(4, na - j0);
+    for (int j = 0; j < b.nax; ++j) {
+      b.ax[j] = ax[j0 + j];
+      b.hh[j] = plan->n[b.ax[j]] / 2;
+    }
+    hipError_t e = launch_butterfly(b, (hipStream_t)hip_stream);
+    if (e != hipSuccess) { set_error(std::string("butterfly launch failed: ") + hipGetErrorString(e)); return TS_ERR_DEVICE; }
+    src = out;
+  }
   return TS_OK;
 }
 

@@ -71,6 +71,10 @@ struct AxisFactor {
   int64_t ne = 0, no = 0, hh = 0, cc = 0, fkp = 0;
   double *Fe64 = nullptr, *Fo64 = nullptr, *Be64 = nullptr, *Bo64 = nullptr;
   float *Fe32 = nullptr, *Fo32 = nullptr, *Be32 = nullptr, *Bo32 = nullptr;
+  // Fr: Fo with its rows reversed (row r is physical i = h - 1 - r), for a
+  // forward pass on data folded beforehand, where d_i sits at row n - 1 - i
+  double* Fr64 = nullptr;
+  float* Fr32 = nullptr;
   // BF16, K-contiguous (transposed) copies of Fe, Fo, Be, Bo for the BF16 passes
   uint16_t *Fe16 = nullptr, *Fo16 = nullptr, *Be16 = nullptr, *Bo16 = nullptr;
   std::vector<double> lam_int_h;  // eigenvalues in the internal spectral order
@@ -107,11 +111,31 @@ struct PassArgs {
   const double2* es = nullptr;
   const int* skip = nullptr;   // if non-null and *skip != 0 the kernel returns
   bool fold = false;           // half-extent pass of a symmetric axis
+  // with fold: a forward pass reads data already folded along this axis
+  // (launch_butterfly), a backward pass leaves its butterfly to the caller
+  bool deferred = false;
   int64_t kband = 0;           // > 0: the factor is banded, |k - output| <= kband (FP64 passes)
 };
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);
 hipError_t launch_pass_bf16(const PassArgs& a, hipStream_t st);
+
+// Butterfly y_i, y_{n-1-i} = x_i + x_{n-1-i}, x_i - x_{n-1-i} (i < hh), in
+// place or not, along up to four axes of a [n_0]...[n_{d-1}][ncomp] array at once
+// (the axes' reflections commute, so their order does not matter).  The same
+// map folds the input of an apply and unfolds its output.
+struct ButterflyArgs {
+  const void* X = nullptr;      // input (may equal Y)
+  void* Y = nullptr;
+  DT t = DT::F64;
+  int d = 0, ncomp = 1;
+  int64_t n[TS_MAX_D] = {};
+  int nax = 0;                  // 1..4
+  int ax[4] = {};               // the axes, as indices into n
+  int64_t hh[4] = {};           // floor(n / 2) of each
+  const int* skip = nullptr;    // if non-null and *skip != 0 the kernel returns
+};
+hipError_t launch_butterfly(const ButterflyArgs& a, hipStream_t st);
 
 // Phase tables for the propagator: es[j] = e^{-i tau lam_s[j]},
 // Ep[p] = prod_{m<s} e^{-i tau lam_m[j_m(p)]}, Er[q] = prod_{m>s} (...).

@@ -125,3 +125,77 @@ def test_single_pass_bf16_fold(shape):
             announce("bf16 pass %s axis %d %s: fold %.2e plain %.2e"
                      % (shape, axis, "fwd" if fwd else "bwd", errs[0], errs[1]))
             assert max(errs) <= 1e-2
+
+
+def _butterfly_ref(x, axes):
+    """out_i = x_i + x_{n-1-i}, out_{n-1-i} = x_i - x_{n-1-i} (i < n // 2) per axis."""
+    y = x.copy()
+    for a in axes:
+        n, h = y.shape[a], y.shape[a] // 2
+        yf = np.flip(y, a)
+        idx = np.arange(n).reshape([-1 if k == a else 1 for k in range(y.ndim)])
+        y = np.where(idx < h, y + yf, np.where(idx >= n - h, yf - y, y))
+    return y
+
+
+@pytest.mark.parametrize("shape,mask", [((100, 99, 130), 7), ((70, 81), 2), ((12, 13, 10, 11, 9), 31),
+                                        ((33, 130, 80), 5), ((7, 64, 5, 3), 11)])
+def test_fold_butterfly(shape, mask):
+    """ts_fold_butterfly against the per-axis definition: out of place, in place,
+    complex and FP32 data, up to five axes (two sweeps)."""
+    plan = ts.ts_setup(shape, 6.0, [W.f_harmonic(n, 6.0) for n in shape], 1.0)
+    axes = [k for k in range(len(shape)) if mask >> k & 1]
+    x = W.rhs_normal(shape, 8)
+    ref = _butterfly_ref(x, axes)
+    assert rel(to_host(ts.ts_fold_butterfly(plan, mask, to_dev(x))), ref) <= 1e-15
+    xd = to_dev(x)
+    ts.ts_fold_butterfly(plan, mask, xd, xd)
+    assert rel(to_host(xd), ref) <= 1e-15
+    # twice: 2x per axis, except on the middle row of an odd extent (copied)
+    ts.ts_fold_butterfly(plan, mask, xd, xd)
+    scale = np.ones(shape)
+    for a in axes:
+        w = np.full(shape[a], 2.0)
+        if shape[a] % 2:
+            w[shape[a] // 2] = 1.0
+        scale = scale * w.reshape([-1 if k == a else 1 for k in range(len(shape))])
+    assert rel(to_host(xd), scale * x) <= 1e-15
+    psi = W.complex_normal(shape, 9)
+    refc = _butterfly_ref(psi, axes)
+    assert rel(to_host(ts.ts_fold_butterfly(plan, mask, to_dev(psi))), refc) <= 1e-15
+    got32 = to_host(ts.ts_fold_butterfly(plan, mask, to_dev(psi).to(torch.complex64)))
+    assert rel(got32.astype(np.complex128), refc) <= 1e-6
+    got32 = to_host(ts.ts_fold_butterfly(plan, mask, to_dev(x).float()))
+    assert rel(got32.astype(np.float64), ref) <= 1e-6
+    with pytest.raises(ts.TSError):
+        ts.ts_fold_butterfly(plan, 1 << len(shape), to_dev(x))
+    with pytest.raises(ts.TSError):
+        ts.ts_fold_butterfly(plan, 0, to_dev(x))
+
+
+@pytest.mark.parametrize("shape", [(100, 99, 130), (70, 81), (65, 64)])
+def test_single_pass_on_folded_data(shape):
+    """ts_mode_pass modes 2 and 3 (the passes inside an apply with several
+    folded axes): the forward pass on butterflied input equals the forward pass
+    on the input, and the backward pass without its butterfly, butterflied,
+    equals the backward pass; FP64, FP32 and complex data."""
+    plan, _, _ = make_pair(shape, 6.0, "cos", sigma=1.0)
+    mask = ts.ts_fold_axes(plan)
+    assert mask == sum(1 << k for k in range(len(shape)))
+    xr = to_dev(W.rhs_normal(shape, 4))
+    xc = to_dev(W.complex_normal(shape, 5))
+    cases = [(xr, "fp64", 1e-13), (xr.float(), "fp32", 2e-6), (xc, "fp64", 1e-13),
+             (xc.to(torch.complex64), "fp32", 2e-6)]
+    for axis in range(len(shape)):
+        for x, prec, tol in cases:
+            xf = ts.ts_fold_butterfly(plan, 1 << axis, x)
+            y1 = ts.ts_mode_pass(plan, axis, True, x, prec=prec)
+            y2 = ts.ts_mode_pass(plan, axis, True, xf, prec=prec, folded=True)
+            z0 = ts.ts_mode_pass(plan, axis, False, y1, prec=prec)
+            z3 = ts.ts_fold_butterfly(plan, 1 << axis, ts.ts_mode_pass(plan, axis, False, y1, prec=prec, folded=True))
+            e_f, e_b = rel(to_host(y2), to_host(y1)), rel(to_host(z3), to_host(z0))
+            announce("folded-data passes %s axis %d %s %s: forward %.2e backward %.2e"
+                     % (shape, axis, x.dtype, prec, e_f, e_b))
+            assert e_f <= tol and e_b <= tol
+    with pytest.raises(ts.TSError):
+        ts.ts_mode_pass(plan, 0, True, xr.float(), prec="bf16", folded=True)
