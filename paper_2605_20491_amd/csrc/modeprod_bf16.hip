@@ -67,6 +67,21 @@ __device__ __forceinline__ void load_vec8(const uint16_t* src, uint16_t* dst) {
   }
 }
 
+// One 16-byte chunk (16 / sizeof(T) consecutive elements; the caller guarantees alignment).
+__device__ __forceinline__ void load_vec16(const double* src, double* dst) {
+  const double2 v = *(const double2*)src;
+  dst[0] = v.x;
+  dst[1] = v.y;
+}
+__device__ __forceinline__ void load_vec16(const float* src, float* dst) {
+  const float4 v = *(const float4*)src;
+  dst[0] = v.x;
+  dst[1] = v.y;
+  dst[2] = v.z;
+  dst[3] = v.w;
+}
+__device__ __forceinline__ void load_vec16(const uint16_t* src, uint16_t* dst) { load_vec8(src, dst); }
+
 template <typename TIn> __device__ __forceinline__ TIn fold_add(TIn x, TIn y, bool sub) {
   return sub ? x - y : x + y;
 }
@@ -192,6 +207,24 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
           }
         }
       }
+    } else if (!CPLX && FOLD != 1) {
+      // data rows in 16-byte chunks: consecutive lanes take consecutive chunks of
+      // one row (BK / VW lanes per row), so every load instruction is coalesced
+      constexpr int VW = 16 / (int)sizeof(TIn), TPR = BK / VW, RPS = NT / TPR, NS = BM / RPS;
+      const int c = t % TPR, rg = t / TPR;
+      const int64_t kk = k0 + VW * c;
+      const bool vec = base_aligned && (a.n % VW) == 0 && (koff % VW) == 0 && kk + VW <= K;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int64_t m = m0 + RPS * s + rg;
+        const TIn* src = X + m * a.n + koff + kk;
+        if (m < a.M && vec) {
+          load_vec16(src, &rdat[VW * s]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < VW; ++e) rdat[VW * s + e] = (m < a.M && kk + e < K) ? src[e] : (TIn)0;
+        }
+      }
     } else if (!CPLX) {
       const int row = t >> 1, half = t & 1;
       const int64_t m = m0 + row;
@@ -298,6 +331,20 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
         uint32_t hi = (uint32_t)to_bf16(rdat[2 * 8 + c]) | ((uint32_t)to_bf16(rdat[3 * 8 + c]) << 16);
         const int row = 8 * oc + c;
         *(uint2*)&Bs[buf][row][swz8(row, kq >> 1) + 4 * (kq & 1)] = make_uint2(lo, hi);
+      }
+    } else if (!CPLX && FOLD != 1) {
+      constexpr int VW = 16 / (int)sizeof(TIn), TPR = BK / VW, RPS = NT / TPR, NS = BM / RPS;
+      const int c = t % TPR, rg = t / TPR;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        uint16_t* dst = &As[buf][RPS * s + rg][VW * c];
+        uint32_t w[VW / 2];
+#pragma unroll
+        for (int e = 0; e < VW / 2; ++e)
+          w[e] = (uint32_t)to_bf16(rdat[VW * s + 2 * e]) | ((uint32_t)to_bf16(rdat[VW * s + 2 * e + 1]) << 16);
+        if constexpr (VW == 2) *(uint32_t*)dst = w[0];
+        else if constexpr (VW == 4) *(uint2*)dst = make_uint2(w[0], w[1]);
+        else *(uint4*)dst = make_uint4(w[0], w[1], w[2], w[3]);
       }
     } else if (!CPLX) {
       const int row = t >> 1, half = t & 1;
