@@ -617,6 +617,105 @@ __global__ __launch_bounds__(256) void k_butterfly(const T* X, T* Y, ButterflyAr
   }
 }
 
+// The same on 2-element units, moved with one 8- or 16-byte access each:
+// complex data (a unit is one element, both components), or real data whose
+// fastest axis is folded with n % 4 == 0 (SWAP: a unit is the pair i, i+1 of
+// the lower half, its mirror the pair n-2-i, n-1-i, so the fastest-axis
+// butterfly pairs a.x with b.y and a.y with b.x).
+template <typename T, int NAX, bool SWAP>
+__global__ __launch_bounds__(256) void k_butterfly_v2(const T* X, T* Y, ButterflyArgs a, int64_t total) {
+  using V = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+  if (a.skip && *a.skip) return;
+  constexpr int NV = 1 << NAX;
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int64_t rest = e, off = 0, stride = 2;  // offsets in elements of T
+    int64_t delta[NAX];
+    bool act[NAX];
+    int jl = -1;  // the fastest axis's slot (SWAP)
+#pragma unroll
+    for (int j = 0; j < NAX; ++j) {
+      delta[j] = 0;
+      act[j] = false;
+    }
+    for (int k = a.d - 1; k >= 0; --k) {
+      int jf = -1;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (a.ax[j] == k) jf = j;
+      if (SWAP && k == a.d - 1) {
+        const int64_t ext = a.hh[jf] / 2;  // pairs of the lower half
+        const int64_t q = rest / ext;
+        const int64_t i = rest - q * ext;
+        rest = q;
+        off = 2 * i;
+        jl = jf;
+#pragma unroll
+        for (int j = 0; j < NAX; ++j)
+          if (j == jf) {
+            act[j] = true;
+            delta[j] = a.n[k] - 2 - 4 * i;
+          }
+        stride = a.n[k];
+        continue;
+      }
+      const int64_t ext = jf >= 0 ? a.n[k] - a.hh[jf] : a.n[k];
+      const int64_t q = rest / ext;
+      const int64_t i = rest - q * ext;
+      rest = q;
+      off += i * stride;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (j == jf && i < a.hh[j]) {
+          act[j] = true;
+          delta[j] = (a.n[k] - 1 - 2 * i) * stride;
+        }
+      stride *= a.n[k];
+    }
+    V v[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      v[m] = ok ? *(const V*)(X + o) : V{};
+    }
+#pragma unroll
+    for (int j = 0; j < NAX; ++j) {
+      if (!act[j]) continue;
+      const bool sw = SWAP && j == jl;
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (!(m & (1 << j))) {
+          const V x0 = v[m], x1 = v[m | (1 << j)];
+          if (sw) {
+            v[m] = V{x0.x + x1.y, x0.y + x1.x};
+            v[m | (1 << j)] = V{x0.y - x1.x, x0.x - x1.y};
+          } else {
+            v[m] = V{x0.x + x1.x, x0.y + x1.y};
+            v[m | (1 << j)] = V{x0.x - x1.x, x0.y - x1.y};
+          }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      if (ok) *(V*)(Y + o) = v[m];
+    }
+  }
+}
+
 template <typename T>
 hipError_t launch_butterfly_t(const ButterflyArgs& a, hipStream_t st) {
   int64_t total = a.ncomp;
@@ -627,9 +726,35 @@ hipError_t launch_butterfly_t(const ButterflyArgs& a, hipStream_t st) {
     total *= ext;
   }
   if (total <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
   const T* X = (const T*)a.X;
   T* Y = (T*)a.Y;
+  // 2-element units: complex data, or a folded fastest axis with n % 4 == 0
+  const uintptr_t al = 2 * sizeof(T) - 1;
+  const bool aligned = ((((uintptr_t)X) | ((uintptr_t)Y)) & al) == 0;
+  int jlast = -1;
+  for (int j = 0; j < a.nax; ++j)
+    if (a.ax[j] == a.d - 1) jlast = j;
+  const bool cplx_units = aligned && a.ncomp == 2;
+  const bool pair_units = aligned && a.ncomp == 1 && jlast >= 0 && a.n[a.d - 1] % 4 == 0;
+  if (cplx_units || pair_units) {
+    const int64_t units = total / 2;  // pair_units: the fastest axis holds n / 2 representatives, i.e. n / 4 pairs
+    const unsigned blocks = (unsigned)std::min<int64_t>((units + 255) / 256, 1 << 20);
+#define TS_BFLY_V2(N)                                                                                  \
+  if (pair_units)                                                                                      \
+    hipLaunchKernelGGL((k_butterfly_v2<T, N, true>), dim3(blocks), dim3(256), 0, st, X, Y, a, units); \
+  else                                                                                                 \
+    hipLaunchKernelGGL((k_butterfly_v2<T, N, false>), dim3(blocks), dim3(256), 0, st, X, Y, a, units);
+    switch (a.nax) {
+      case 1: TS_BFLY_V2(1) break;
+      case 2: TS_BFLY_V2(2) break;
+      case 3: TS_BFLY_V2(3) break;
+      case 4: TS_BFLY_V2(4) break;
+      default: return hipErrorInvalidValue;
+    }
+#undef TS_BFLY_V2
+    return hipGetLastError();
+  }
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
   switch (a.nax) {
     case 1: hipLaunchKernelGGL((k_butterfly<T, 1>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
     case 2: hipLaunchKernelGGL((k_butterfly<T, 2>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;

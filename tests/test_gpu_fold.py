@@ -139,10 +139,13 @@ def _butterfly_ref(x, axes):
 
 
 @pytest.mark.parametrize("shape,mask", [((100, 99, 130), 7), ((70, 81), 2), ((12, 13, 10, 11, 9), 31),
-                                        ((33, 130, 80), 5), ((7, 64, 5, 3), 11)])
+                                        ((33, 130, 80), 5), ((7, 64, 5, 3), 11), ((64, 66, 100), 7),
+                                        ((20, 12), 2), ((9, 7, 5, 3, 8), 31), ((50, 1000), 3)])
 def test_fold_butterfly(shape, mask):
     """ts_fold_butterfly against the per-axis definition: out of place, in place,
-    complex and FP32 data, up to five axes (two sweeps)."""
+    complex and FP32 data, up to five axes (two sweeps); real data whose
+    fastest axis folds with n % 4 == 0 move in pairs (the mirror pair swapped),
+    complex data one element per access."""
     plan = ts.ts_setup(shape, 6.0, [W.f_harmonic(n, 6.0) for n in shape], 1.0)
     axes = [k for k in range(len(shape)) if mask >> k & 1]
     x = W.rhs_normal(shape, 8)
