@@ -634,6 +634,21 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     if (rc) return rc;
     src = ap.out;
   }
+  // BF16 transforms of FP64 data: round the input to BF16 in one streaming
+  // sweep (into the output buffer, which the last pass overwrites), so that
+  // the first pass reads 2 instead of 8 bytes per value (the pass kernels
+  // would round the same value through FP32; this rounds once)
+  const int64_t Ntot = p->N * ncomp;
+  if (ap.prec == TS_PREC_BF16 && ap.tin == DT::F64 && ap.in != ap.out && Ntot % 4 == 0 &&
+      ((((uintptr_t)ap.in) & 15) == 0) && ((((uintptr_t)ap.out) & 7) == 0)) {
+    hipError_t e = launch_data_to_bf16((const double*)ap.in, (uint16_t*)ap.out, Ntot, ap.skip, st);
+    if (e != hipSuccess) {
+      set_error(std::string("BF16 rounding launch failed: ") + hipGetErrorString(e));
+      return TS_ERR_DEVICE;
+    }
+    src = ap.out;
+    src_t = DT::BF16;
+  }
   for (int t = 1; t <= T; ++t) {
     const bool fwd = t <= d;
     const int k = fwd ? order[t - 1] : (t == d + 1 ? p->s : order[t - d - 2]);
