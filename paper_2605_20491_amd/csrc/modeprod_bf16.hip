@@ -406,6 +406,63 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
   }
 
   TOut* Y = (TOut*)a.Y;
+  if constexpr (EPI != 0 && !ROWS) {
+    // Scaling pass: the table entries of this thread's rows and columns are read
+    // once (the stores below may alias the tables as far as the compiler can
+    // tell); same arithmetic and order as store_cols.
+    double tr[4];
+    double2 er[4], ep = make_double2(0.0, 0.0);
+    if (EPI == (int)Epi::Exp) ep = a.Ep[p];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = n0 + wn * 64 + j * 16 + lr;
+      const bool ok = col < a.R;
+      if (EPI == (int)Epi::Inv) tr[j] = ok ? a.Lr[CPLX ? (col >> 1) : col] : 0.0;
+      else er[j] = ok ? a.Er[col >> 1] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int64_t dm[4];
+      double tm[4];
+      double2 fm[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 64 + i * 16 + out_row<float>(lane, r);
+        int64_t dst = m;
+        bool ok = m < a.n;
+        if (FOLD) {
+          const int64_t cnt = FOLD == 1 ? (odd ? a.no : a.ne) : (odd ? a.hh : a.hh + a.cc);
+          ok = m < cnt;
+          dst = FOLD == 1 ? (odd ? a.ne + m : m) : (odd ? a.n - 1 - m : m);
+        }
+        dm[r] = ok ? dst : -1;
+        if (EPI == (int)Epi::Inv) {
+          tm[r] = ok ? a.lam[dst] + a.Lp[p] : 0.0;
+        } else {
+          const double2 f1 = ok ? a.es[dst] : make_double2(0.0, 0.0);
+          fm[r] = make_double2(f1.x * ep.x - f1.y * ep.y, f1.x * ep.y + f1.y * ep.x);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t col = n0 + wn * 64 + j * 16 + lr;
+          double v = (double)acc[i][j][r];
+          double partner = 0.0;
+          if (EPI == (int)Epi::Exp) partner = __shfl_xor(v, 1);
+          if (dm[r] < 0 || col >= a.R) continue;
+          if (EPI == (int)Epi::Inv) {
+            v = v / (tm[r] + tr[j] + a.shift);
+          } else {
+            const double gr = fm[r].x * er[j].x - fm[r].y * er[j].y, gi = fm[r].x * er[j].y + fm[r].y * er[j].x;
+            v = (col & 1) ? (gi * partner + gr * v) : (gr * v - gi * partner);
+          }
+          Y[(p * a.n + dm[r]) * a.R + col] = cvt_out<TOut>(v);
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
