@@ -12,6 +12,7 @@
 // converted to BF16 on the way into LDS (FP64 -> FP32 -> BF16, each round to
 // nearest even); the column operand is transposed there.
 #include <algorithm>
+#include <type_traits>
 
 #include "modeprod_common.h"
 #include "ts_internal.h"
@@ -406,6 +407,63 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
   }
 
   TOut* Y = (TOut*)a.Y;
+  // BF16 output of a plain (or scaling, real) pass with rows of a multiple of 8
+  // outputs: the tile is staged in LDS as BF16 and written back with one 16-byte
+  // store per 8 consecutive outputs (the MFMA layout alone gives 2-byte stores,
+  // 16 per row segment; for other row lengths the direct stores are faster)
+  constexpr bool kStage = !CPLX && FOLD == 0 && EPI != (int)Epi::Exp && std::is_same<TOut, uint16_t>::value;
+  if (kStage && ((((uintptr_t)a.Y) & 15) == 0) && ((ROWS ? a.n : a.R) % 8) == 0) {
+    constexpr int LT = BN + 8;  // staged row length (elements): 272 B, 16-byte aligned rows
+    static_assert(BM * LT <= 2 * BM * LDK, "staged tile must fit in the A buffers");
+    uint16_t* Ts = &As[0][0][0];
+    double tr[4] = {0.0, 0.0, 0.0, 0.0};
+    if (EPI == (int)Epi::Inv) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = n0 + wn * 64 + j * 16 + lr;
+        tr[j] = col < a.R ? a.Lr[col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double tm[4] = {0.0, 0.0, 0.0, 0.0};
+      if (EPI == (int)Epi::Inv) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + wm * 64 + i * 16 + out_row<float>(lane, r);
+          tm[r] = m < a.n ? a.lam[m] + a.Lp[p] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = wm * 64 + i * 16 + out_row<float>(lane, r), cl = wn * 64 + j * 16 + lr;
+          double v = (double)acc[i][j][r];
+          // (entries outside the grid are staged but never written back)
+          if (EPI == (int)Epi::Inv) v = v / (tm[r] + tr[j] + a.shift);
+          Ts[ml * LT + cl] = cvt_out<uint16_t>(v);
+        }
+    }
+    __syncthreads();
+    const int64_t rowlen = ROWS ? a.n : a.R;
+#pragma unroll
+    for (int q = 0; q < (BM * BN / 8) / NT; ++q) {
+      const int idx = q * NT + t, lrow = idx >> 4, ch = idx & 15;
+      const int64_t mg = m0 + lrow, cg = n0 + 8 * ch;
+      if (ROWS ? mg >= a.M : mg >= a.n) continue;
+      const int64_t base = ROWS ? mg * a.n : (p * a.n + mg) * a.R;
+      const uint16_t* src = &Ts[lrow * LT + 8 * ch];
+      if (cg + 8 <= rowlen) {
+        *(uint4*)(Y + base + cg) = *(const uint4*)src;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (cg + e < rowlen) Y[base + cg + e] = src[e];
+      }
+    }
+    return;
+  }
   if constexpr (EPI != 0 && !ROWS) {
     // Scaling pass: the table entries of this thread's rows and columns are read
     // once (the stores below may alias the tables as far as the compiler can
