@@ -15,7 +15,7 @@ namespace ts {
 namespace {
 
 constexpr int kMarch = 32;       // stencil: points per thread along axis 0
-constexpr int kGroup = 4;        // stencil: points whose loads are issued together
+constexpr int kGroup = 8;        // stencil: points whose loads are issued together
 
 // Stencil: each thread owns one index r of the faster axes (1..d-1) and a run
 // of kMarch consecutive points along axis 0, keeping the axis-0 neighbours in
