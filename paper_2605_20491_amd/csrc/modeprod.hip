@@ -920,14 +920,16 @@ __global__ void k_cast_bf16(const double* x, uint16_t* y, int64_t n) {
     y[i] = f64_to_bf16_rne(x[i]);
 }
 
-// The same over a data array, four elements per thread (x 16-byte, y 8-byte
-// aligned, n % 4 == 0), stopping at once when *skip is set.
+// A data array to BF16 for the BF16 passes, four elements per thread (x
+// 16-byte, y 8-byte aligned, n % 4 == 0), stopping at once when *skip is set.
+// Rounded as the pass kernels round FP64 data they load (FP64 -> FP32 -> BF16,
+// each to nearest even), so an apply gives the same result either way.
 __global__ __launch_bounds__(256) void k_cast_bf16_x4(const double2* x, uint2* y, int64_t n4, const int* skip) {
   if (skip && *skip) return;
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) {
     const double2 a = x[2 * i], b = x[2 * i + 1];
-    y[i] = make_uint2((uint32_t)f64_to_bf16_rne(a.x) | ((uint32_t)f64_to_bf16_rne(a.y) << 16),
-                      (uint32_t)f64_to_bf16_rne(b.x) | ((uint32_t)f64_to_bf16_rne(b.y) << 16));
+    y[i] = make_uint2((uint32_t)cvt_out<uint16_t>(a.x) | ((uint32_t)cvt_out<uint16_t>(a.y) << 16),
+                      (uint32_t)cvt_out<uint16_t>(b.x) | ((uint32_t)cvt_out<uint16_t>(b.y) << 16));
   }
 }
 

@@ -636,8 +636,8 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   }
   // BF16 transforms of FP64 data: round the input to BF16 in one streaming
   // sweep (into the output buffer, which the last pass overwrites), so that
-  // the first pass reads 2 instead of 8 bytes per value (the pass kernels
-  // would round the same value through FP32; this rounds once)
+  // the first pass reads 2 instead of 8 bytes per value (rounded as the pass
+  // kernels would round it while loading)
   const int64_t Ntot = p->N * ncomp;
   if (ap.prec == TS_PREC_BF16 && ap.tin == DT::F64 && ap.in != ap.out && Ntot % 4 == 0 &&
       ((((uintptr_t)ap.in) & 15) == 0) && ((((uintptr_t)ap.out) & 7) == 0)) {
