@@ -117,8 +117,18 @@ def pcg_section(ts, W, torch, dev, n, precs):
             _, it, rr, _ = ts.ts_pcg_solve(plan, V2, f, u, rtol=1e-10, precond=prec)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
-            out[prec] = {"solve_ms": ms, "iters": it, "relres": rr}
-            log("pcg n=%d %s: %.1f ms, %d iters, relres %.2e" % (n, prec, ms, it, rr))
+            N = n ** 3
+            # per-iteration roofline: one preconditioner apply (4 N sum n_k flops at the MFMA peak of its
+            # precision, or its 16 B/point of FP64 in/out at the HBM peak) plus the FP64 vector work of
+            # one PCG iteration (operator 24 B/point, x and r updates 48, <z,r> 16, p update 24)
+            t_pre = max(12.0 * N * n / (PEAK[prec] * 1e12), 16.0 * N / (HBM_PEAK * 1e9))
+            t_vec = 112.0 * N / (HBM_PEAK * 1e9)
+            t_iter = ms / max(it, 1)
+            out[prec] = {"solve_ms": ms, "iters": it, "relres": rr, "ms_per_iter": t_iter,
+                         "roofline_ms_per_iter": (t_pre + t_vec) * 1e3,
+                         "roofline_frac_per_iter": (t_pre + t_vec) * 1e3 / t_iter}
+            log("pcg n=%d %s: %.1f ms, %d iters, relres %.2e, %.2f ms/iter = %.0f%% of its roofline"
+                % (n, prec, ms, it, rr, t_iter, 100 * out[prec]["roofline_frac_per_iter"]))
         except ts.TSError as e:
             out[prec] = "unavailable: %s" % e.status
     if isinstance(out.get("fp64"), dict):
@@ -147,8 +157,16 @@ def invit_section(ts, W, torch, dev, n, precs, steps=20):
             _, lam, its = ts.ts_inverse_iteration(plan, V2, shift, u, steps=steps, pcg_rtol=1e-10, precond=prec)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
-            out[prec] = {"ms": ms, "lambda": float(lam[-1]), "pcg_iters_total": int(sum(its))}
-            log("inverse iteration n=%d %s: %.1f ms, lambda %.10f, %d PCG iters" % (n, prec, ms, lam[-1], sum(its)))
+            # eigen-residual ||H u - lambda u|| / |lambda| of the final unit vector (H = H1 + V2)
+            r = ts.ts_operator_apply(plan, V2, 0.0, u)
+            r.sub_(u, alpha=float(lam[-1]))
+            eres = float(torch.linalg.vector_norm(r)) / abs(float(lam[-1])) / float(torch.linalg.vector_norm(u))
+            del r
+            out[prec] = {"ms": ms, "lambda": float(lam[-1]), "lambda_history": [float(x) for x in lam],
+                         "pcg_iters": [int(x) for x in its], "pcg_iters_total": int(sum(its)),
+                         "eigen_residual": eres}
+            log("inverse iteration n=%d %s: %.1f ms, lambda %.10f, %d PCG iters, eigen-residual %.2e"
+                % (n, prec, ms, lam[-1], sum(its), eres))
         except ts.TSError as e:
             out[prec] = "unavailable: %s" % e.status
     return out
@@ -180,7 +198,7 @@ def split_section(ts, W, torch, dev, d, n, steps=100, dt=1e-3):
     w = ts.ts_eigvals(plan, 0)
     terms = W.superposition_terms([Q] * d, [w] * d, 4, seed=4)
     out = {"d": d, "n": n, "dofs": N, "steps": steps, "dt": dt}
-    for dtype, prec in ((torch.complex64, "fp32"), (torch.complex128, "fp64")):
+    for dtype, prec in ((torch.complex64, "fp32"), (torch.complex64, "fp64"), (torch.complex128, "fp64")):
         V2 = pairwise_on_device(W, torch, dev, shape, L, torch.float32 if dtype == torch.complex64 else torch.float64)
         psi0 = torch.zeros(shape, dtype=dtype, device=dev)
         for cm, idx in terms:
@@ -202,10 +220,19 @@ def split_section(ts, W, torch, dev, d, n, steps=100, dt=1e-3):
             ms = e0.elapsed_time(e1)
             n_apply = steps + 1 if scheme == "strang_bab" else 3 * steps + 1
             drift = abs(float(torch.linalg.vector_norm(psi)) / float(torch.linalg.vector_norm(psi0)) - 1.0)
-            key = "%s_%s" % (scheme, "c64" if dtype == torch.complex64 else "c128")
+            key = "%s_%s" % (scheme, "c128" if dtype == torch.complex128 else
+                             ("c64" if prec == "fp32" else "c64_fp64_transforms"))
+            sz = 8 if dtype == torch.complex64 else 16
+            # algorithmic bytes of one propagation: read and write the state once (2 N s); flops 8 N sum n_k
+            gbs = 2.0 * N * sz / (ms / n_apply * 1e-3) / 1e9
+            tfl = 8.0 * N * n * d / (ms / n_apply * 1e-3) / 1e12
             out[key] = {"ms_per_step": ms / steps, "ms_per_apply": ms / n_apply, "norm_drift": drift,
-                        "dof_s_per_apply": N / (ms / n_apply * 1e-3)}
-            log("split %dD n=%d %s: %.2f ms/step, drift %.1e" % (d, n, key, ms / steps, drift))
+                        "dof_s_per_apply": N / (ms / n_apply * 1e-3), "alg_gb_s": gbs, "alg_tflops": tfl,
+                        "roofline_ms_per_apply": max(8.0 * N * n * d / (PEAK[prec] * 1e12),
+                                                     2.0 * N * sz / (HBM_PEAK * 1e9)) * 1e3}
+            out[key]["roofline_frac"] = out[key]["roofline_ms_per_apply"] / (ms / n_apply)
+            log("split %dD n=%d %s: %.2f ms/step, %.2f ms/apply (%.0f%% of roofline), drift %.1e"
+                % (d, n, key, ms / steps, ms / n_apply, 100 * out[key]["roofline_frac"], drift))
         del V2, psi0, psi
         torch.cuda.empty_cache()
     return out
@@ -525,49 +552,59 @@ def multilevel_section(ts, W, torch, dev, k=20, cells=(5, 10, 25)):
     return out
 
 
-SERVE_SHAPES = [(2048, 2048), (128, 128, 128), (256, 256, 256), (512, 512, 512), (64,) * 4, (16,) * 6]
-SERVE_KINDS = ["inverse_fp64", "inverse_mixed", "exp_c64"]
-
-
-def serve_stream(seed, count, rate):
-    """Seeded Poisson arrivals; each request draws a shape, a kind, V2 present with
-    probability 1/2 and tau ~ U[1e-3, 1e-1]."""
-    import numpy as np
-    rng = np.random.default_rng(seed)
-    t = 0.0
-    reqs = []
-    for i in range(count):
-        t += rng.exponential(1.0 / rate)
-        reqs.append({"t": t, "shape": SERVE_SHAPES[rng.integers(len(SERVE_SHAPES))],
-                     "kind": SERVE_KINDS[rng.integers(len(SERVE_KINDS))], "v2": bool(rng.integers(2)),
-                     "tau": float(rng.uniform(1e-3, 1e-1))})
-    return reqs
-
-
 def serve_run(ts, W, torch, dev, reqs, mode, inputs):
     """Replay the stream against a server.  mode: 'batch' (4 streams, no cap),
-    'fp64' (same, every request in plain FP64), 'fifo' (1 stream, 1 request)."""
+    'fp64' (same, every request in plain FP64), 'fifo' (1 stream, 1 request),
+    'saturate' (as batch, every request submitted at once: saturation throughput).
+    Output tensors come from per-class pools of at most ~16 GB each (a request
+    whose pool is empty is submitted once a buffer returns; its latency still
+    counts from its arrival)."""
     import numpy as np
     n_streams, max_active = (1, 1) if mode == "fifo" else (4, 0)
     srv = ts.Server(64 << 30, n_streams, max_active)
     L = 8.0
+    pools, made = {}, {}
 
-    def submit(r, tag):
+    def request_args(r):
         shape = r["shape"]
-        f = inputs["f"][shape]
         V2 = inputs["v2"][shape] if r["v2"] else None
         if r["kind"].startswith("inverse"):
-            x = inputs["rhs"][shape]
             prec = "fp64" if (mode == "fp64" or r["kind"] == "inverse_fp64") else "bf16"
-            out = torch.empty_like(x)
-            return srv.submit(ts.TS_REQ_INVERSE, shape, L, f, inputs["sigma"][shape], x, out, prec=prec, V2=V2,
-                              rtol=1e-10, maxit=500 if V2 is not None else 60, tag=tag)
+            return ts.TS_REQ_INVERSE, inputs["rhs"][shape], prec, V2, inputs["sigma"][shape]
         c128 = mode == "fp64"
         x = inputs["psi128" if c128 else "psi64"][shape]
         V2 = None if V2 is None else (V2 if c128 else inputs["v2f"][shape])
-        out = torch.empty_like(x)
-        return srv.submit(ts.TS_REQ_EXP, shape, L, f, 1.0, x, out, prec="fp64" if c128 else "fp32", V2=V2,
-                          tau=r["tau"], dt=1e-2, tag=tag)
+        return ts.TS_REQ_EXP, x, "fp64" if c128 else "fp32", V2, 1.0
+
+    def take_out(x):
+        key = (tuple(x.shape), x.dtype)
+        lst = pools.setdefault(key, [])
+        if lst:
+            return lst.pop()
+        cap = max(2, min(256, int(16e9 // (x.numel() * x.element_size()))))
+        if made.get(key, 0) < cap:
+            made[key] = made.get(key, 0) + 1
+            return torch.empty_like(x)
+        return None
+
+    def submit(r, tag):
+        kind, x, prec, V2, sigma = request_args(r)
+        out = take_out(x)
+        if out is None:
+            return None, None
+        try:
+            if kind == ts.TS_REQ_INVERSE:
+                t = srv.submit(kind, r["shape"], L, inputs["f"][r["shape"]], sigma, x, out, prec=prec, V2=V2,
+                               rtol=1e-10, maxit=500 if V2 is not None else 60, tag=tag)
+            else:
+                t = srv.submit(kind, r["shape"], L, inputs["f"][r["shape"]], sigma, x, out, prec=prec, V2=V2,
+                               tau=r["tau"], dt=1e-2, tag=tag)
+        except ts.TSError as e:
+            pools[(tuple(out.shape), out.dtype)].append(out)
+            if e.code != ts.TS_ERR_BUSY:   # plan reserve held by running requests: retry later
+                raise
+            return None, None
+        return t, out
 
     # warm the plan cache and the kernels with one request per (shape, kind, V2)
     seen = set()
@@ -575,30 +612,53 @@ def serve_run(ts, W, torch, dev, reqs, mode, inputs):
         k = (r["shape"], r["kind"], r["v2"])
         if k not in seen:
             seen.add(k)
-            submit(r, 0)
-    srv.drain()
+            t, out = submit(r, 0)
+            srv.drain()
+            pools[(tuple(out.shape), out.dtype)].append(out)
     torch.cuda.synchronize()
     t0 = srv.clock()
     tickets = {}
-    pending = list(enumerate(reqs))
+    waiting = []                      # arrived, not yet submitted (no free output buffer)
+    upcoming = list(enumerate(reqs))
     results = {}
-    while pending or tickets:
+    while upcoming or waiting or tickets:
         now = srv.clock() - t0
-        while pending and pending[0][1]["t"] <= now:
-            i, r = pending.pop(0)
-            tickets[i] = submit(r, i)
+        while upcoming and (mode == "saturate" or upcoming[0][1]["t"] <= now):
+            waiting.append(upcoming.pop(0))
+        still = []
+        for i, r in waiting:
+            t, out = submit(r, i)
+            if t is None:
+                still.append((i, r))
+            else:
+                tickets[i] = (t, out)
+        waiting = still
         for i in list(tickets):
-            res = srv.poll(tickets[i])
+            t, out = tickets[i]
+            res = srv.poll(t)
             if res is not None:
                 results[i] = (res, t0 + reqs[i]["t"])
+                pools[(tuple(out.shape), out.dtype)].append(out)
                 del tickets[i]
         time.sleep(0.0005)
+    if mode == "saturate":
+        results = {i: (res, t0) for i, (res, _) in results.items()}
     makespan = max(res.t_done for res, _ in results.values()) - t0
     lat = np.array([res.t_done - arr for res, arr in results.values()])
     ok = sum(1 for res, _ in results.values() if res.status == 0)
     dofs = sum(int(np.prod(r["shape"])) for r in reqs)
     srv.close()
-    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+    del pools
+    torch.cuda.empty_cache()
+    by = {}
+    for i, (res, arr) in results.items():
+        key = "%dD_n%d_%s%s" % (len(reqs[i]["shape"]), reqs[i]["shape"][0], reqs[i]["kind"],
+                                 "_v2" if reqs[i]["v2"] else "")
+        by.setdefault(key, []).append(res.t_done - arr)
+    by = {k: {"count": len(v), "p50_ms": float(np.percentile(v, 50) * 1e3), "p99_ms": float(np.percentile(v, 99) * 1e3)}
+          for k, v in sorted(by.items())}
+    return {"by_class": by,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "makespan_s": makespan, "dof_s": dofs / makespan, "ok": ok, "requests": len(reqs)}
 
 
@@ -607,11 +667,11 @@ def serve_section(ts, W, torch, dev, count, rate=200.0):
     x {inverse FP64, inverse mixed (BF16 + refinement / BF16-preconditioned PCG),
     exp complex64 tau ~ U[1e-3, 1e-1]}, V2 zero or 8 seeded bumps."""
     L = 8.0
-    reqs = serve_stream(5, count, rate)
+    reqs = W.serve_stream(5, count, rate)
     inputs = {"f": {}, "v2": {}, "v2f": {}, "rhs": {}, "psi64": {}, "psi128": {}, "sigma": {}}
     gen = torch.Generator(device=dev)
     gen.manual_seed(5)
-    for shape in SERVE_SHAPES:
+    for shape in W.SERVE_SHAPES:
         inputs["f"][shape] = [W.f_harmonic(n, L) for n in shape]
         V2 = bumps_on_device(W, torch, dev, shape, L, 8, 5)
         inputs["v2"][shape] = V2
@@ -626,8 +686,8 @@ def serve_section(ts, W, torch, dev, count, rate=200.0):
         # sigma: 1, raised so that H1 + V2 + sigma >= 0.5 (lambda_min(H1) >= sum of min f_k)
         lam_lb = sum(float(min(f)) for f in inputs["f"][shape])
         inputs["sigma"][shape] = max(1.0, 0.5 - lam_lb - float(V2.min()))
-    out = {"requests": count, "rate_per_s": rate}
-    for mode in ("batch", "fp64", "fifo"):
+    out = {"requests": count, "rate_per_s": rate, "arrival_span_s": reqs[-1]["t"]}
+    for mode in ("batch", "fp64", "fifo", "saturate"):
         out[mode] = serve_run(ts, W, torch, dev, reqs, mode, inputs)
         log("serve %s: p50 %.1f ms p99 %.1f ms, %.3e DoF/s, %d/%d ok" % (
             mode, out[mode]["p50_ms"], out[mode]["p99_ms"], out[mode]["dof_s"], out[mode]["ok"], count))
@@ -656,45 +716,26 @@ def cpu_baseline(n, depth):
                       "O(N) diagonal scaling is not timed" % (depth, n, n, depth, n, depth, n, n)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=1000, help="points per axis (1000 is the headline workload)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-depth", type=int, default=96)
-    ap.add_argument("--no-pcg", action="store_true")
-    ap.add_argument("--no-split", action="store_true")
-    ap.add_argument("--no-table", action="store_true", help="skip the Table tab:accuracy_gh200 rows")
-    ap.add_argument("--no-gpe", action="store_true", help="skip the GPE and multi-level sections")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run a plain 1 GiB device copy three times first (reference for HBM byte counters)")
-    ap.add_argument("--serve-requests", type=int, default=300)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+SECTIONS = ["headline", "variants", "small64", "pcg", "split", "qhop", "table", "hermite", "gpe", "serve", "cpu"]
 
-    import numpy as np
-    import torch
 
-    import paper_2605_20491_amd as ts
-    import workloads as W
+def apply_rooflines(N, n, d, t_ms, prec, flops_exec=None):
+    """Roofline of one apply: the algorithmic flops 4 N sum(n_k) (real data) over
+    the time, against the MFMA peak of the transform precision; flops_exec, if
+    given, is what the kernels execute (half on folded axes)."""
+    alg = 4.0 * N * n * d
+    out = {"alg_flops": alg, "alg_tflops": alg / (t_ms * 1e-3) / 1e12, "peak_tflops": PEAK[prec]}
+    out["alg_frac"] = out["alg_tflops"] / PEAK[prec]
+    if flops_exec is not None:
+        out["executed_flops"] = flops_exec
+        out["executed_tflops"] = flops_exec / (t_ms * 1e-3) / 1e12
+        out["executed_frac"] = out["executed_tflops"] / PEAK[prec]
+    return out
 
-    dev = torch.device("cuda:0")
-    if args.calibrate_copy:
-        # 2^27 doubles: each copy reads and writes exactly 1 GiB
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("copy calibration: 3 copies of 1 GiB")
-    n, L, sigma, tau = args.n, 10.0, 1.0, 0.01
+
+def headline_section(ts, W, torch, dev, args):
+    """The 1e9-DoF FP64 inverse apply (the headline value) and its dominant kernel."""
+    n, L, sigma = args.n, 10.0, 1.0
     shape = (n, n, n)
     N = n ** 3
     f = [W.f_harmonic_cos(n, L) for _ in range(3)]
@@ -702,16 +743,13 @@ def main():
     plan = ts.ts_setup(shape, L, f, sigma)
     setup_s = time.perf_counter() - t0
     log("setup %.2f s" % setup_s)
-
     gen = torch.Generator(device=dev)
     gen.manual_seed(2)
     b = torch.randn(shape, dtype=torch.float64, device=dev, generator=gen)
     u = torch.empty_like(b)
-
     ms, wall = timed(lambda: ts.ts_apply_inverse(plan, b, u, prec="fp64"), args.steps, args.warmup)
     value = N / (ms * 1e-3)
     log("fp64 inverse %.2f ms/apply -> %.3e DoF/s" % (ms, value))
-
     # FP64 residual of the timed result (self-check; parity lives in tests/)
     r = ts.ts_operator_apply(plan, None, sigma, u)
     r.sub_(b)
@@ -725,7 +763,8 @@ def main():
     folded = bool(fmask & 2)
     deferred = folded and bin(fmask).count("1") >= 2
     hh, cc = n // 2, n % 2
-    flops_pass = 2.0 * (N / n) * ((hh + cc) ** 2 + hh ** 2) if folded else 2.0 * N * n
+    flops_alg = 2.0 * N * n                      # per pass, dense (any f_k)
+    flops_exec = 2.0 * (N / n) * ((hh + cc) ** 2 + hh ** 2) if folded else flops_alg
     work = torch.empty_like(b)
     t_pass, _ = timed(lambda: ts.ts_mode_pass(plan, 1, True, b, work, folded=deferred), args.steps, 1)
     t_back, _ = timed(lambda: ts.ts_mode_pass(plan, 1, False, b, work, folded=deferred), args.steps, 1)
@@ -734,12 +773,25 @@ def main():
         t_bfly, _ = timed(lambda: ts.ts_fold_butterfly(plan, fmask, b, work), args.steps, 1)
         log("single launches: forward pass %.2f ms, backward pass %.2f ms, %d-axis butterfly %.2f ms"
             % (t_pass, t_back, bin(fmask).count("1"), t_bfly))
+    # the same apply and pass with the half-extent passes off: what a potential
+    # without reflection symmetry runs
+    ts.ts_set_fold(plan, False)
+    ms_plain, _ = timed(lambda: ts.ts_apply_inverse(plan, b, u, prec="fp64"), max(2, args.steps // 2), 1)
+    t_plain, _ = timed(lambda: ts.ts_mode_pass(plan, 1, True, b, work), max(2, args.steps // 2), 1)
+    ts.ts_set_fold(plan, True)
+    log("plain passes: apply %.2f ms (%.3e DoF/s), forward column pass %.2f ms = %.1f%% of the FP64 peak"
+        % (ms_plain, N / (ms_plain * 1e-3), t_plain, 100 * flops_alg / (t_plain * 1e-3) / 1e12 / PEAK["fp64"]))
     del work
-    achieved = flops_pass / (t_pass * 1e-3) / 1e12
+    achieved = flops_alg / (t_pass * 1e-3) / 1e12
+    executed = flops_exec / (t_pass * 1e-3) / 1e12
     traffic, tinfo = measured_traffic()
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp64"], "traffic": traffic, "traffic_unit": "bytes per launch",
                 "traffic_algorithmic": 2 * 8 * N,
+                "achieved_basis": "algorithmic flops 2 N n per pass (dense mode product), per the work count of "
+                                  "the method; the folded kernel executes %.3g of them" % (flops_exec / flops_alg),
+                "executed_flops_per_launch": flops_exec, "executed_achieved": executed,
+                "executed_frac": executed / PEAK["fp64"], "fold_factor": flops_exec / flops_alg,
                 "traffic_note": (tinfo if isinstance(tinfo, str) else
                                  (None if tinfo is None else {k: tinfo[k] for k in ("fetch_bytes", "write_bytes",
                                                                                      "copy_scale", "profile")})),
@@ -748,79 +800,185 @@ def main():
                            "k_mode_mfma<double, cols, FOLD=1>: FP64 16x16x4 MFMA forward pass over half the extent "
                            "(even/odd halves of a symmetric axis)" if folded else
                            "k_mode_mfma<double, cols>: FP64 16x16x4 MFMA forward pass"),
-                "per_launch_flops": flops_pass, "avg_launch_ms": t_pass,
-                "backward_pass_ms": t_back, "butterfly_ms": t_bfly, "apply_ms": ms, "folded": folded}
-
+                "per_launch_flops": flops_alg, "avg_launch_ms": t_pass,
+                "backward_pass_ms": t_back, "butterfly_ms": t_bfly, "apply_ms": ms, "folded": folded,
+                "plain": {"kernel": "k_mode_mfma<double, cols>: FP64 16x16x4 MFMA forward pass, full extent",
+                          "avg_launch_ms": t_plain,
+                          "achieved": flops_alg / (t_plain * 1e-3) / 1e12,
+                          "frac": flops_alg / (t_plain * 1e-3) / 1e12 / PEAK["fp64"],
+                          "apply_ms": ms_plain, "apply_dof_s": N / (ms_plain * 1e-3),
+                          "apply": apply_rooflines(N, n, 3, ms_plain, "fp64")}}
+    roofline["apply"] = apply_rooflines(N, n, 3, ms, "fp64", flops_exec * 6)
     extra = {"setup_s": setup_s, "fp64_relres": resid, "wall_s_timed": wall}
-    if not args.no_extras:
-        for prec in ("fp32", "bf16"):
-            try:
-                msx, _ = timed(lambda: ts.ts_apply_inverse(plan, b, u, prec=prec), args.steps, 1)
-                extra["inverse_%s_dof_s" % prec] = N / (msx * 1e-3)
-                extra["inverse_%s_ms" % prec] = msx
-                extra["inverse_%s_alg_tflops" % prec] = 6 * flops_pass / (msx * 1e-3) / 1e12
-                log("%s inverse %.2f ms/apply" % (prec, msx))
-            except ts.TSError as e:
-                extra["inverse_%s" % prec] = "unavailable: %s" % e.status
-        # mixed-precision direct inverse refined to 1e-10 (FP64 residuals, FP32 / BF16 inner applies)
-        for inner in ("fp32", "bf16"):
-            ur = torch.empty_like(b)
-            it_rr = {}
+    state = {"plan": plan, "b": b, "shape": shape, "N": N, "n": n, "L": L, "flops_exec": flops_exec,
+             "flops_alg": flops_alg}
+    return value, ms, roofline, extra, state
 
-            def run_refined():
-                _, it_rr["it"], it_rr["rr"] = ts.ts_solve_refined(plan, b, ur, inner=inner, rtol=1e-10, maxit=60)
-            msr, _ = timed(run_refined, max(1, args.steps // 4), 1)
-            extra["refined_%s" % inner] = {"ms": msr, "iters": it_rr["it"], "relres": it_rr["rr"],
-                                          "dof_s": N / (msr * 1e-3)}
-            log("%s inverse refined to 1e-10: %.1f ms, %d iterations, relres %.2e"
-                % (inner, msr, it_rr["it"], it_rr["rr"]))
-            del ur
-        del u
-        facs = W.wavepacket_factors(shape, L, 2)
-        g = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in facs]
-        psi = (g[0][:, None, None] * g[1][None, :, None]) * g[2][None, None, :]
-        out = torch.empty_like(psi)
-        msx, _ = timed(lambda: ts.ts_apply_exp(plan, tau, psi, out, prec="fp64"), max(1, args.steps // 2), 1)
-        extra["exp_c128_fp64_dof_s"] = N / (msx * 1e-3)
-        extra["exp_c128_fp64_ms"] = msx
-        log("c128 exp %.2f ms/apply" % msx)
-        del out
-        psi64 = psi.to(torch.complex64)
-        del psi
-        out64 = torch.empty_like(psi64)
-        msx, _ = timed(lambda: ts.ts_apply_exp(plan, tau, psi64, out64, prec="fp32"), args.steps, 1)
-        extra["exp_c64_fp32_dof_s"] = N / (msx * 1e-3)
-        extra["exp_c64_fp32_ms"] = msx
-        log("c64 exp %.2f ms/apply" % msx)
-        del psi64, out64
-    if not args.no_extras:
-        extra["small_64"] = small_section(ts, W, torch, dev)
-    if not args.no_pcg:
-        precs = ["fp64", "fp32", "bf16"]
-        extra["pcg_n256"] = pcg_section(ts, W, torch, dev, 256, precs)
-        extra["pcg_n512"] = pcg_section(ts, W, torch, dev, 512, precs)
-        extra["inverse_iteration_n256"] = invit_section(ts, W, torch, dev, 256, precs)
+
+def variants_section(ts, W, torch, dev, args, st):
+    """FP32 / BF16 transforms, the mixed inverse refined to 1e-10, propagators."""
+    import numpy as np
+    plan, b, shape, N, n, L = st["plan"], st["b"], st["shape"], st["N"], st["n"], st["L"]
+    tau = 0.01
+    extra = {}
+    u = torch.empty_like(b)
+    for prec in ("fp32", "bf16"):
+        try:
+            msx, _ = timed(lambda: ts.ts_apply_inverse(plan, b, u, prec=prec), args.steps, 1)
+            extra["inverse_%s_dof_s" % prec] = N / (msx * 1e-3)
+            extra["inverse_%s_ms" % prec] = msx
+            extra["inverse_%s_roofline" % prec] = apply_rooflines(
+                N, n, 3, msx, prec, st["flops_exec"] * 6 if prec == "fp32" else None)
+            if prec == "bf16":
+                # HBM side: one BF16 apply moves 2 N s_io + (passes) x 2 N x 2 B at the least
+                extra["inverse_bf16_roofline"]["hbm_alg_bytes"] = 2.0 * N * 8
+                extra["inverse_bf16_roofline"]["hbm_alg_ms"] = 2.0 * N * 8 / HBM_PEAK / 1e6
+            log("%s inverse %.2f ms/apply (%.1f%% of the %s MFMA peak on the algorithmic flops)"
+                % (prec, msx, 100 * extra["inverse_%s_roofline" % prec]["alg_frac"], prec))
+        except ts.TSError as e:
+            extra["inverse_%s" % prec] = "unavailable: %s" % e.status
+    # mixed-precision direct inverse refined to 1e-10 (FP64 residuals, FP32 / BF16 inner applies)
+    for inner in ("fp32", "bf16"):
+        ur = torch.empty_like(b)
+        it_rr = {}
+
+        def run_refined():
+            _, it_rr["it"], it_rr["rr"] = ts.ts_solve_refined(plan, b, ur, inner=inner, rtol=1e-10, maxit=60)
+        msr, _ = timed(run_refined, max(1, args.steps // 4), 1)
+        extra["refined_%s" % inner] = {"ms": msr, "iters": it_rr["it"], "relres": it_rr["rr"],
+                                      "dof_s": N / (msr * 1e-3)}
+        log("%s inverse refined to 1e-10: %.1f ms, %d iterations, relres %.2e"
+            % (inner, msr, it_rr["it"], it_rr["rr"]))
+        del ur
+    del u
+    facs = W.wavepacket_factors(shape, L, 2)
+    g = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in facs]
+    psi = (g[0][:, None, None] * g[1][None, :, None]) * g[2][None, None, :]
+    out = torch.empty_like(psi)
+    msx, _ = timed(lambda: ts.ts_apply_exp(plan, tau, psi, out, prec="fp64"), max(1, args.steps // 2), 1)
+    extra["exp_c128_fp64_dof_s"] = N / (msx * 1e-3)
+    extra["exp_c128_fp64_ms"] = msx
+    log("c128 exp %.2f ms/apply" % msx)
+    del out
+    psi64 = psi.to(torch.complex64)
+    del psi
+    out64 = torch.empty_like(psi64)
+    msx, _ = timed(lambda: ts.ts_apply_exp(plan, tau, psi64, out64, prec="fp32"), args.steps, 1)
+    extra["exp_c64_fp32_dof_s"] = N / (msx * 1e-3)
+    extra["exp_c64_fp32_ms"] = msx
+    log("c64 exp %.2f ms/apply" % msx)
+    del psi64, out64
+    return extra
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1000, help="points per axis (1000 is the headline workload)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated sections to run (%s); the headline value is then omitted unless "
+                         "'headline' is listed" % ",".join(SECTIONS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-depth", type=int, default=96)
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-table", action="store_true", help="skip the Table tab:accuracy_gh200 rows")
+    ap.add_argument("--no-gpe", action="store_true", help="skip the GPE and multi-level sections")
+    ap.add_argument("--split-steps", type=int, default=100)
+    ap.add_argument("--pcg-sizes", default="256,512")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 1 GiB device copy three times first (reference for HBM byte counters)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path in this build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2605_20491_amd as ts
+    import workloads as W
+
+    if args.only:
+        run = set(x.strip() for x in args.only.split(",") if x.strip())
+        unknown = run - set(SECTIONS)
+        if unknown:
+            print("unknown sections: %s" % sorted(unknown), file=sys.stderr)
+            sys.exit(2)
+    else:
+        run = set(SECTIONS)
+        if args.no_extras:
+            run -= {"variants", "small64"}
+        if args.no_pcg:
+            run.discard("pcg")
+        if args.no_split:
+            run -= {"split", "qhop"}
+        if args.no_table:
+            run -= {"table", "hermite"}
+        if args.no_gpe:
+            run.discard("gpe")
+        if args.serve_requests <= 0:
+            run.discard("serve")
+        if args.no_cpu_baseline:
+            run.discard("cpu")
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # 2^27 doubles: each copy reads and writes exactly 1 GiB
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 copies of 1 GiB")
+    n = args.n
+    N = n ** 3
+    value = ms = roofline = None
+    extra = {}
+    if "headline" in run or "variants" in run:
+        value, ms, roofline, extra, st = headline_section(ts, W, torch, dev, args)
+        if "headline" not in run:
+            value = ms = roofline = None
+        if "variants" in run:
+            extra.update(variants_section(ts, W, torch, dev, args, st))
+        del st
         torch.cuda.empty_cache()
-    if not args.no_split:
-        extra["split_6d_n24"] = split_section(ts, W, torch, dev, 6, 24)
-        extra["split_9d_n8"] = split_section(ts, W, torch, dev, 9, 8)
+    if "small64" in run:
+        extra["small_64"] = small_section(ts, W, torch, dev)
+    if "pcg" in run:
+        precs = ["fp64", "fp32", "bf16"]
+        for m in [int(x) for x in args.pcg_sizes.split(",") if x]:
+            extra["pcg_n%d" % m] = pcg_section(ts, W, torch, dev, m, precs)
+            extra["inverse_iteration_n%d" % m] = invit_section(ts, W, torch, dev, m, precs)
+            torch.cuda.empty_cache()
+    if "split" in run:
+        extra["split_6d_n24"] = split_section(ts, W, torch, dev, 6, 24, steps=args.split_steps)
+        extra["split_9d_n8"] = split_section(ts, W, torch, dev, 9, 8, steps=args.split_steps)
+    if "qhop" in run:
         extra["qhop_separable_499"] = qhop_section(ts, W, torch, dev)
-    if not args.no_table:
+    if "table" in run:
         extra["accuracy_table"] = accuracy_section(ts, W, torch, dev)
+    if "hermite" in run:
         extra["hermite_table"] = hermite_section(ts, W, torch, dev)
-    if not args.no_gpe:
+    if "gpe" in run:
         extra["gpe_h1_flow_599"] = gpe_section(ts, W, torch, dev)
         extra["gpe_beta1600_599"] = gpe1600_section(ts, W, torch, dev)
         extra["multilevel_stirrer"] = multilevel_section(ts, W, torch, dev)
-    if args.serve_requests > 0:
+    if "serve" in run:
         extra["serving"] = serve_section(ts, W, torch, dev, args.serve_requests)
         torch.cuda.empty_cache()
     extra["paper_context"] = ("FP64 direct inverse, 1099^3 (Q^1 = FD), NVIDIA GH200: 0.508 s = 2.61e9 DoF/s "
                               "(Table tab:accuracy_gh200); not the same workload or hardware")
+    extra["sections"] = sorted(run)
     torch.cuda.synchronize()
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if "cpu" in run:
         t0 = time.perf_counter()
         cpu = cpu_baseline(n, args.cpu_depth)
         log("cpu baseline %.3e DoF/s (%.1f s)" % (cpu["value"], time.perf_counter() - t0))

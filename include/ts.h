@@ -57,9 +57,12 @@ typedef enum {
 typedef enum { TS_F64 = 0, TS_F32 = 1, TS_C128 = 2, TS_C64 = 3 } ts_dtype;
 
 /* Arithmetic of the per-axis transforms inside an apply.
- * FP64: FP64 MFMA, FP64 intermediates.  FP32: FP32 MFMA, FP32 intermediates.
- * BF16: BF16 MFMA operands with FP32 accumulation, BF16 intermediates.
- * Denominators and phase factors are always formed in FP64 and then cast. */
+ * FP64: FP64 MFMA with FP64 factors; FP64 intermediates for FP64 data, and
+ * for FP32 data (TS_F32, TS_C64) FP32 intermediates between HBM passes with
+ * every pass computed in FP64 (the paper's complex64 runs with FP64
+ * transforms, Sec. 6).  FP32: FP32 MFMA, FP32 intermediates.  BF16: BF16 MFMA
+ * operands with FP32 accumulation, BF16 intermediates.  Denominators and phase
+ * factors are always formed in FP64 and then cast. */
 typedef enum { TS_PREC_FP64 = 0, TS_PREC_FP32 = 1, TS_PREC_BF16 = 2 } ts_prec;
 
 /* Splitting schemes for ts_split_step (paper Sec. 5.1).  A = H1 (exact
@@ -103,7 +106,8 @@ int ts_setup(int d, const int64_t* n, double L, const double* const* f, double s
 int ts_destroy(ts_plan* plan);
 
 /* Half-extent passes on reflection-symmetric axes.  When f_k is symmetric
- * (f_k(x_j) = f_k(x_{n-1-j}) to 1e-13 relative) every eigenvector of H_k is
+ * (|f_k(x_j) - f_k(x_{n-1-j})| within 8 ulps of max(1, max|f_k|); the
+ * eigensolver then uses the mean of each mirrored pair) every eigenvector of H_k is
  * even or odd; the passes on that axis (n_k >= 64, every transform precision)
  * then fold x into x_i +- x_{n-1-i} and contract half the extent against the
  * even and odd halves of the factor (half the MFMA work), with a butterfly
@@ -229,7 +233,7 @@ int ts_mass(const ts_plan* plan, int axis, double* out);
  * FP64, backward transform with Q_k.
  *   b, u  : device arrays of prod(n) elements of dtype TS_F64 or TS_F32; u may
  *           alias b (in place)
- *   prec  : transform arithmetic (see ts_prec); FP64 requires dtype TS_F64
+ *   prec  : transform arithmetic (see ts_prec), any with either dtype
  * Errors: TS_ERR_INVALID (dtype/prec), TS_ERR_NOT_SPD, TS_ERR_NOMEM. */
 int ts_apply_inverse(ts_plan* plan, const void* b, void* u, int dtype, int prec,
                      void* hip_stream);
@@ -447,6 +451,16 @@ int ts_tridiag_eig_even_odd(int64_t n, const double* diag, const double* off, do
  * positive.  Host pointers.  Errors: TS_ERR_INVALID, TS_ERR_NOCONV. */
 int ts_sym_eig(int64_t n, const double* A, double* lam, double* Q);
 
+/* BF16 rounding exactly as the library applies it, run on the host (needs no
+ * GPU); BF16 = 1 sign, 8 exponent, 7 fraction bits.  route 0: the factor
+ * copies of the BF16 passes, FP64 rounded once to nearest, ties to even.
+ * route 1: data entering a BF16 pass, FP64 rounded to FP32 and then to BF16,
+ * each to nearest even (reading of the paper's BF16 runs: data are held in
+ * FP32 and rounded to BF16 for the matrix cores).  x: n host doubles; y: n
+ * host uint16 bit patterns.  Errors: TS_ERR_INVALID (null pointer, n < 0,
+ * route not 0 or 1). */
+int ts_bf16_round(int64_t n, const double* x, int route, uint16_t* y);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* ts_last_error(void);
 
@@ -496,16 +510,26 @@ typedef struct {
   uint64_t tag;
 } ts_result;
 
-/* Create a server on the current device.  hbm_budget_bytes is the arena
- * from which every admitted request's scratch is carved (allocated once,
- * here; resident factors of the plan cache are allocated outside it);
- * n_streams >= 1 non-blocking HIP streams of default priority; max_active
- * caps the requests in flight (0 = no cap; 1 with one stream = plain FIFO). */
-int ts_serve_create(size_t hbm_budget_bytes, int n_streams, int max_active, ts_server** out);
+/* Create a server on the current device.  hbm_budget_bytes bounds the device
+ * memory of the server: plan_reserve_bytes of it (0 = a quarter) hold the
+ * resident factors of the plan cache (plans are keyed by grid and potential
+ * samples; plans no queued or running request uses are evicted least recently
+ * used first), the rest is the arena from which every admitted request's
+ * scratch is carved (allocated once, here).  n_streams >= 1 non-blocking HIP streams of
+ * default priority: each runs the next unit of the most urgent admitted
+ * request (urgency = submit time + estimated GPU time), so at most n_streams
+ * requests are in flight at once.  max_active caps the admitted requests (0 =
+ * no cap); max_active = 1 makes the server a plain FIFO queue (arrival
+ * order, one request at a time). */
+int ts_serve_create(size_t hbm_budget_bytes, size_t plan_reserve_bytes, int n_streams, int max_active,
+                    ts_server** out);
 
 /* Queue a request; it is admitted when its scratch fits.  Returns a ticket.
- * TS_ERR_NOMEM if the request could never fit the budget, TS_ERR_INVALID for
- * a malformed request. */
+ * Builds the request's plan here (host eigendecomposition) unless it is cached.
+ * TS_ERR_NOMEM if the request could never fit the budget (scratch above the
+ * arena or factors above the plan reserve), TS_ERR_BUSY if its plan does not
+ * fit the plan reserve while queued or running requests hold the other plans
+ * (resubmit later), TS_ERR_INVALID for a malformed request. */
 int ts_serve_submit(ts_server* s, const ts_request* req, uint64_t* ticket);
 
 /* Non-blocking: *done = 1 and *res filled once the request has finished. */

@@ -91,6 +91,7 @@ def lib():
             "ts_tridiag_eig": [ctypes.c_int64, _dp, _dp, _dp, _dp],
             "ts_sym_eig": [ctypes.c_int64, _dp, _dp, _dp],
             "ts_tridiag_eig_even_odd": [ctypes.c_int64, _dp, _dp, _dp, _dp],
+            "ts_bf16_round": [ctypes.c_int64, _dp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint16)],
         }
         for name, argt in sig.items():
             fn = getattr(L, name)
@@ -513,6 +514,16 @@ def ts_sym_eig(A: np.ndarray):
     return lam, Q
 
 
+def ts_bf16_round(x: np.ndarray, route: int) -> np.ndarray:
+    """BF16 bit patterns (uint16) of x as the library rounds them: route 0 =
+    factor copies (FP64 rounded once), route 1 = data (FP64 -> FP32 -> BF16)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    y = np.empty(x.size, dtype=np.uint16)
+    _check(lib().ts_bf16_round(x.size, _dptr(x), int(route), y.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))),
+           "ts_bf16_round")
+    return y
+
+
 # ------------------------------------------------------------------ serving --
 
 TS_REQ_INVERSE, TS_REQ_EXP = 0, 1
@@ -535,7 +546,8 @@ class TsResult(ctypes.Structure):
 def _serve_lib():
     L = lib()
     if not hasattr(L, "_serve_ready"):
-        L.ts_serve_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]
+        L.ts_serve_create.argtypes = [ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(_vp)]
         L.ts_serve_submit.argtypes = [_vp, ctypes.POINTER(TsRequest), ctypes.POINTER(ctypes.c_uint64)]
         L.ts_serve_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(TsResult)]
         L.ts_serve_drain.argtypes = [_vp]
@@ -555,11 +567,11 @@ class Server:
     request has finished (the library reads and writes them asynchronously).
     """
 
-    def __init__(self, budget_bytes: int, n_streams: int = 4, max_active: int = 0):
+    def __init__(self, budget_bytes: int, n_streams: int = 4, max_active: int = 0, plan_reserve: int = 0):
         L = _serve_lib()
         h = _vp()
-        _check(L.ts_serve_create(int(budget_bytes), int(n_streams), int(max_active), ctypes.byref(h)),
-               "ts_serve_create")
+        _check(L.ts_serve_create(int(budget_bytes), int(plan_reserve), int(n_streams), int(max_active),
+                                 ctypes.byref(h)), "ts_serve_create")
         self._h = h
         self._keep = {}
 
@@ -613,5 +625,5 @@ class Server:
             pass
 
 
-def ts_serve_create(budget_bytes, n_streams=4, max_active=0) -> Server:
-    return Server(budget_bytes, n_streams, max_active)
+def ts_serve_create(budget_bytes, n_streams=4, max_active=0, plan_reserve=0) -> Server:
+    return Server(budget_bytes, n_streams, max_active, plan_reserve)

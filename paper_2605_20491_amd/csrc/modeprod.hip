@@ -844,8 +844,9 @@ hipError_t launch_butterfly(const ButterflyArgs& a, hipStream_t st) {
 
 hipError_t launch_pass(const PassArgs& pa, hipStream_t st) {
   if (pa.prec == 0) {
-    if (pa.tin != DT::F64 || pa.tout != DT::F64) return hipErrorInvalidValue;
-    return launch_typed<double, double, double>(pa, st);
+    if (pa.tin == DT::F64 && pa.tout == DT::F64) return launch_typed<double, double, double>(pa, st);
+    if (pa.tin == DT::F32 && pa.tout == DT::F32) return launch_typed<double, float, float>(pa, st);
+    return hipErrorInvalidValue;
   }
   if (pa.prec == 1) {
     if (pa.tin == DT::F64 && pa.tout == DT::F64) return launch_typed<float, double, double>(pa, st);
@@ -898,28 +899,6 @@ __global__ void k_cast_f32(const double* x, float* y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
 }
-// FP64 -> BF16 rounded directly to nearest even (no intermediate FP32 rounding).
-__device__ __forceinline__ uint16_t f64_to_bf16_rne(double v) {
-  const uint64_t u = __double_as_longlong(v);
-  const uint64_t sign = u >> 63;
-  const double av = fabs(v);
-  const float f = (float)av;  // candidate; fix up by comparing the two bf16 neighbours in FP64
-  const uint32_t fb = __float_as_uint(f) & 0xffff0000u;
-  const float lo = __uint_as_float(fb), hi = __uint_as_float(fb + 0x10000u);
-  const double dlo = av - (double)lo, dhi = (double)hi - av;
-  uint32_t pick;
-  if (dlo < dhi) pick = fb;
-  else if (dhi < dlo) pick = fb + 0x10000u;
-  else pick = ((fb >> 16) & 1u) ? fb + 0x10000u : fb;
-  if (av == 0.0) pick = 0;
-  return (uint16_t)((pick >> 16) | (sign << 15));
-}
-
-__global__ void k_cast_bf16(const double* x, uint16_t* y, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = f64_to_bf16_rne(x[i]);
-}
-
 // A data array to BF16 for the BF16 passes, four elements per thread (x
 // 16-byte, y 8-byte aligned, n % 4 == 0), stopping at once when *skip is set.
 // Rounded as the pass kernels round FP64 data they load (FP64 -> FP32 -> BF16,
@@ -948,15 +927,7 @@ __global__ void k_cast_bf16_t(const double* x, uint16_t* y, int64_t ld) {
   const int64_t total = ld * ld;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = e / ld, i = e % ld;  // output row j, column i
-    const double v = x[i * ld + j];
-    const double av = fabs(v);
-    const float f = (float)av;
-    const uint32_t fb = __float_as_uint(f) & 0xffff0000u;
-    const float lo = __uint_as_float(fb), hi = __uint_as_float(fb + 0x10000u);
-    const double dlo = av - (double)lo, dhi = (double)hi - av;
-    uint32_t pick = dlo < dhi ? fb : (dhi < dlo ? fb + 0x10000u : (((fb >> 16) & 1u) ? fb + 0x10000u : fb));
-    if (av == 0.0) pick = 0;
-    y[e] = (uint16_t)((pick >> 16) | ((v < 0.0 ? 1u : 0u) << 15));
+    y[e] = bf16_from_f64(x[i * ld + j]);
   }
 }
 
@@ -971,12 +942,6 @@ hipError_t launch_cast_f64_to_f32(const double* x, float* y, int64_t n, hipStrea
   int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
   if (blocks < 1) return hipSuccess;
   hipLaunchKernelGGL(k_cast_f32, dim3(blocks), dim3(256), 0, st, x, y, n);
-  return hipGetLastError();
-}
-hipError_t launch_cast_f64_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st) {
-  int blocks = (int)std::min<int64_t>(4096, (n + 255) / 256);
-  if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_cast_bf16, dim3(blocks), dim3(256), 0, st, x, y, n);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Device helpers shared by the FP64/FP32 and BF16 mode-product kernels.
 #pragma once
 
+#include "bf16_round.h"
 #include "ts_internal.h"
 
 namespace ts {
@@ -28,12 +29,7 @@ template <> __device__ __forceinline__ int out_row<float>(int l, int r) { return
 
 // ---- element conversions ----
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
-}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) { return bf16_from_f32(f); }  // nearest even
 
 template <typename TIn, typename TC> __device__ __forceinline__ TC cvt_in(TIn x);
 template <> __device__ __forceinline__ double cvt_in<double, double>(double x) { return x; }

@@ -27,14 +27,15 @@ template <typename T> __device__ __forceinline__ void sincos_t(T x, T* s, T* c);
 template <> __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) { sincos(x, s, c); }
 template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename TIO, typename TC, int NMAX, bool CPLX>
+template <typename TIO, typename TC, int MT, bool CPLX>
 __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
   if (a.skip && *a.skip) return;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   TC* tile = (TC*)smem;
-  TC* Qs = tile + a.tile_elems;  // NMAX x NMAX
 
   const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
   const int64_t lb = xcd_logical_block(blockIdx.x, a.nblocks);
   const int64_t ptile = lb / a.rtiles, rtile = lb % a.rtiles;
   const int64_t p0 = ptile * a.PB, r0 = rtile * a.RT;
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
   TIO* Xout = (TIO*)a.Xout;
   const TIO* V2 = (const TIO*)a.V2;
 
-  // ---- load (optionally multiplied by e^{-i th_pre V2}) ----
+  // ---- load (optionally multiplied by e^{-i th_pre V2}); padding rows/columns are zero ----
   if (CPLX) {
     for (int e = 2 * t; e < elems; e += 2 * GT) {
       const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
@@ -78,39 +79,47 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
 
   for (int s = 0; s < a.nsteps; ++s) {
     const GroupStep S = a.step[s];
-    const int n = S.n, st = S.stride;
-    const TC* Qg = (const TC*)S.Q;
-    for (int e = t; e < NMAX * NMAX; e += GT) {
-      const int i = e / NMAX, j = e % NMAX;
-      Qs[e] = (i < n && j < n) ? Qg[(int64_t)i * S.ld + j] : (TC)0;
-    }
-    __syncthreads();
-    const int outer = G / (n * st);
-    const int fibres = a.PB * outer * st * RT;
-    const int estep = st * RT;
-    for (int f = t; f < fibres; f += GT) {
-      const int rl = f % RT;
-      int rest = f / RT;
-      const int gin = rest % st;
-      rest /= st;
-      const int gout = rest % outer, pl = rest / outer;
-      const int base = (pl * G + gout * n * st + gin) * RT + rl;
-      TC x[NMAX], y[NMAX];
+    const int n = S.n;
+    // The tile is [B][n][W] along this axis (W = stride x RT contiguous values
+    // per row); the step is the batched product Y_b = F^T X_b over the B x W
+    // columns, 16 columns per MFMA chunk: A = F^T (M = output row, K = input
+    // row, from the zero-padded factor in registers), B = 4 input rows x 16
+    // columns read from LDS, accumulators written back in place (a chunk's
+    // columns belong to one wave, which reads all their rows first).
+    const int W = S.stride * RT;
+    const int ncols = elems / n;
+    const int kt = (n + 3) >> 2;
+    const TC* F = (const TC*)S.Q;
+    TC af[MT][8];
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) x[i] = (i < n) ? tile[base + i * estep] : (TC)0;
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j) y[j] = 0;
+      for (int k = 0; k < 8; ++k)
+        af[m][k] = k < kt ? F[(int64_t)(k * 4 + lk) * S.ld + m * 16 + lr] : (TC)0;
+    for (int c0 = wave * 16; c0 < ncols; c0 += (GT / 64) * 16) {
+      const int c = c0 + lr;
+      const bool cok = c < ncols;
+      const int b = c / W;
+      const int base = b * n * W + (c - b * W);
+      typename AccT<TC>::V acc[MT];
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) {
-        if (i < n) {
-          const TC xi = x[i];
+      for (int m = 0; m < MT; ++m) acc[m] = {0, 0, 0, 0};
 #pragma unroll
-          for (int j = 0; j < NMAX; ++j) y[j] += Qs[i * NMAX + j] * xi;
+      for (int k = 0; k < 8; ++k) {
+        if (k < kt) {
+          const int i = k * 4 + lk;
+          const TC x = (cok && i < n) ? tile[base + i * W] : (TC)0;
+#pragma unroll
+          for (int m = 0; m < MT; ++m) acc[m] = mfma(af[m][k], x, acc[m]);
         }
       }
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j)
-        if (j < n) tile[base + j * estep] = y[j];
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = m * 16 + out_row<TC>(lane, r);
+          if (cok && j < n) tile[base + j * W] = acc[m][r];
+        }
     }
     __syncthreads();
     if (s == a.scale_after) {
@@ -165,15 +174,11 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
 
 template <typename TIO, typename TC, bool CPLX>
 hipError_t launch_nmax(const GroupArgs& a, int nmax, hipStream_t st) {
-  const size_t lds = sizeof(TC) * ((size_t)a.tile_elems + (size_t)nmax * nmax);
+  const size_t lds = sizeof(TC) * (size_t)a.tile_elems;
   dim3 grid((unsigned)a.nblocks), block(GT);
-  switch (nmax) {
-    case 8: hipLaunchKernelGGL((k_group<TIO, TC, 8, CPLX>), grid, block, lds, st, a); break;
-    case 16: hipLaunchKernelGGL((k_group<TIO, TC, 16, CPLX>), grid, block, lds, st, a); break;
-    case 24: hipLaunchKernelGGL((k_group<TIO, TC, 24, CPLX>), grid, block, lds, st, a); break;
-    case 32: hipLaunchKernelGGL((k_group<TIO, TC, 32, CPLX>), grid, block, lds, st, a); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (nmax <= 16) hipLaunchKernelGGL((k_group<TIO, TC, 1, CPLX>), grid, block, lds, st, a);
+  else if (nmax <= 32) hipLaunchKernelGGL((k_group<TIO, TC, 2, CPLX>), grid, block, lds, st, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -196,6 +201,8 @@ hipError_t launch_group(const GroupArgs& a, DT tio, bool fp64_compute, bool cplx
     return cplx ? launch_nmax<double, float, true>(a, nmax, st) : launch_nmax<double, float, false>(a, nmax, st);
   if (tio == DT::F32 && !fp64_compute)
     return cplx ? launch_nmax<float, float, true>(a, nmax, st) : launch_nmax<float, float, false>(a, nmax, st);
+  if (tio == DT::F32 && fp64_compute)
+    return cplx ? launch_nmax<float, double, true>(a, nmax, st) : launch_nmax<float, double, false>(a, nmax, st);
   return hipErrorInvalidValue;
 }
 

@@ -1,16 +1,27 @@
 // Serving loop over the solver (not part of the paper): continuous batching of
 // requests of different d, n and kind on one GPU.
 //
-// * Admission by memory: the server allocates one arena of device memory at
-//   creation and carves each admitted request's scratch (apply workspace,
-//   phase tables, solver vectors) from it with a first-fit free list, so no
-//   hipMalloc / hipFree happens while requests run.  A request waits in the
-//   queue until its scratch fits.
-// * Resident factors: plans are cached by (grid, potential samples, sigma).
-// * Concurrency: admitted requests run on a pool of non-blocking streams;
-//   each advances one unit at a time (an apply, a refinement sweep, a few PCG
-//   iterations, a few split steps; ts_tasks.h), so new requests join between
-//   units and their kernels overlap on the device.
+// * Memory: the budget is split into a request arena and a plan reserve (by
+//   default a quarter of the budget).  The arena is allocated once, at creation, and
+//   each admitted request's scratch (apply workspace, phase tables, solver
+//   vectors) is carved from it with a first-fit free list, so no hipMalloc /
+//   hipFree happens while requests run; a request waits in the queue until
+//   its scratch fits.
+// * Resident factors: plans are cached by (grid, potential samples) -- the
+//   shift is a per-request argument of the tasks -- and the cache is held
+//   within the plan reserve: plans that no queued or running request uses are
+//   evicted least recently used first, and a submit whose plan cannot fit
+//   even then returns TS_ERR_BUSY.
+// * Scheduling: requests advance one unit at a time (an apply, a refinement
+//   sweep, a few PCG iterations, a few split steps; ts_tasks.h) on a pool of
+//   non-blocking streams.  Each free stream takes the next unit of the most
+//   urgent admitted request, urgency being the submit time plus the request's
+//   estimated GPU time (earliest expected completion first): a short request
+//   that arrives behind long ones overtakes them at their next unit boundary,
+//   while a long request is not starved by a stream of short ones, whose
+//   urgency lies later than its own once they arrive late enough.  At most one
+//   request per stream is in flight, so the kernels of a few requests overlap
+//   on the device instead of every admitted request sharing it.
 // * A request computes exactly what the plain entry points compute: the same
 //   task code, deterministic kernels, no dependence on the schedule.
 #include <algorithm>
@@ -90,11 +101,26 @@ class Arena {
   std::map<size_t, size_t> free_;  // offset -> length
 };
 
+struct CachedPlan {
+  ts_plan* plan = nullptr;
+  size_t bytes = 0;
+  int refs = 0;          // queued or running requests that use it
+  uint64_t last_use = 0;
+};
+
+enum class RState : int { Waiting = 0, InFlight = 1, Ready = 2 };
+
 struct Request {
   uint64_t ticket = 0;
   ts_request r{};
   std::vector<std::vector<double>> f;
   double t_submit = 0, t_admit = 0, t_done = 0;
+  double est = 0.0;       // estimated GPU seconds
+  double urgency = 0.0;   // t_submit + est
+  RState state = RState::Waiting;
+  bool started = false;
+  bool holds_stream = false;  // q->st is taken from the pool
+  std::string key;
   ts_plan* plan = nullptr;
   size_t slot_bytes[kSlots] = {};
   size_t need = 0;
@@ -114,9 +140,28 @@ std::string plan_key(const ts_request& r) {
   std::string k((const char*)&r.d, sizeof(r.d));
   k.append((const char*)r.n, sizeof(int64_t) * r.d);
   k.append((const char*)&r.L, sizeof(r.L));
-  k.append((const char*)&r.sigma, sizeof(r.sigma));
   for (int i = 0; i < r.d; ++i) k.append((const char*)r.f[i], sizeof(double) * r.n[i]);
   return k;
+}
+
+// Rough GPU seconds of a request, for ordering only: per-point costs of an
+// apply on this device (FP64 ~1.1e-10 s, FP32 about half, BF16 about a
+// quarter; complex data twice the real cost), ~12 iterations for PCG and
+// ~6 sweeps for refinement, plus a fixed launch cost per unit.
+double estimate_seconds(const ts_request& r, int64_t N) {
+  const double pt = r.prec == TS_PREC_FP64 ? 1.1e-10 : (r.prec == TS_PREC_FP32 ? 6e-11 : 3e-11);
+  const double vec = 3e-11;  // FP64 stencil and vector updates per point and iteration
+  double t;
+  if (r.kind == TS_REQ_INVERSE) {
+    if (r.V2) t = 12.0 * (pt + vec) * N;
+    else if (r.prec == TS_PREC_FP64) t = pt * N;
+    else t = 6.0 * (pt + vec) * N;
+  } else {
+    const double c = r.dtype == TS_C128 ? 2.0 : 1.0;
+    const int steps = r.V2 ? std::max(1, (int)std::ceil(std::fabs(r.tau) / r.dt)) : 1;
+    t = steps * c * pt * N;
+  }
+  return t + 1e-4;
 }
 
 }  // namespace
@@ -128,10 +173,12 @@ struct ts_server {
   std::deque<ts::Request*> pending;  // submitted, waiting for memory
   std::vector<ts::Request*> active;
   std::unordered_map<uint64_t, std::unique_ptr<ts::Request>> all;
-  std::map<std::string, ts_plan*> plans;
+  std::map<std::string, ts::CachedPlan> plans;
+  size_t plan_reserve = 0, plan_bytes = 0;
+  uint64_t use_clock = 0;
   ts::Arena arena;
   std::vector<hipStream_t> streams;
-  int next_stream = 0;
+  std::vector<hipStream_t> free_streams;
   int max_active = 0;
   int device = 0;
   char* pinned = nullptr;
@@ -146,7 +193,10 @@ struct ts_server {
   }
   void loop();
   bool try_admit(ts::Request* q);
+  int dispatch(ts::Request* q, hipStream_t st);
   void finish(ts::Request* q, int status);
+  void release_plan(const std::string& key);
+  bool evict_for(size_t bytes);
 };
 
 namespace ts {
@@ -159,7 +209,7 @@ void request_needs(const ts_request& r, const ts_plan* p, size_t* b) {
   for (int i = 0; i < kSlots; ++i) b[i] = 0;
   if (r.kind == TS_REQ_INVERSE) {
     for (int i = 0; i < kSlots; ++i) b[i] = need_inverse(p, i);
-    if (r.V2 || r.prec != TS_PREC_FP64) b[kSlotSolver] = need_solver(p, 4);
+    if (r.V2 || r.prec != TS_PREC_FP64) b[kSlotSolver] = need_solver(p, 5);  // PCG: r, z, p (x2), q
   } else {
     for (int i = 0; i < kSlots; ++i) b[i] = need_exp(p, i);
   }
@@ -177,7 +227,6 @@ int validate(const ts_request* r) {
     if ((r->V2 || r->prec != TS_PREC_FP64) && (!(r->rtol > 0) || r->maxit < 1)) return TS_ERR_INVALID;
   } else {
     if (r->dtype != TS_C128 && r->dtype != TS_C64) return TS_ERR_INVALID;
-    if (r->prec == TS_PREC_FP64 && r->dtype != TS_C128) return TS_ERR_INVALID;
     if (r->V2 && !(r->dt > 0)) return TS_ERR_INVALID;
   }
   return TS_OK;
@@ -206,41 +255,86 @@ bool ts_server::try_admit(Request* q) {
   q->host_slot = free_pinned.back();
   free_pinned.pop_back();
   q->ctx->host = pinned + 256 * (size_t)q->host_slot;
-  q->st = streams[next_stream];
-  next_stream = (next_stream + 1) % (int)streams.size();
   const ts_request& r = q->r;
-  int rc = TS_OK;
   if (r.kind == TS_REQ_INVERSE) {
     if (r.V2) {
-      if (hipMemsetAsync(r.out, 0, sizeof(double) * q->plan->N, q->st) != hipSuccess) rc = TS_ERR_DEVICE;
       q->task = make_pcg_task(q->plan, (const double*)r.V2, r.sigma, r.sigma, (const double*)r.in, (double*)r.out,
                               r.rtol, r.maxit, r.prec, *q->ctx);
     } else if (r.prec == TS_PREC_FP64) {
       q->task = make_inverse_task(q->plan, r.sigma, r.in, r.out, TS_F64, TS_PREC_FP64, *q->ctx);
     } else {
-      q->task = make_refine_task(q->plan, (const double*)r.in, (double*)r.out, r.prec, r.rtol, r.maxit, *q->ctx);
+      q->task = make_refine_task(q->plan, r.sigma, (const double*)r.in, (double*)r.out, r.prec, r.rtol, r.maxit,
+                                 *q->ctx);
     }
   } else {
     if (r.V2) {
       const int nsteps = std::max(1, (int)std::ceil(std::fabs(r.tau) / r.dt));
-      const double dt = r.tau / nsteps;
-      const size_t eb = r.dtype == TS_C128 ? 16 : 8;
-      if (r.in != r.out &&
-          hipMemcpyAsync(r.out, r.in, eb * q->plan->N, hipMemcpyDeviceToDevice, q->st) != hipSuccess)
-        rc = TS_ERR_DEVICE;
-      q->task = make_split_task(q->plan, r.V2, r.out, dt, nsteps, TS_STRANG_BAB, r.dtype, r.prec, *q->ctx);
+      q->task = make_split_task(q->plan, r.V2, r.out, r.tau / nsteps, nsteps, TS_STRANG_BAB, r.dtype, r.prec,
+                                *q->ctx);
     } else {
       q->task = make_exp_task(q->plan, r.tau, r.in, r.out, r.dtype, r.prec, *q->ctx);
     }
   }
-  if (rc == TS_OK) rc = q->task->start(q->st);
-  if (rc == TS_OK && hipEventCreateWithFlags(&q->ev, hipEventDisableTiming) != hipSuccess) rc = TS_ERR_DEVICE;
-  if (rc == TS_OK && hipEventRecord(q->ev, q->st) != hipSuccess) rc = TS_ERR_DEVICE;
+  q->state = RState::Ready;
   active.push_back(q);
+  return true;
+}
+
+// Enqueue the request's next unit (its first: the set-up copies and start())
+// on stream st and record its event.  Returns TS_OK if a unit is in flight,
+// else the request has been finished (done or failed) and st is free again.
+int ts_server::dispatch(Request* q, hipStream_t st) {
+  const ts_request& r = q->r;
+  int rc = TS_OK;
+  bool done = false;
+  q->st = st;
+  if (!q->started) {
+    q->started = true;
+    if (r.kind == TS_REQ_INVERSE && r.V2) {
+      if (hipMemsetAsync(r.out, 0, sizeof(double) * q->plan->N, st) != hipSuccess) rc = TS_ERR_DEVICE;
+    } else if (r.kind == TS_REQ_EXP && r.V2 && r.in != r.out) {
+      const size_t eb = r.dtype == TS_C128 ? 16 : 8;
+      if (hipMemcpyAsync(r.out, r.in, eb * q->plan->N, hipMemcpyDeviceToDevice, st) != hipSuccess) rc = TS_ERR_DEVICE;
+    }
+    if (rc == TS_OK) rc = q->task->start(st);
+  } else {
+    rc = q->task->advance(st, &done);
+  }
+  if (rc == TS_OK && done) {
+    q->iters = q->task->iters;
+    q->relres = q->task->relres;
+    finish(q, q->task->status);
+    return q->status == TS_OK ? 1 : q->status;
+  }
+  if (rc == TS_OK && !q->ev && hipEventCreateWithFlags(&q->ev, hipEventDisableTiming) != hipSuccess) rc = TS_ERR_DEVICE;
+  if (rc == TS_OK && hipEventRecord(q->ev, st) != hipSuccess) rc = TS_ERR_DEVICE;
   if (rc != TS_OK) {
-    // let queued work (if any) drain before the scratch is reused
-    hipStreamSynchronize(q->st);
+    hipStreamSynchronize(st);  // let queued work drain before the scratch is reused
     finish(q, rc);
+    return rc;
+  }
+  q->state = RState::InFlight;
+  return TS_OK;
+}
+
+// Plan cache: drop one reference; keep the plan resident for later requests.
+void ts_server::release_plan(const std::string& key) {
+  auto it = plans.find(key);
+  if (it != plans.end() && it->second.refs > 0) --it->second.refs;
+}
+
+// Evict unreferenced plans, least recently used first, until `bytes` more fit
+// in the plan reserve.  Returns false if they cannot.
+bool ts_server::evict_for(size_t bytes) {
+  while (plan_bytes + bytes > plan_reserve) {
+    auto victim = plans.end();
+    for (auto it = plans.begin(); it != plans.end(); ++it)
+      if (it->second.refs == 0 && (victim == plans.end() || it->second.last_use < victim->second.last_use))
+        victim = it;
+    if (victim == plans.end()) return false;
+    plan_bytes -= victim->second.bytes;
+    ts_destroy(victim->second.plan);
+    plans.erase(victim);
   }
   return true;
 }
@@ -249,6 +343,10 @@ bool ts_server::try_admit(Request* q) {
 void ts_server::finish(Request* q, int status) {
   q->status = status;
   q->t_done = clock();
+  if (q->holds_stream) free_streams.push_back(q->st);
+  q->holds_stream = false;
+  q->state = RState::Ready;
+  release_plan(q->key);
   if (q->ev) {
     hipEventDestroy(q->ev);
     q->ev = nullptr;
@@ -268,44 +366,52 @@ void ts_server::finish(Request* q, int status) {
 void ts_server::loop() {
   hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
+  // one request at a time (max_active == 1) is a plain FIFO queue: arrival order
+  const bool fifo = max_active == 1;
+  auto more_urgent = [fifo](const Request* a, const Request* b) {
+    if (fifo) return a->ticket < b->ticket;
+    return a->urgency < b->urgency || (a->urgency == b->urgency && a->ticket < b->ticket);
+  };
   for (;;) {
     if (stop && pending.empty() && active.empty()) break;
     bool progressed = false;
-    // admission: first fit in arrival order
+    // admission: most urgent first, first fit in the arena
+    std::stable_sort(pending.begin(), pending.end(), more_urgent);
     for (auto it = pending.begin(); it != pending.end();) {
-      Request* q = *it;
-      if (try_admit(q)) {
+      if (try_admit(*it)) {
         it = pending.erase(it);
         progressed = true;
       } else {
         ++it;
       }
     }
-    // progress: advance every request whose last unit has completed
-    std::vector<Request*> snapshot(active);
-    for (Request* q : snapshot) {
-      if (q->done || !q->ev) continue;
-      hipError_t e = hipEventQuery(q->ev);
+    // completions: a request whose unit has finished gives its stream back
+    for (Request* q : active) {
+      if (q->state != RState::InFlight) continue;
+      const hipError_t e = hipEventQuery(q->ev);
       if (e == hipErrorNotReady) continue;
       progressed = true;
-      if (e != hipSuccess) {
-        finish(q, TS_ERR_DEVICE);
-        continue;
+      q->state = RState::Ready;
+      free_streams.push_back(q->st);
+      q->holds_stream = false;
+      if (e != hipSuccess) q->status = TS_ERR_DEVICE;
+    }
+    for (Request* q : std::vector<Request*>(active))
+      if (q->state == RState::Ready && q->status != TS_OK) finish(q, q->status);
+    // dispatch: each free stream takes the next unit of the most urgent ready request
+    if (!free_streams.empty()) {
+      std::vector<Request*> ready;
+      for (Request* q : active)
+        if (q->state == RState::Ready) ready.push_back(q);
+      std::sort(ready.begin(), ready.end(), more_urgent);
+      for (Request* q : ready) {
+        if (free_streams.empty()) break;
+        hipStream_t st = free_streams.back();
+        free_streams.pop_back();
+        q->holds_stream = true;
+        dispatch(q, st);
+        progressed = true;
       }
-      bool done = false;
-      int rc = q->task->advance(q->st, &done);
-      if (rc != TS_OK) {
-        hipStreamSynchronize(q->st);
-        finish(q, rc);
-        continue;
-      }
-      if (done) {
-        q->iters = q->task->iters;
-        q->relres = q->task->relres;
-        finish(q, q->task->status);
-        continue;
-      }
-      if (hipEventRecord(q->ev, q->st) != hipSuccess) finish(q, TS_ERR_DEVICE);
     }
     if (!progressed) {
       cv_work.wait_for(lk, std::chrono::microseconds(50));
@@ -320,8 +426,11 @@ void ts_server::loop() {
 
 extern "C" {
 
-int ts_serve_create(size_t hbm_budget_bytes, int n_streams, int max_active, ts_server** out) {
-  if (!out || n_streams < 1 || n_streams > 64 || max_active < 0 || hbm_budget_bytes < kAlign) {
+int ts_serve_create(size_t hbm_budget_bytes, size_t plan_reserve_bytes, int n_streams, int max_active,
+                    ts_server** out) {
+  if (plan_reserve_bytes == 0) plan_reserve_bytes = hbm_budget_bytes / 4;
+  if (!out || n_streams < 1 || n_streams > 64 || max_active < 0 || plan_reserve_bytes >= hbm_budget_bytes ||
+      hbm_budget_bytes - plan_reserve_bytes < kAlign) {
     set_error("bad argument");
     return TS_ERR_INVALID;
   }
@@ -329,7 +438,8 @@ int ts_serve_create(size_t hbm_budget_bytes, int n_streams, int max_active, ts_s
   std::unique_ptr<ts_server> s(new ts_server());
   s->t0 = std::chrono::steady_clock::now();
   hipGetDevice(&s->device);
-  if (!s->arena.init(hbm_budget_bytes)) {
+  s->plan_reserve = plan_reserve_bytes;
+  if (!s->arena.init(hbm_budget_bytes - s->plan_reserve)) {
     set_error("arena allocation failed");
     return TS_ERR_NOMEM;
   }
@@ -340,6 +450,7 @@ int ts_serve_create(size_t hbm_budget_bytes, int n_streams, int max_active, ts_s
       return TS_ERR_DEVICE;
     }
     s->streams.push_back(st);
+    s->free_streams.push_back(st);
   }
   if (hipHostMalloc((void**)&s->pinned, 256 * (size_t)kPinnedSlots, hipHostMallocDefault) != hipSuccess) {
     set_error("pinned allocation failed");
@@ -363,29 +474,59 @@ int ts_serve_submit(ts_server* s, const ts_request* req, uint64_t* ticket) {
     q->f.emplace_back(req->f[k], req->f[k] + req->n[k]);
     q->r.f[k] = q->f.back().data();
   }
-  // resident factors: build the plan outside the server lock (host work)
-  const std::string key = plan_key(q->r);
+  // resident factors: build a missing plan outside the server lock (host work),
+  // then hold it in the cache within the plan reserve
+  q->key = plan_key(q->r);
   ts_plan* plan = nullptr;
   {
     std::lock_guard<std::mutex> g(s->mu);
-    auto it = s->plans.find(key);
-    if (it != s->plans.end()) plan = it->second;
+    auto it = s->plans.find(q->key);
+    if (it != s->plans.end()) {
+      plan = it->second.plan;
+      it->second.refs += 1;
+      it->second.last_use = ++s->use_clock;
+    }
   }
   if (!plan) {
     const double* fp[TS_MAX_D];
     for (int k = 0; k < req->d; ++k) fp[k] = q->r.f[k];
     int rc = ts_setup(req->d, req->n, req->L, fp, req->sigma, &plan);
     if (rc) return rc;
+    const size_t pb = plan_device_bytes(plan);
     std::lock_guard<std::mutex> g(s->mu);
-    auto it = s->plans.find(key);
-    if (it != s->plans.end()) {
+    auto it = s->plans.find(q->key);
+    if (it != s->plans.end()) {  // built by another thread meanwhile
       ts_destroy(plan);
-      plan = it->second;
+      plan = it->second.plan;
+      it->second.refs += 1;
+      it->second.last_use = ++s->use_clock;
     } else {
-      s->plans[key] = plan;
+      if (pb > s->plan_reserve) {
+        ts_destroy(plan);
+        set_error("the request's factors (" + std::to_string(pb) + " bytes) exceed the plan reserve (" +
+                  std::to_string(s->plan_reserve) + " bytes)");
+        return TS_ERR_NOMEM;
+      }
+      if (!s->evict_for(pb)) {
+        ts_destroy(plan);
+        set_error("plan reserve held by running requests; resubmit later");
+        return TS_ERR_BUSY;
+      }
+      CachedPlan cp;
+      cp.plan = plan;
+      cp.bytes = pb;
+      cp.refs = 1;
+      cp.last_use = ++s->use_clock;
+      s->plans[q->key] = cp;
+      s->plan_bytes += pb;
     }
   }
+  auto unref = [&]() {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->release_plan(q->key);
+  };
   if (req->kind == TS_REQ_INVERSE && !(plan->lam_min + req->sigma > 0.0)) {
+    unref();
     set_error("H1 + sigma is not positive definite");
     return TS_ERR_NOT_SPD;
   }
@@ -394,9 +535,13 @@ int ts_serve_submit(ts_server* s, const ts_request* req, uint64_t* ticket) {
   q->need = 0;
   for (int i = 0; i < kSlots; ++i) q->need += round_up((int64_t)q->slot_bytes[i], kAlign);
   if (q->need > s->arena.size()) {
-    set_error("request scratch (" + std::to_string(q->need) + " bytes) exceeds the server budget");
+    unref();
+    set_error("request scratch (" + std::to_string(q->need) + " bytes) exceeds the server's arena (" +
+              std::to_string(s->arena.size()) + " bytes)");
     return TS_ERR_NOMEM;
   }
+  q->est = estimate_seconds(q->r, plan->N);
+  q->urgency = q->t_submit + q->est;
   std::lock_guard<std::mutex> g(s->mu);
   q->ticket = s->next_ticket++;
   *ticket = q->ticket;
@@ -447,7 +592,7 @@ int ts_serve_destroy(ts_server* s) {
     hipStreamSynchronize(st);
     hipStreamDestroy(st);
   }
-  for (auto& kv : s->plans) ts_destroy(kv.second);
+  for (auto& kv : s->plans) ts_destroy(kv.second.plan);
   if (s->pinned) hipHostFree(s->pinned);
   delete s;
   return TS_OK;

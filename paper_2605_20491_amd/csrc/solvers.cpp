@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <utility>
 
 #include "../../include/ts.h"
 #include "ts_apply.h"
@@ -84,7 +85,7 @@ namespace {
 // Layout of a context's solver slot: a fixed header (two partial arrays and
 // the scalar block) followed by nvec FP64 vectors of N.
 struct SolverBufs {
-  double* vec[6] = {};
+  double* vec[8] = {};
   double* partial = nullptr;
   double* partial2 = nullptr;
   SolverScalars* sc = nullptr;
@@ -132,16 +133,17 @@ class PcgTask : public Task {
         scale_(scale_io && p->massed), c_(c) {}
 
   int start(hipStream_t st) override {
-    TS_RC(solver_buffers(c_, p_, scale_ ? 5 : 4, b_));
+    TS_RC(solver_buffers(c_, p_, scale_ ? 6 : 5, b_));
     r_ = b_.vec[0];
     z_ = b_.vec[1];
     pp_ = b_.vec[2];
     q_ = b_.vec[3];
+    pp2_ = b_.vec[4];
     N_ = p_->N;
     if (scale_) {  // f and x into the symmetric form's variables
-      TS_TRY(mass_scale(p_, f_, b_.vec[4], true, st));
+      TS_TRY(mass_scale(p_, f_, b_.vec[5], true, st));
       TS_TRY(mass_scale(p_, x_, x_, true, st));
-      f_ = b_.vec[4];
+      f_ = b_.vec[5];
     }
     flexible_ = prec_ != TS_PREC_FP64;
     done_ = &b_.sc->done;
@@ -165,6 +167,8 @@ class PcgTask : public Task {
     sq_.dot = StDot::UdotOut;
     sq_.partial = b_.partial;
     sq_.skip = done_;
+    // the update p = z + beta p rides on the next operator sweep (FD stencil only)
+    can_fuse_ = sq_.bw == 0 && !sq_.dense[0];
     TS_RC(enqueue_chunk(st));
     TS_TRY(snapshot(b_, st));
     return TS_OK;
@@ -204,7 +208,15 @@ class PcgTask : public Task {
  private:
   int enqueue_chunk(hipStream_t st) {
     for (int ci = 0; ci < chunk_ && enq_ < maxit_; ++ci, ++enq_) {
+      // q = A p with <p, q>; after the first iteration p = z + beta p is formed
+      // inside this sweep (into the other direction buffer)
+      sq_.u = pp_;
+      sq_.z = pending_ ? z_ : nullptr;
+      sq_.bsc = pending_ ? b_.sc : nullptr;
+      sq_.unew = pending_ ? pp2_ : nullptr;
       TS_TRY(launch_stencil(sq_, st));
+      if (pending_) std::swap(pp_, pp2_);
+      pending_ = false;
       TS_TRY(launch_scalar(ScalarStep::Alpha, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
       TS_TRY(launch_cg_update(x_, r_, pp_, q_, N_, b_.sc, b_.partial, done_, st));
       TS_TRY(launch_scalar(ScalarStep::RR, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
@@ -213,7 +225,8 @@ class PcgTask : public Task {
                         done_, st));
       TS_TRY(launch_scalar(ScalarStep::Beta, b_.sc, b_.partial, flexible_ ? b_.partial2 : nullptr, flexible_,
                            maxit_, st));
-      TS_TRY(launch_xpby(z_, pp_, N_, b_.sc, done_, st));
+      if (can_fuse_) pending_ = true;
+      else TS_TRY(launch_xpby(z_, pp_, N_, b_.sc, done_, st));
     }
     return TS_OK;
   }
@@ -228,9 +241,10 @@ class PcgTask : public Task {
   bool scale_;
   ExecCtx& c_;
   SolverBufs b_;
-  double *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr, *q_ = nullptr;
+  double *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr, *q_ = nullptr, *pp2_ = nullptr;
   int64_t N_ = 0;
   int flexible_ = 0;
+  bool can_fuse_ = false, pending_ = false;
   const int* done_ = nullptr;
   int chunk_ = 4, enq_ = 0;
   bool final_ = false;
@@ -243,26 +257,27 @@ class PcgTask : public Task {
 // than 0.9 twice, the rest is flexible CG warm-started from u.
 class RefineTask : public Task {
  public:
-  RefineTask(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, bool scale_io,
-             ExecCtx& c)
-      : p_(p), f_(f), u_(u), inner_(inner), rtol_(rtol), maxit_(maxit), scale_(scale_io && p->massed), c_(c) {}
+  RefineTask(ts_plan* p, double sigma, const double* f, double* u, int inner, double rtol, int maxit,
+             bool scale_io, ExecCtx& c)
+      : p_(p), sigma_(sigma), f_(f), u_(u), inner_(inner), rtol_(rtol), maxit_(maxit),
+        scale_(scale_io && p->massed), c_(c) {}
 
   int start(hipStream_t st) override {
-    // vector 4 holds the scaled right-hand side: the CG fallback uses 0..3
-    TS_RC(solver_buffers(c_, p_, scale_ ? 5 : 2, b_));
+    // vector 5 holds the scaled right-hand side: the CG fallback uses 0..4
+    TS_RC(solver_buffers(c_, p_, scale_ ? 6 : 2, b_));
     r_ = b_.vec[0];
     dlt_ = b_.vec[1];
     N_ = p_->N;
     if (scale_) {
-      TS_TRY(mass_scale(p_, f_, b_.vec[4], true, st));
-      f_ = b_.vec[4];
+      TS_TRY(mass_scale(p_, f_, b_.vec[5], true, st));
+      f_ = b_.vec[5];
     }
     TS_TRY(launch_init_scalars(b_.sc, rtol_ * rtol_, st));
     TS_TRY(launch_dot(f_, f_, N_, b_.partial, nullptr, nullptr, nullptr, st));
     TS_TRY(launch_scalar(ScalarStep::SetAux0, b_.sc, b_.partial, nullptr, 0, maxit_, st));
     // first sweep from u = 0: u = M^{-1} f, then its residual
-    TS_RC(apply_inverse_impl(p_, p_->sigma, f_, u_, TS_F64, inner_, st, c_, nullptr, true));
-    sa_ = stencil_args(p_, nullptr, p_->sigma, u_, r_, true);
+    TS_RC(apply_inverse_impl(p_, sigma_, f_, u_, TS_F64, inner_, st, c_, nullptr, true));
+    sa_ = stencil_args(p_, nullptr, sigma_, u_, r_, true);
     sa_.mode = StOut::FminusAx;
     sa_.rhs = f_;
     sa_.dot = StDot::OutdotOut;
@@ -308,10 +323,10 @@ class RefineTask : public Task {
     if (sweeps_ >= maxit_) { set_error("refinement did not reach rtol"); status = TS_ERR_NOCONV; return TS_OK; }
     *done = false;
     if (slow_ >= 2) {
-      cg_ = make_pcg_task(p_, nullptr, p_->sigma, p_->sigma, f_, u_, rtol_, maxit_ - sweeps_, inner_, c_, false);
+      cg_ = make_pcg_task(p_, nullptr, sigma_, sigma_, f_, u_, rtol_, maxit_ - sweeps_, inner_, c_, false);
       return cg_->start(st);
     }
-    TS_RC(apply_inverse_impl(p_, p_->sigma, r_, dlt_, TS_F64, inner_, st, c_, nullptr, true));
+    TS_RC(apply_inverse_impl(p_, sigma_, r_, dlt_, TS_F64, inner_, st, c_, nullptr, true));
     TS_TRY(launch_axpy1(u_, dlt_, N_, nullptr, st));
     TS_TRY(launch_stencil(sa_, st));
     TS_TRY(launch_scalar(ScalarStep::SetRR, b_.sc, b_.partial, nullptr, 0, maxit_, st));
@@ -321,6 +336,7 @@ class RefineTask : public Task {
   }
 
   ts_plan* p_;
+  double sigma_;
   const double* f_;
   double* u_;
   int inner_;
@@ -382,9 +398,9 @@ std::unique_ptr<Task> make_pcg_task(ts_plan* p, const double* V2, double s_op, d
                                     double* x, double rtol, int maxit, int prec, ExecCtx& c, bool scale_io) {
   return std::unique_ptr<Task>(new PcgTask(p, V2, s_op, s_pc, f, x, rtol, maxit, prec, scale_io, c));
 }
-std::unique_ptr<Task> make_refine_task(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit,
-                                       ExecCtx& c) {
-  return std::unique_ptr<Task>(new RefineTask(p, f, u, inner, rtol, maxit, true, c));
+std::unique_ptr<Task> make_refine_task(ts_plan* p, double sigma, const double* f, double* u, int inner, double rtol,
+                                       int maxit, ExecCtx& c) {
+  return std::unique_ptr<Task>(new RefineTask(p, sigma, f, u, inner, rtol, maxit, true, c));
 }
 std::unique_ptr<Task> make_inverse_task(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
                                         ExecCtx& c) {
@@ -408,7 +424,7 @@ int pcg_run(ts_plan* p, const double* V2, double s_op, double s_pc, const double
 
 int refine_run(ts_plan* p, const double* f, double* u, int inner, double rtol, int maxit, int* iters,
                double* relres, hipStream_t st, ExecCtx& c) {
-  RefineTask t(p, f, u, inner, rtol, maxit, true, c);
+  RefineTask t(p, p->sigma, f, u, inner, rtol, maxit, true, c);
   int rc = run_blocking(t, st);
   if (iters) *iters = t.iters;
   if (relres) *relres = t.relres;
@@ -433,11 +449,11 @@ int invit_run(ts_plan* plan, const double* V2, double shift, double* u, int step
   }
   const int64_t N = plan->N;
   ExecCtx& c = plan->ctx;
-  // PCG uses vectors 0..3; H u and the warm-started iterate w take 4 and 5
+  // PCG uses vectors 0..4; H u and the warm-started iterate w take 5 and 6
   SolverBufs b;
-  TS_RC(solver_buffers(c, plan, 6, b));
-  double* Hu = b.vec[4];
-  double* w = b.vec[5];
+  TS_RC(solver_buffers(c, plan, 7, b));
+  double* Hu = b.vec[5];
+  double* w = b.vec[6];
   // SEM: iterate on the symmetric form, u in the variables M^{1/2} u
   TS_TRY(mass_scale(plan, u, u, true, st));
   auto rayleigh = [&](double* lam) -> int {

@@ -137,7 +137,6 @@ int check_common(ts_plan* plan, const void* V2, void* psi, double dt, int nsteps
   if (nsteps < 0 || !std::isfinite(dt)) { set_error("bad dt or nsteps"); return TS_ERR_INVALID; }
   if (dtype != TS_C128 && dtype != TS_C64) { set_error("splitting needs TS_C128 or TS_C64 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
-  if (prec == TS_PREC_FP64 && dtype != TS_C128) { set_error("FP64 transforms need TS_C128 data"); return TS_ERR_INVALID; }
   return TS_OK;
 }
 

@@ -3,13 +3,16 @@
 // accessors and error plumbing.  Solvers built on the applies live in
 // solvers.cpp.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
 
 #include "../../include/ts.h"
+#include "bf16_round.h"
 #include "ts_internal.h"
 #include "ts_apply.h"
 #include "ts_sem.h"
@@ -67,14 +70,16 @@ struct FoldPlan {
   int64_t ne = 0, no = 0, hh = 0, cc = 0;
 };
 
-// f symmetric to 1e-13 relative
+// f reflection-symmetric up to the rounding of its samples: |f_i - f_{n-1-i}|
+// within 8 ulps of max(1, max|f|).  The split eigensolvers then use the
+// average of each mirrored pair, which moves the operator by at most half that.
 bool symmetric_samples(int64_t n, const double* f) {
   double fmax = 0.0, fasym = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     fmax = std::max(fmax, std::fabs(f[i]));
     fasym = std::max(fasym, std::fabs(f[i] - f[n - 1 - i]));
   }
-  return fasym <= 1e-13 * std::max(1.0, fmax);
+  return fasym <= 8.0 * DBL_EPSILON * std::max(1.0, fmax);
 }
 
 // Assemble the full eigenvectors from the two blocks (Ue: ne x ne, Uo: no x no,
@@ -133,14 +138,14 @@ bool split_eig_tridiag(int64_t n, const double* dg, const double* off, double* l
   const int64_t hh = n / 2, cc = n % 2, ne = hh + cc, no = hh;
   if (hh == 0) return false;
   std::vector<double> de(ne), oe(ne > 1 ? ne - 1 : 1, 0.0), dd(no), od(no > 1 ? no - 1 : 1, 0.0);
-  for (int64_t i = 0; i < hh; ++i) {
-    de[i] = dg[i];
-    dd[i] = dg[i];
+  for (int64_t i = 0; i < hh; ++i) {  // mirrored pairs averaged (equal up to rounding)
+    de[i] = 0.5 * (dg[i] + dg[n - 1 - i]);
+    dd[i] = de[i];
   }
-  for (int64_t i = 0; i + 1 < hh; ++i) oe[i] = od[i] = off[i];
+  for (int64_t i = 0; i + 1 < hh; ++i) oe[i] = od[i] = 0.5 * (off[i] + off[n - 2 - i]);
   if (cc) {
     de[hh] = dg[hh];
-    oe[hh - 1] = std::sqrt(2.0) * off[hh - 1];  // e_{h-1} pair coupled to the centre
+    oe[hh - 1] = std::sqrt(2.0) * 0.5 * (off[hh - 1] + off[hh]);  // e_{h-1} pair coupled to the centre
   } else {
     de[hh - 1] += off[hh - 1];  // the pair h-1, h = n-1-(h-1) couples to itself
     dd[hh - 1] -= off[hh - 1];
@@ -520,6 +525,26 @@ static int build_axis_general(int64_t n, const double* K, const double* m_in, co
   return upload_op_pass(n, std::vector<double>(K, K + n * n), phys->op_pass);
 }
 
+// Device bytes held by a plan: factors of every distinct axis (all
+// precisions, half factors of folded axes), per-axis vectors and the scaling
+// tables.  Scratch contexts are not counted.
+size_t plan_device_bytes(const ts_plan* p) {
+  std::vector<const AxisFactor*> seen;
+  size_t b = sizeof(double) * (size_t)(p->Ps + p->Rs);
+  std::function<void(const AxisFactor*)> add = [&](const AxisFactor* F) {
+    if (!F || std::find(seen.begin(), seen.end(), F) != seen.end()) return;
+    seen.push_back(F);
+    b += (size_t)(F->kpad * F->ld) * (8 + 8 + 4 + 4 + 2 + 2);
+    b += sizeof(double) * (size_t)F->n * (F->msq ? 5 : 3);
+    if (F->band) b += sizeof(double) * (size_t)F->n * (2 * F->bw + 1);
+    if (F->fold) b += (size_t)(F->fkp * F->fkp) * (5 * 8 + 5 * 4 + 4 * 2);
+    add(F->op_pass.get());
+  };
+  for (const auto& F : p->ax) add(F.get());
+  for (const auto& F : p->ax_sym) add(F.get());
+  return b;
+}
+
 ExecCtx::~ExecCtx() {
   if (!growable) return;
   for (int i = 0; i < kSlots; ++i) hipFree(buf[i]);
@@ -585,7 +610,10 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   const int d = p->d;
   const bool cplx = ap.cplx;
   const int ncomp = cplx ? 2 : 1;
-  DT inter = ap.prec == TS_PREC_FP64 ? DT::F64 : (ap.prec == TS_PREC_FP32 ? DT::F32 : DT::BF16);
+  // (FP64 transforms of FP32-stored data keep FP32 intermediates: the output
+  // buffer, which holds every other intermediate, has room for no more)
+  DT inter = ap.prec == TS_PREC_FP64 ? (ap.tin == DT::F32 && ap.tout == DT::F32 ? DT::F32 : DT::F64)
+                                     : (ap.prec == TS_PREC_FP32 ? DT::F32 : DT::BF16);
   // pass order: forward over every axis but s (fastest first), then s with the
   // scaling epilogue; backward over s first, then the others.
   std::vector<int> order;
@@ -698,7 +726,6 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
   if (!p || !b || !u) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_F64 && dtype != TS_F32) { set_error("inverse apply needs TS_F64 or TS_F32 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
-  if (prec == TS_PREC_FP64 && dtype != TS_F64) { set_error("FP64 transforms need TS_F64 data"); return TS_ERR_INVALID; }
   if (!(p->lam_min + shift > 0.0)) {
     set_error("H1 + sigma is not positive definite: lambda_min(H1) + sigma = " + std::to_string(p->lam_min + shift));
     return TS_ERR_NOT_SPD;
@@ -737,7 +764,6 @@ static int check_exp_args(ts_plan* p, double tau, const void* in, const void* ou
   if (!p || !in || !out) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_C128 && dtype != TS_C64) { set_error("propagator needs TS_C128 or TS_C64 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
-  if (prec == TS_PREC_FP64 && dtype != TS_C128) { set_error("FP64 transforms need TS_C128 data"); return TS_ERR_INVALID; }
   if (!std::isfinite(tau)) { set_error("tau is not finite"); return TS_ERR_INVALID; }
   return TS_OK;
 }
@@ -1188,6 +1214,12 @@ int ts_tridiag_eig_even_odd(int64_t n, const double* diag, const double* off, do
     if (off[i] != off[n - 2 - i]) { set_error("off-diagonal is not reflection-symmetric"); return TS_ERR_INVALID; }
   FoldPlan fp;
   if (!split_eig_tridiag(n, diag, off, lam, Q, fp)) { set_error("QL iteration limit reached"); return TS_ERR_NOCONV; }
+  return TS_OK;
+}
+
+int ts_bf16_round(int64_t n, const double* x, int route, uint16_t* y) {
+  if (n < 0 || (n > 0 && (!x || !y)) || (route != 0 && route != 1)) { set_error("bad argument"); return TS_ERR_INVALID; }
+  for (int64_t i = 0; i < n; ++i) y[i] = route == 0 ? bf16_from_f64(x[i]) : bf16_from_f32((float)x[i]);
   return TS_OK;
 }
 

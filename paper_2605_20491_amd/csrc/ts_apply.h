@@ -59,5 +59,7 @@ int invit_run(ts_plan* plan, const double* V2, double shift, double* u, int step
               double pcg_rtol, int maxit, int precond, double* lam_hist, int* pcg_iters, int* steps_done,
               hipStream_t st);
 size_t need_solver(const ts_plan* p, int nvec);
+// Device bytes of a plan's factors and tables (its scratch not included).
+size_t plan_device_bytes(const ts_plan* p);
 
 }  // namespace ts

@@ -153,7 +153,6 @@ hipError_t launch_phase_tables(const PhaseTableArgs& a, hipStream_t st);
 
 // Device-side casts for the plan's reduced-precision copies of Q.
 hipError_t launch_cast_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
-hipError_t launch_cast_f64_to_bf16(const double* x, uint16_t* y, int64_t n, hipStream_t st);
 // FP64 data -> BF16 as the BF16 pass kernels round what they load (through
 // FP32, each step to nearest even), four per thread: n % 4 == 0, x 16-byte and
 // y 8-byte aligned (else hipErrorInvalidValue); honours *skip.

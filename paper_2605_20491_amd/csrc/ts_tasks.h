@@ -35,8 +35,8 @@ int run_blocking(Task& t, hipStream_t st);
 // moved to and from the symmetric form's variables M^{1/2} x.
 std::unique_ptr<Task> make_pcg_task(ts_plan* p, const double* V2, double s_op, double s_pc, const double* f,
                                     double* x, double rtol, int maxit, int prec, ExecCtx& c, bool scale_io = true);
-std::unique_ptr<Task> make_refine_task(ts_plan* p, const double* f, double* u, int inner, double rtol,
-                                       int maxit, ExecCtx& c);
+std::unique_ptr<Task> make_refine_task(ts_plan* p, double sigma, const double* f, double* u, int inner,
+                                       double rtol, int maxit, ExecCtx& c);
 std::unique_ptr<Task> make_inverse_task(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
                                         ExecCtx& c);
 std::unique_ptr<Task> make_exp_task(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,

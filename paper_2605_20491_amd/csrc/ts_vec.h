@@ -13,6 +13,8 @@ constexpr int kRedBlocks = 1024;  // fixed grid of every reduction: results are 
 enum class StOut : int { Ax = 0, FminusAx = 1 };
 enum class StDot : int { None = 0, UdotOut = 1, OutdotOut = 2 };
 
+struct SolverScalars;
+
 struct StencilArgs {
   int d = 0;
   int64_t N = 0;
@@ -23,6 +25,12 @@ struct StencilArgs {
   const double* V2 = nullptr;
   double s = 0.0;
   const double* u = nullptr;
+  // Fused update of the PCG direction: with z set, the operator acts on
+  // z + beta u (beta = bsc->beta), which is also written to unew (a buffer
+  // other than u: neighbouring tiles still read the old u)
+  const double* z = nullptr;
+  const SolverScalars* bsc = nullptr;
+  double* unew = nullptr;
   const double* rhs = nullptr;     // StOut::FminusAx: out = rhs - A u
   double* out = nullptr;
   StOut mode = StOut::Ax;

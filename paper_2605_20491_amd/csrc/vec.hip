@@ -14,85 +14,127 @@
 namespace ts {
 namespace {
 
-constexpr int kMarch = 32;       // stencil: points per thread along axis 0
-constexpr int kGroup = 8;        // stencil: points whose loads are issued together
+// Stencil tiles: the grid is viewed as [P][NY][NX] with NX = n_{d-1}, NY =
+// n_{d-2} and P the flattened slower axes 0..d-3.  A block covers a TY x TX
+// patch of one (y, x) plane and marches through `planes` consecutive planes p:
+// the patch and its one-point halo are staged in LDS for the y and x
+// neighbours, the neighbours along axis d-3 (p -+ 1) stay in registers, and
+// the neighbours along axes 0..d-4 are read from memory.  Every value of u is
+// read from HBM once (plus the halo).
+constexpr int kTX = 64, kTYT = 4, kRows = 4, kTY = kTYT * kRows;
+constexpr int kLX = kTX + 2;  // LDS row length
 
-// Stencil: each thread owns one index r of the faster axes (1..d-1) and a run
-// of kMarch consecutive points along axis 0, keeping the axis-0 neighbours in
-// registers.  Faster-axis neighbours come from L1/L2.
 template <int MODE, int DOT>
-__global__ __launch_bounds__(RT) void k_stencil(StencilArgs a) {
+__global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles, int64_t ty_tiles,
+                                                int64_t p_tiles, int64_t planes) {
   if (a.skip && *a.skip) {
     if (DOT && threadIdx.x == 0 && blockIdx.x < kRedBlocks) a.partial[blockIdx.x] = 0.0;
     return;
   }
-  const int64_t n0 = a.n[0];
-  const int64_t rest = a.N / n0;  // = stride[0]
-  const int64_t chunks = (n0 + kMarch - 1) / kMarch;
-  const int64_t work = rest * chunks;
+  __shared__ double tile[kTY + 2][kLX];
+  const int d = a.d;
+  const int ax = d - 1, ay = d - 2, ap = d - 3;  // ay < 0 if d == 1, ap < 0 if d <= 2
+  const int64_t NX = a.n[ax], NY = ay >= 0 ? a.n[ay] : 1, NXY = NX * NY;
+  const int64_t P = a.N / NXY;
+  const int64_t np = ap >= 0 ? a.n[ap] : 1;  // extent of the marching axis
+  const double ihx = a.ih2[ax], ihy = ay >= 0 ? a.ih2[ay] : 0.0, ihp = ap >= 0 ? a.ih2[ap] : 0.0;
+  const int tx = threadIdx.x & (kTX - 1), ty = threadIdx.x / kTX;
+  const int64_t ntask = tx_tiles * ty_tiles * p_tiles;
+  // operand: u, or z + beta u when the PCG direction update is fused in
+  const double* __restrict__ zz = a.z;
+  const double beta = zz ? a.bsc->beta : 0.0;
+  auto ld = [&](int64_t i) -> double { return zz ? zz[i] + beta * a.u[i] : a.u[i]; };
   double dsum = 0.0;
-  for (int64_t w = blockIdx.x * (int64_t)RT + threadIdx.x; w < work; w += (int64_t)gridDim.x * RT) {
-    const int64_t r = w % rest;
-    const int64_t c = w / rest;
-    // decode r into the faster axes once: boundary flags and the f sum
-    double fsum = a.s;
-    unsigned lo_ok = 0, hi_ok = 0;  // bit k: the neighbour below / above exists on axis k
-    int64_t rem = r;
-    for (int k = a.d - 1; k >= 1; --k) {
-      const int64_t j = rem % a.n[k];
-      rem /= a.n[k];
-      fsum += a.f[k][j];
-      if (j > 0) lo_ok |= 1u << k;
-      if (j + 1 < a.n[k]) hi_ok |= 1u << k;
+  for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+    const int64_t bx = task % tx_tiles, rest = task / tx_tiles;
+    const int64_t by = rest % ty_tiles, bp = rest / ty_tiles;
+    const int64_t x = bx * kTX + tx;
+    const int64_t p0 = bp * planes, p1 = p0 + planes < P ? p0 + planes : P;
+    const bool xin = x < NX;
+    double fxy[kRows], um[kRows], uc[kRows];
+    int64_t yy[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      yy[j] = by * kTY + ty + kTYT * j;
+      const bool in = xin && yy[j] < NY;
+      fxy[j] = in ? a.f[ax][x] + (ay >= 0 ? a.f[ay][yy[j]] : 0.0) : 0.0;
+      const int64_t idx = (p0 * NY + yy[j]) * NX + x;
+      uc[j] = in ? ld(idx) : 0.0;
+      um[j] = (in && p0 > 0) ? ld(idx - NXY) : 0.0;
     }
-    const int64_t i_beg = c * kMarch;
-    const int64_t i_end = i_beg + kMarch < n0 ? i_beg + kMarch : n0;
-    double um = i_beg > 0 ? a.u[(i_beg - 1) * rest + r] : 0.0;
-    double uc = a.u[i_beg * rest + r];
-    // groups of kGroup points along axis 0: every load of a group is issued
-    // before its arithmetic (the per-point operations and their order are
-    // those of one point at a time)
-    for (int64_t i = i_beg; i < i_end; i += kGroup) {
-      const int cnt = (int)(i_end - i < kGroup ? i_end - i : kGroup);
-      double uv[kGroup + 1];  // u at axis-0 index i .. i + kGroup
-      uv[0] = uc;
-#pragma unroll
-      for (int j = 1; j <= kGroup; ++j) uv[j] = (j <= cnt && i + j < n0) ? a.u[(i + j) * rest + r] : 0.0;
-      double acc[kGroup];
-#pragma unroll
-      for (int j = 0; j < kGroup; ++j) acc[j] = a.ih2[0] * (2.0 * uv[j] - (j == 0 ? um : uv[j - 1]) - uv[j + 1]);
-      for (int k = 1; k < a.d; ++k) {
-        const int64_t st = a.stride[k];
-        const bool lk = (lo_ok >> k) & 1u, hk = (hi_ok >> k) & 1u;
-#pragma unroll
-        for (int j = 0; j < kGroup; ++j) {
-          if (j < cnt) {
-            const int64_t idx = (i + j) * rest + r;
-            const double lo = lk ? a.u[idx - st] : 0.0;
-            const double hi = hk ? a.u[idx + st] : 0.0;
-            acc[j] += a.ih2[k] * (2.0 * uv[j] - lo - hi);
-          }
+    for (int64_t p = p0; p < p1; ++p) {
+      // position of plane p on the slower axes: diagonal part and neighbours
+      const int64_t jp = ap >= 0 ? p % np : 0;
+      double fp = a.s + (ap >= 0 ? a.f[ap][jp] : 0.0);
+      unsigned lo_ok = 0, hi_ok = 0;
+      {
+        int64_t rem = ap >= 0 ? p / np : 0;
+        for (int k = ap - 1; k >= 0; --k) {
+          const int64_t j = rem % a.n[k];
+          rem /= a.n[k];
+          fp += a.f[k][j];
+          if (j > 0) lo_ok |= 1u << k;
+          if (j + 1 < a.n[k]) hi_ok |= 1u << k;
         }
       }
+      const bool has_dn = jp > 0, has_up = jp + 1 < np;
+      double up[kRows];
 #pragma unroll
-      for (int j = 0; j < kGroup; ++j) {
-        if (j < cnt) {
-          const int64_t idx = (i + j) * rest + r;
-          double diag = fsum + a.f[0][i + j] + (a.V2 ? a.V2[idx] : 0.0);
-          double v = acc[j] + diag * uv[j];
+      for (int j = 0; j < kRows; ++j) {
+        const bool in = xin && yy[j] < NY;
+        up[j] = (in && has_up) ? ld(((p + 1) * NY + yy[j]) * NX + x) : 0.0;
+        tile[ty + kTYT * j + 1][tx + 1] = uc[j];
+      }
+      // halo of plane p: rows y0 - 1 and y0 + kTY, columns x0 - 1 and x0 + kTX
+      {
+        const int64_t y0 = by * kTY, x0 = bx * kTX;
+        const int64_t pb = p * NXY;
+        if (ty < 2) {
+          const int64_t yh = ty == 0 ? y0 - 1 : y0 + kTY;
+          const bool in = xin && yh >= 0 && yh < NY;
+          tile[ty == 0 ? 0 : kTY + 1][tx + 1] = in ? ld(pb + yh * NX + x) : 0.0;
+        } else if (tx < kTY) {
+          const int64_t xh = ty == 2 ? x0 - 1 : x0 + kTX, yh = y0 + tx;
+          const bool in = xh >= 0 && xh < NX && yh < NY;
+          tile[tx + 1][ty == 2 ? 0 : kLX - 1] = in ? ld(pb + yh * NX + xh) : 0.0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const int ly = ty + kTYT * j + 1;
+        const bool in = xin && yy[j] < NY;
+        if (in) {
+          const int64_t idx = (p * NY + yy[j]) * NX + x;
+          const double u0 = uc[j];
+          double acc = 0.0;
+          // axes 0 .. d-4 from memory, then the marching axis, then y and x (axis order)
+          for (int k = 0; k < ap; ++k) {
+            const int64_t st = a.stride[k];
+            const double lo = ((lo_ok >> k) & 1u) ? ld(idx - st) : 0.0;
+            const double hi = ((hi_ok >> k) & 1u) ? ld(idx + st) : 0.0;
+            acc += a.ih2[k] * (2.0 * u0 - lo - hi);
+          }
+          if (ap >= 0) acc += ihp * (2.0 * u0 - (has_dn ? um[j] : 0.0) - up[j]);
+          if (ay >= 0) acc += ihy * (2.0 * u0 - tile[ly - 1][tx + 1] - tile[ly + 1][tx + 1]);
+          acc += ihx * (2.0 * u0 - tile[ly][tx] - tile[ly][tx + 2]);
+          const double diag = fp + fxy[j] + (a.V2 ? a.V2[idx] : 0.0);
+          double v = acc + diag * u0;
           if (MODE == (int)StOut::FminusAx) v = a.rhs[idx] - v;
           a.out[idx] = v;
-          if (DOT == (int)StDot::UdotOut) dsum += uv[j] * v;
+          if (zz) a.unew[idx] = u0;
+          if (DOT == (int)StDot::UdotOut) dsum += u0 * v;
           if (DOT == (int)StDot::OutdotOut) dsum += v * v;
         }
+        um[j] = uc[j];
+        uc[j] = up[j];
       }
-      um = uv[cnt - 1];
-      uc = uv[cnt];
+      __syncthreads();
     }
   }
   if (DOT) {
-    double s = block_sum(dsum);
-    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+    double sm = block_sum(dsum);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = sm;
   }
 }
 
@@ -371,6 +413,7 @@ static hipError_t launch_dense_operator(const StencilArgs& a, hipStream_t st) {
 
 hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
   if (a.N <= 0) return hipSuccess;
+  if (a.z && (a.dense[0] || a.bw > 0 || !a.bsc || !a.unew || a.unew == a.u)) return hipErrorInvalidValue;
   if (a.dense[0]) return launch_dense_operator(a, st);
   if (a.bw > 0) {
     const unsigned g = a.dot != StDot::None ? kRedBlocks
@@ -382,13 +425,23 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
 #undef TS_BD
     return hipErrorInvalidValue;
   }
-  const int64_t work = (a.N / a.n[0]) * ((a.n[0] + kMarch - 1) / kMarch);
+  const int64_t NX = a.n[a.d - 1], NY = a.d >= 2 ? a.n[a.d - 2] : 1;
+  const int64_t P = a.N / (NX * NY);
+  const int64_t txt = (NX + kTX - 1) / kTX, tyt = (NY + kTY - 1) / kTY;
+  // planes per task: long marches (fewer halo and first-plane loads), but at
+  // least ~2048 tasks when the grid allows
+  const int64_t planes = std::max<int64_t>(1, std::min<int64_t>(32, P * txt * tyt / 2048));
+  const int64_t pt = (P + planes - 1) / planes;
+  const int64_t ntask = txt * tyt * pt;
   unsigned grid;
-  if (a.dot != StDot::None) grid = kRedBlocks;
-  else grid = (unsigned)std::min<int64_t>((work + RT - 1) / RT, 1 << 20);
+  if (a.dot != StDot::None) grid = kRedBlocks;  // one partial per block, every slot written
+  else grid = (unsigned)std::min<int64_t>(ntask, 1 << 20);
   const int m = (int)a.mode, dt = (int)a.dot;
 #define TS_ST(M, D) \
-  if (m == M && dt == D) { hipLaunchKernelGGL((k_stencil<M, D>), dim3(grid), dim3(RT), 0, st, a); return hipGetLastError(); }
+  if (m == M && dt == D) {                                                                            \
+    hipLaunchKernelGGL((k_stencil<M, D>), dim3(grid), dim3(RT), 0, st, a, txt, tyt, pt, planes);       \
+    return hipGetLastError();                                                                         \
+  }
   TS_ST(0, 0) TS_ST(0, 1) TS_ST(0, 2) TS_ST(1, 0) TS_ST(1, 1) TS_ST(1, 2)
 #undef TS_ST
   return hipErrorInvalidValue;

@@ -32,6 +32,13 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def maxrel(a, b):
+    """max|a - b| / max|b|: the elementwise companion of rel()."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def to_dev(x, dtype=None):
     t = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
     return t if dtype is None else t.to(dtype)

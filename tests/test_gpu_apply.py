@@ -14,7 +14,7 @@ import torch
 import oracle
 import paper_2605_20491_amd as ts
 import workloads as W
-from gpu_common import announce, exp_tol, inv_tol, make_pair, rel, to_dev, to_host
+from gpu_common import DEV, announce, exp_tol, inv_tol, make_pair, maxrel, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,9 @@ def test_inverse_fp64_parity(shape):
     b = W.rhs_normal(shape, 1)
     u = to_host(ts.ts_apply_inverse(plan, to_dev(b)))
     ref = oracle.apply_inverse(oplan, b, 1.0)
-    e = rel(u, ref)
-    announce("  rel err %.3e" % e)
-    assert e <= 1e-12
+    e, em = rel(u, ref), maxrel(u, ref)
+    announce("  rel err %.3e, max-norm rel err %.3e" % (e, em))
+    assert e <= 1e-12 and em <= 1e-12
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -51,10 +51,10 @@ def test_exp_fp64_parity(shape, tau):
     psi = W.complex_normal(shape, 2)
     out = to_host(ts.ts_apply_exp(plan, tau, to_dev(psi)))
     ref = oracle.apply_exp(oplan, psi, tau)
-    e = rel(out, ref)
+    e, em = rel(out, ref), maxrel(out, ref)
     tol = exp_tol(oplan, tau)
-    announce("  rel err %.3e (tol %.1e)" % (e, tol))
-    assert e <= tol
+    announce("  rel err %.3e, max-norm rel err %.3e (tol %.1e)" % (e, em, tol))
+    assert e <= tol and em <= tol
 
 
 def test_config0_workload_inverse_and_exp():
@@ -148,16 +148,18 @@ def test_bf16_transforms_error_reported(shape):
     ref = oracle.apply_inverse(oplan, b, 1.0)
     for dt in (torch.float64, torch.float32):
         u = to_host(ts.ts_apply_inverse(plan, to_dev(b).to(dt), prec="bf16")).astype(np.float64)
-        e = rel(u, ref)
-        announce("bf16 inverse %s in=%s rel err %.3e" % (shape, dt, e))
-        assert 1e-5 < e <= 4e-2
+        e, em = rel(u, ref), maxrel(u, ref)
+        announce("bf16 inverse %s in=%s rel err %.3e, max-norm %.3e" % (shape, dt, e, em))
+        # measured 4.8e-3 .. 7.2e-3: BF16 operands through 2d passes; the max-norm bar
+        # catches a few corrupted outputs that the 2-norm would average away
+        assert 1e-3 < e <= 1.5e-2 and em <= 5e-2
     psi = W.complex_normal(shape, 8)
     refp = oracle.apply_exp(oplan, psi, 0.01)
     for dt in (torch.complex128, torch.complex64):
         out = to_host(ts.ts_apply_exp(plan, 0.01, to_dev(psi).to(dt), prec="bf16")).astype(np.complex128)
-        e = rel(out, refp)
-        announce("bf16 exp %s in=%s rel err %.3e" % (shape, dt, e))
-        assert 1e-5 < e <= 4e-2
+        e, em = rel(out, refp), maxrel(out, refp)
+        announce("bf16 exp %s in=%s rel err %.3e, max-norm %.3e" % (shape, dt, e, em))
+        assert 1e-3 < e <= 1.5e-2 and em <= 5e-2
 
 
 @pytest.mark.parametrize("shape", [(100, 99, 128), (99, 101, 7), (64, 96)])
@@ -177,11 +179,56 @@ def test_bf16_input_rounding_sweep_and_in_place(shape):
     u_in = to_host(bd)
     e_out, e_in, e_pair = rel(u_out, ref), rel(u_in, ref), rel(u_out, u_in)
     announce("bf16 inverse %s: out of place %.3e, in place %.3e, between %.3e" % (shape, e_out, e_in, e_pair))
-    assert e_out <= 4e-2 and e_in <= 4e-2
+    assert e_out <= 1.5e-2 and e_in <= 1.5e-2
     assert np.array_equal(u_out, u_in)
     psi = W.complex_normal(shape, 10)
     refp = oracle.apply_exp(oplan, psi, 0.01)
     pd = to_dev(psi)
     o = to_host(ts.ts_apply_exp(plan, 0.01, pd, prec="bf16"))
     assert np.array_equal(to_host(pd), psi)
-    assert rel(o, refp) <= 4e-2
+    assert rel(o, refp) <= 1.5e-2
+
+
+@pytest.mark.parametrize("n", [100, 257, 1000])
+def test_bf16_factor_copies_are_rne_of_fp64(n):
+    """The BF16 factor copies are FP64 Q rounded once to nearest even: a BF16
+    pass over the identity (FP32 data, FP32 accumulation of one product)
+    returns the BF16 factor entries exactly, which must equal the host
+    rounding of ts_eigvecs bit for bit (route 0 of ts_bf16_round, itself
+    checked against exact RNE on the CPU)."""
+    rng = np.random.default_rng(n)
+    f = [rng.uniform(0.0, 3.0, n), rng.uniform(0.0, 3.0, n)]   # not symmetric: natural order, no fold
+    plan = ts.ts_setup((n, n), 4.0, f, 1.0)
+    assert ts.ts_fold_axes(plan) == 0
+    eye = torch.eye(n, dtype=torch.float32, device=DEV)
+    for axis in (0, 1):
+        Q = ts.ts_eigvecs(plan, axis)
+        want = ts.ts_bf16_round(Q, 0).reshape(n, n)
+        for forward in (True, False):
+            y = to_host(ts.ts_mode_pass(plan, axis, forward, eye, prec="bf16"))
+            # axis 0: forward gives Q^T, backward Q; axis 1: forward Q, backward Q^T
+            transposed = (axis == 0) == forward
+            got = (y.T if transposed else y).copy().view(np.uint32) >> 16
+            assert np.all((y.view(np.uint32) & 0xffff) == 0)
+            bad = int(np.count_nonzero(got.astype(np.uint16) != want))
+            announce("bf16 factor copy n=%d axis %d forward %s: %d of %d entries differ" % (n, axis, forward, bad, n * n))
+            assert bad == 0
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (130, 70, 150), (20, 17, 24, 19), (12, 10, 11, 9, 8, 7)])
+def test_fp32_data_fp64_transforms(shape):
+    """FP32 / complex64 data with FP64 transforms (FP64 factors and arithmetic
+    inside each pass, FP32 between passes): the error against the oracle is
+    the FP32 rounding of the data (a few 1e-8 per pass), well below the FP32
+    transforms' error."""
+    plan, oplan, _ = make_pair(shape, 8.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 7)
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    u = to_host(ts.ts_apply_inverse(plan, to_dev(b).float(), prec="fp64")).astype(np.float64)
+    e = rel(u, ref)
+    psi = W.complex_normal(shape, 8)
+    refp = oracle.apply_exp(oplan, psi, 0.01)
+    out = to_host(ts.ts_apply_exp(plan, 0.01, to_dev(psi).to(torch.complex64), prec="fp64")).astype(np.complex128)
+    ep = rel(out, refp)
+    announce("fp32 data, fp64 transforms %s: inverse %.2e, exp %.2e" % (shape, e, ep))
+    assert e <= 5e-7 and ep <= 5e-7

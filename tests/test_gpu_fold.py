@@ -51,7 +51,7 @@ def test_fold_matches_plain_and_oracle(shape):
     assert e32 <= 2e-6 and e64c <= 2e-6
     # (the two variants round different quantities, so their errors are two samples
     # of the BF16 rounding noise; in 1D a few low modes dominate and the ratio varies)
-    assert max(e16 + e16c) <= 3e-2
+    assert max(e16 + e16c) <= 1.5e-2   # measured 2.9e-3 .. 7.5e-3
 
 
 def test_non_symmetric_axes_are_not_folded():
@@ -88,7 +88,7 @@ def test_fold_in_solvers_and_sem():
     b = W.rhs_normal(sp.shape, 7)
     assert rel(to_host(ts.ts_apply_inverse(sp, to_dev(b))), oracle.apply_inverse(osp, b, 1.0)) <= 1e-12
     u16 = to_host(ts.ts_apply_inverse(sp, to_dev(b).float(), prec="bf16")).astype(np.float64)
-    assert rel(u16, oracle.apply_inverse(osp, b, 1.0)) <= 3e-2
+    assert rel(u16, oracle.apply_inverse(osp, b, 1.0)) <= 1.5e-2
 
 
 @pytest.mark.parametrize("shape", [(100, 99, 130), (70, 81)])
@@ -124,7 +124,7 @@ def test_single_pass_bf16_fold(shape):
             ts.ts_set_fold(plan, True)
             announce("bf16 pass %s axis %d %s: fold %.2e plain %.2e"
                      % (shape, axis, "fwd" if fwd else "bwd", errs[0], errs[1]))
-            assert max(errs) <= 1e-2
+            assert max(errs) <= 5e-3   # measured 2.2e-3 .. 2.4e-3
 
 
 def _butterfly_ref(x, axes):
@@ -227,3 +227,28 @@ def test_five_folded_axes_two_sweeps():
     res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
     announce("64^5 fold vs plain %.2e, relative residual %.2e" % (e, res))
     assert e <= 1e-13 and res <= 1e-12
+
+
+@pytest.mark.parametrize("rel_pert,folds", [(2.0e-16, True), (5.0e-14, False)])
+def test_nearly_symmetric_f(rel_pert, folds):
+    """f perturbed on one side: within a few ulps the axis still folds (the
+    solver averages the mirrored pair); at 5e-14 relative it takes the plain
+    path.  Either way the result matches the oracle, which uses the samples as
+    given, to the FP64 bar (the 1e9-DoF potential f = x^2 + 0.5 cos 2x on
+    [-10, 10] has max|f| ~ 100)."""
+    n, L = 200, 10.0
+    f0 = W.f_harmonic_cos(n, L)
+    fmax = np.abs(f0).max()
+    f1 = f0.copy()
+    f1[: n // 2] += rel_pert * fmax * np.linspace(0.2, 1.0, n // 2)
+    shape = (n, 96)
+    fs = [f1, W.f_harmonic_cos(96, L)]
+    plan = ts.ts_setup(shape, L, fs, 1.0)
+    assert bool(ts.ts_fold_axes(plan) & 1) == folds
+    oplan = oracle.make_plan(shape, L, fs)
+    b = W.rhs_normal(shape, 12)
+    e = rel(to_host(ts.ts_apply_inverse(plan, to_dev(b))), oracle.apply_inverse(oplan, b, 1.0))
+    psi = W.complex_normal(shape, 13)
+    ep = rel(to_host(ts.ts_apply_exp(plan, 0.01, to_dev(psi))), oracle.apply_exp(oplan, psi, 0.01))
+    announce("near-symmetric f (%.0e): folds %s, inverse %.2e, exp %.2e" % (rel_pert, folds, e, ep))
+    assert e <= 1e-12 and ep <= exp_tol(oplan, 0.01)

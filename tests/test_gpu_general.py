@@ -62,7 +62,7 @@ def test_hermite_applies_match_oracle(shape):
              % (shape, e_inv, e_sh, e_exp, exp_tol(oplan, tau), e32, e16))
     assert e_inv <= 1e-12 and e_sh <= 1e-12
     assert e_exp <= exp_tol(oplan, tau)
-    assert e32 <= 2e-5 and e16 <= 3e-2
+    assert e32 <= 2e-5 and e16 <= 1.5e-2   # BF16 measured 3.3e-3 .. 4.6e-3
 
 
 def test_generic_fd_operator_matches_fd_oracle():

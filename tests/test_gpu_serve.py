@@ -79,8 +79,8 @@ def _alone(r, x, V2):
     return ts.ts_apply_exp(plan, r["tau"], x, prec=r["prec"])
 
 
-def _run_server(reqs, budget, n_streams, max_active):
-    srv = ts.Server(budget, n_streams, max_active)
+def _run_server(reqs, budget, n_streams, max_active, plan_reserve=0):
+    srv = ts.Server(budget, n_streams, max_active, plan_reserve)
     tickets, outs, ins = [], [], []
     for i, r in enumerate(reqs):
         x, V2 = _device_inputs(r)
@@ -122,8 +122,9 @@ def test_mix_matches_requests_alone_bitwise():
 
 def test_admission_by_memory_and_fifo():
     reqs = _requests(seed=1)[:12]
-    # the largest of these requests needs ~2.2 MB of scratch; a 3 MB arena holds one to three at once
-    results, outs, _ = _run_server(reqs, 3 << 20, 3, 0)
+    # the largest of these requests needs ~3 MB of scratch; a 4 MB arena holds one to three at once
+    # (the other 20 MB of the budget hold the twelve plans)
+    results, outs, _ = _run_server(reqs, 24 << 20, 3, 0, plan_reserve=20 << 20)
     assert all(r is not None and r.status == ts.TS_OK for r in results)
     admits = sorted(r.t_admit for r in results)
     dones = sorted(r.t_done for r in results)
@@ -138,10 +139,65 @@ def test_admission_by_memory_and_fifo():
 
 
 def test_oversized_request_rejected():
-    srv = ts.Server(1 << 20, 2, 0)
+    srv = ts.Server(2 << 20, 2, 0, plan_reserve=1 << 20)
     shape, L = (64, 64, 64), 6.0
     x = torch.zeros(shape, dtype=torch.float64, device=DEV)
     with pytest.raises(ts.TSError) as e:
         srv.submit(ts.TS_REQ_INVERSE, shape, L, [W.f_harmonic(64, L)] * 3, 1.0, x, torch.empty_like(x))
     assert e.value.code == ts.TS_ERR_NOMEM
+    srv.close()
+
+
+def test_plan_cache_within_reserve_and_busy():
+    """Plans are keyed without the shift (one cached plan serves requests of
+    different sigma); the plan reserve is honoured by evicting plans that no
+    request uses, and a submit whose plan cannot fit while running requests
+    hold the others returns TS_ERR_BUSY."""
+    L = 6.0
+    shapes = [(40, 36, 44), (44, 40, 36), (36, 44, 40)]   # three distinct axes each: ~1.4 MB of factors
+    srv = ts.Server(64 << 20, 2, 0, plan_reserve=3 << 20)
+    outs, refs = [], []
+    for i, shape in enumerate(shapes[:2]):
+        f = [W.f_harmonic(n, L) for n in shape]
+        for sigma in (1.0, 2.5):
+            x = to_dev(W.rhs_normal(shape, 30 + i))
+            out = torch.empty_like(x)
+            srv.submit(ts.TS_REQ_INVERSE, shape, L, f, sigma, x, out)
+            outs.append(out)
+            refs.append((shape, f, sigma, x))
+    srv.drain()
+    for out, (shape, f, sigma, x) in zip(outs, refs):
+        alone = ts.ts_apply_inverse(ts.ts_setup(shape, L, f, sigma), x)
+        torch.cuda.synchronize()
+        assert torch.equal(out, alone)
+    # two plans resident (~2.8 MB); a third evicts the least recently used idle one
+    shape = shapes[2]
+    f = [W.f_harmonic(n, L) for n in shape]
+    x = to_dev(W.rhs_normal(shape, 40))
+    out = torch.empty_like(x)
+    srv.submit(ts.TS_REQ_INVERSE, shape, L, f, 1.0, x, out)
+    srv.drain()
+    srv.close()
+    # a reserve that holds one 256^3 plan (~2.9 MB with its half factors) but not
+    # that and a 1.4 MB plan: a submit made while a long 256^3 PCG holds its plan
+    # is told to come back later, and succeeds once that request has finished
+    srv = ts.Server(2 << 30, 2, 0, plan_reserve=3 << 20)
+    big = (256, 256, 256)
+    fb = [W.f_harmonic(n, L) for n in big]
+    V2b = torch.from_numpy(W.gaussian_bumps(big, L, 8, seed=5)).to(DEV).abs()
+    xb = torch.randn(big, dtype=torch.float64, device=DEV)
+    ob = torch.empty_like(xb)
+    srv.submit(ts.TS_REQ_INVERSE, big, L, fb, 1.0, xb, ob, V2=V2b, rtol=1e-12, maxit=500)
+    shape = shapes[0]
+    f = [W.f_harmonic(n, L) for n in shape]
+    x = to_dev(W.rhs_normal(shape, 41))
+    out = torch.empty_like(x)
+    with pytest.raises(ts.TSError) as e:
+        srv.submit(ts.TS_REQ_INVERSE, shape, L, f, 1.0, x, out)
+    assert e.value.code == ts.TS_ERR_BUSY
+    srv.drain()
+    srv.submit(ts.TS_REQ_INVERSE, shape, L, f, 1.0, x, out)
+    srv.drain()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ts.ts_apply_inverse(ts.ts_setup(shape, L, f, 1.0), x))
     srv.close()

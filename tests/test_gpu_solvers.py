@@ -58,9 +58,12 @@ def test_pcg_bumps_matches_oracle(precond):
     assert it <= ref.iters + 3
 
 
-def test_pcg_config2_n256_fp64_vs_mixed():
-    """3D n = 256, V1 = sum x^2 on [-8,8]^3, 16 bumps (seed 3), f ~ N(0,1): rtol 1e-10."""
-    n, L = 256, 8.0
+@pytest.mark.parametrize("n", [256, 512])
+def test_pcg_config2_fp64_vs_mixed(n):
+    """3D n = 256 and 512, V1 = sum x^2 on [-8,8]^3, 16 bumps (seed 3), f ~ N(0,1):
+    rtol 1e-10 with the FP64, FP32 and BF16 preconditioners; the true residual
+    of each result is recomputed on the host by the oracle's stencil."""
+    L = 8.0
     shape = (n, n, n)
     f_list = [W.f_harmonic(n, L) for _ in range(3)]
     V2 = W.gaussian_bumps(shape, L, 16, seed=3)
@@ -73,15 +76,19 @@ def test_pcg_config2_n256_fp64_vs_mixed():
     f = W.rhs_normal(shape, 3)
     fd, V2d = to_dev(f), to_dev(V2)
     sols = {}
-    for pc in ("fp64", "fp32"):
+    for pc in ("fp64", "fp32", "bf16"):
         u, it, rr, _ = ts.ts_pcg_solve(plan, V2d, fd, rtol=1e-10, precond=pc)
         uh = to_host(u)
+        del u
         true = np.linalg.norm(f - oracle.stencil_apply(oplan, uh, V2, sigma)) / np.linalg.norm(f)
-        announce("n=256 pcg %s: iters %d relres %.2e oracle-stencil %.2e" % (pc, it, rr, true))
+        err = rel(uh, sols["fp64"][0]) if sols else 0.0
+        announce("n=%d pcg %s: iters %d relres %.2e oracle-stencil %.2e, vs the FP64-preconditioned solution %.2e"
+                 % (n, pc, it, rr, true, err))
         assert true <= 1.05e-10
         sols[pc] = (uh, it)
-    assert rel(sols["fp32"][0], sols["fp64"][0]) <= 1e-8
-    assert abs(sols["fp32"][1] - sols["fp64"][1]) <= 3
+    for pc in ("fp32", "bf16"):
+        assert rel(sols[pc][0], sols["fp64"][0]) <= 1e-8
+        assert abs(sols[pc][1] - sols["fp64"][1]) <= 3
 
 
 @pytest.mark.parametrize("shape", [(64, 64, 64), (100, 90, 80)])

@@ -138,6 +138,52 @@ def test_split_workload_full_size(d, n):
         announce("  %s: norm drift c128 %.1e (bar %.1e) c64 %.1e (bar %.1e); c64 vs c128 %.2e"
                  % (scheme, drift128, bar128, drift64, bar64, e))
         assert drift128 <= bar128 and drift64 <= bar64 and e <= bar64
+        # complex64 data with FP64 transforms (the paper's complex64 runs): FP64 factors and
+        # arithmetic inside each pass, state rounded to FP32 between HBM passes (unbiased, so
+        # the error grows as the square root of the pass count and the norm does not drift)
+        t64 = to_dev(psi0).to(torch.complex64)
+        ts.ts_split_step(plan, to_dev(V2).to(torch.float32), t64, dt, steps, scheme, prec="fp64")
+        b = to_host(t64).astype(np.complex128)
+        drift64d = abs(np.linalg.norm(b) - 1)
+        e64d = rel(b, a)
+        announce("  %s complex64 / FP64 transforms: norm drift %.1e, vs c128 %.2e" % (scheme, drift64d, e64d))
+        assert drift64d <= 1e-6 and e64d <= 3e-6
         res[scheme] = a
     # Strang and Yoshida agree to the splitting error (order dt^2 T ||[A,B]||, small here)
     assert rel(res["strang_bab"], res["yoshida_bab"]) <= 1e-4
+
+
+@pytest.mark.parametrize("d,n", [(6, 24), (9, 8)])
+def test_split_workload_full_size_reversal_and_constant_v2(d, n):
+    """The splitting workload at full size, checks that need no oracle run:
+    Strang and Yoshida are symmetric compositions, so 100 steps of dt followed
+    by 100 steps of -dt return psi0 up to rounding; a constant V2 = c makes the
+    result the exact propagator times the global phase e^{-i c T}."""
+    L, dt, steps = 6.0, 1e-3, 100
+    shape = (n,) * d
+    f = [W.f_harmonic(n, L) for _ in range(d)]
+    plan = ts.ts_setup(shape, L, f, 1.0)
+    w, Q = oracle.jacobi_eigh(oracle.fd_axis_matrix(n, L, f[0]))
+    terms = W.superposition_terms([Q] * d, [w] * d, 4, seed=4)
+    psi0 = W.superposition_grid([Q] * d, terms)
+    V2 = to_dev(W.pairwise_v2(shape, L))
+    for scheme in ("strang_bab", "yoshida_bab"):
+        t = to_dev(psi0)
+        ts.ts_split_step(plan, V2, t, dt, steps, scheme)
+        ts.ts_split_step(plan, V2, t, -dt, steps, scheme)
+        e = rel(to_host(t), psi0)
+        n_apply = 2 * (301 if scheme.startswith("yoshida") else 101)
+        bar = max(1e-12, 1e-15 * 2 * d * n_apply)
+        announce("split %dD n=%d %s: forward then backward, |psi - psi0| / |psi0| = %.2e (bar %.1e)"
+                 % (d, n, scheme, e, bar))
+        assert e <= bar
+        del t
+    T, c = dt * steps, 0.7
+    exact = sum(cm * np.exp(-1j * T * (c + sum(w[j] for j in idx))) * W.outer([Q[:, j] for j in idx])
+                for cm, idx in terms)
+    for scheme in ("strang_bab", "yoshida_bab"):
+        t = to_dev(psi0)
+        ts.ts_split_step(plan, torch.full(shape, c, dtype=torch.float64, device=DEV), t, dt, steps, scheme)
+        e = rel(to_host(t), exact)
+        announce("  constant V2 = %.1f, %s: vs e^{-icT} times the closed form %.2e" % (c, scheme, e))
+        assert e <= 1e-12

@@ -193,3 +193,23 @@ def superposition_grid(Qs, terms) -> np.ndarray:
         t = cm * outer([Qs[k][:, j] for k, j in enumerate(idx)])
         out = t if out is None else out + t
     return out
+
+
+# The serving mix: seeded Poisson arrivals over the request classes.
+SERVE_SHAPES = [(2048, 2048), (128, 128, 128), (256, 256, 256), (512, 512, 512), (64,) * 4, (16,) * 6]
+SERVE_KINDS = ["inverse_fp64", "inverse_mixed", "exp_c64"]
+
+
+def serve_stream(seed: int, count: int, rate: float):
+    """Requests with Poisson arrival times at `rate` per second; each draws a
+    shape and a kind uniformly, V2 present with probability 1/2 and
+    tau ~ U[1e-3, 1e-1] (used by the propagator kinds)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for _ in range(count):
+        t += rng.exponential(1.0 / rate)
+        reqs.append({"t": t, "shape": SERVE_SHAPES[rng.integers(len(SERVE_SHAPES))],
+                     "kind": SERVE_KINDS[rng.integers(len(SERVE_KINDS))], "v2": bool(rng.integers(2)),
+                     "tau": float(rng.uniform(1e-3, 1e-1))})
+    return reqs
