@@ -716,7 +716,7 @@ def cpu_baseline(n, depth):
                       "O(N) diagonal scaling is not timed" % (depth, n, n, depth, n, depth, n, n)}
 
 
-SECTIONS = ["headline", "variants", "small64", "pcg", "split", "qhop", "table", "hermite", "gpe", "serve", "cpu"]
+SECTIONS = ["headline", "variants", "bf16", "small64", "pcg", "split", "qhop", "table", "hermite", "gpe", "serve", "cpu"]
 
 
 def apply_rooflines(N, n, d, t_ms, prec, flops_exec=None):
@@ -871,6 +871,21 @@ def variants_section(ts, W, torch, dev, args, st):
     return extra
 
 
+def bf16_section(ts, W, torch, dev, args):
+    """The BF16 inverse apply of the 1e9-DoF workload alone (for counter runs):
+    setup, then `steps` timed applies of FP64 data with BF16 transforms."""
+    n, L = args.n, 10.0
+    shape = (n, n, n)
+    plan = ts.ts_setup(shape, L, [W.f_harmonic_cos(n, L) for _ in range(3)], 1.0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(2)
+    b = torch.randn(shape, dtype=torch.float64, device=dev, generator=gen)
+    u = torch.empty_like(b)
+    ms, _ = timed(lambda: ts.ts_apply_inverse(plan, b, u, prec="bf16"), args.steps, 1)
+    log("bf16 inverse %.2f ms/apply" % ms)
+    return {"inverse_bf16_ms": ms, "roofline": apply_rooflines(n ** 3, n, 3, ms, "bf16")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -947,6 +962,9 @@ def main():
         if "variants" in run:
             extra.update(variants_section(ts, W, torch, dev, args, st))
         del st
+        torch.cuda.empty_cache()
+    if "bf16" in run and args.only:
+        extra["bf16_only"] = bf16_section(ts, W, torch, dev, args)
         torch.cuda.empty_cache()
     if "small64" in run:
         extra["small_64"] = small_section(ts, W, torch, dev)

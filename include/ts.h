@@ -2,11 +2,17 @@
  * ts.h -- C ABI of the MI355X separable tensor-product solver for the
  * Schroedinger operator H = -Delta + V1 (+ V2), V1(x) = sum_k f_k(x_k).
  *
- * Discretisation (paper Sec. 2.1, eq. (general_system), eq. (tensor_system)):
- * second-order finite differences (the Q^1 case) on n_k interior nodes of
- * [-L, L] per axis, x_{k,j} = -L + j h_k, h_k = 2L/(n_k+1), homogeneous
- * Dirichlet.  Per axis H_k = h_k^-2 tridiag(-1, 2, -1) + diag(f_k(x_{k,j})),
- * and H1 = sum_k I (x) ... (x) H_k (x) ... (x) I (the Kronecker sum).
+ * Discretisations (paper Sec. 2, Sec. 2.1, eq. (general_system), eq. (tensor_system)),
+ * each giving per-axis operators H_k and H1 = sum_k I (x) ... (x) H_k (x) ... (x) I
+ * (the Kronecker sum):
+ *  - ts_setup: second-order finite differences (the Q^1 case) on n_k interior
+ *    nodes of [-L, L], x_{k,j} = -L + j h_k, h_k = 2L/(n_k+1), homogeneous
+ *    Dirichlet; H_k = h_k^-2 tridiag(-1, 2, -1) + diag(f_k(x_{k,j}));
+ *  - ts_setup_sem: Q^k spectral elements with Gauss-Lobatto nodes and lumped
+ *    mass, H_k = M_k^-1 S_k + diag(f_k);
+ *  - ts_setup_general: any per-axis operator K_k self-adjoint in weights m_k
+ *    (Hermite collocation on R from ts_hermite_axis is one such input).
+ * The applies, solvers and splitting schemes below work on any of them.
  *
  * Data layout: a grid function is a C-contiguous array of shape
  * (n_0, ..., n_{d-1}); axis d-1 is the fastest index (the paper's x).

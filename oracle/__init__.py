@@ -36,14 +36,27 @@ os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "_oracle.so")
+# ORACLE_LIBRARY selects another build of the C part (a sanitizer build)
+_LIB = os.environ.get("ORACLE_LIBRARY") or os.path.join(_HERE, "_oracle.so")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 
 
+def build_sanitized(out: str) -> str:
+    """oracle.c with the address and undefined-behaviour sanitizers (ROCm's
+    clang, serial, -O1), for the host sanitizer test."""
+    clang = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang")
+    subprocess.check_call([clang, "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-fPIC", "-shared", "-std=c11", "-o", out, _SRC,
+                           "-lm"])
+    return out
+
+
 def build(force: bool = False) -> str:
     """Compile oracle.c with gcc (-O2, OpenMP, no fast-math)."""
+    if "ORACLE_LIBRARY" in os.environ:
+        return _LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libts.so")
+# TS_LIBRARY selects another build of the library (for instance a copy whose
+# host code is compiled with the address and undefined-behaviour sanitizers)
+LIB_PATH = os.environ.get("TS_LIBRARY") or os.path.join(_HERE, "libts.so")
 
 TS_OK, TS_ERR_INVALID, TS_ERR_NOT_SPD, TS_ERR_NOMEM, TS_ERR_DEVICE = 0, 1, 2, 3, 4
 TS_ERR_NOCONV, TS_ERR_NONFINITE, TS_ERR_BUSY, TS_ERR_BREAKDOWN = 5, 6, 7, 8

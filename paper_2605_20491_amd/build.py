@@ -53,6 +53,38 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(outdir: str, verbose: bool = False) -> str:
+    """A copy of libts.so whose host code (every .cpp source) is compiled with
+    the address and undefined-behaviour sanitizers; device code and the .hip
+    sources are the regular objects (GPU sanitizers are not used).  Needs the
+    regular objects of build() in _build/."""
+    os.makedirs(outdir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+    def one(src):
+        if not src.endswith(".cpp"):
+            return os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
+        obj = os.path.join(outdir, src.rsplit(".", 1)[0] + ".o")
+        cmd = [HIPCC] + FLAGS + san + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc (sanitized) failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(one, SOURCES))
+    lib = os.path.join(outdir, "libts.so")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", lib] + objs + ["-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n%s\n%s" % (r.stdout, r.stderr))
+    if verbose:
+        print("built", lib)
+    return lib
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

@@ -27,7 +27,42 @@ template <typename T> __device__ __forceinline__ void sincos_t(T x, T* s, T* c);
 template <> __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) { sincos(x, s, c); }
 template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename TIO, typename TC, int MT, bool CPLX>
+// VW consecutive values of one tile row move together: one 16-byte access
+// when the rows allow it (VEC), else VW single accesses (VW = 2 keeps the two
+// parts of a complex value together).  Row r of the tile [PB][G][RT] starts at
+// global offset (p0 G + r) R + r0.
+template <typename TIO> struct Vec16;
+template <> struct Vec16<double> { using V = double2; };
+template <> struct Vec16<float> { using V = float4; };
+
+template <typename TIO, int VW, bool VEC>
+__device__ __forceinline__ void vload(const TIO* p, TIO (&v)[VW]) {
+  if constexpr (VEC) {
+    static_assert(VW * sizeof(TIO) == 16, "16-byte chunks");
+    const typename Vec16<TIO>::V w = *(const typename Vec16<TIO>::V*)p;
+    const TIO* e = (const TIO*)&w;
+#pragma unroll
+    for (int m = 0; m < VW; ++m) v[m] = e[m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < VW; ++m) v[m] = p[m];
+  }
+}
+template <typename TIO, int VW, bool VEC>
+__device__ __forceinline__ void vstore(TIO* p, const TIO (&v)[VW]) {
+  if constexpr (VEC) {
+    typename Vec16<TIO>::V w;
+    TIO* e = (TIO*)&w;
+#pragma unroll
+    for (int m = 0; m < VW; ++m) e[m] = v[m];
+    *(typename Vec16<TIO>::V*)p = w;
+  } else {
+#pragma unroll
+    for (int m = 0; m < VW; ++m) p[m] = v[m];
+  }
+}
+
+template <typename TIO, typename TC, int MT, bool CPLX, int VW, bool VEC>
 __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
   if (a.skip && *a.skip) return;
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -43,37 +78,37 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
   const int rt = (int)(a.R - r0 < a.RT ? a.R - r0 : a.RT);
   const int G = a.G, RT = a.RT;
   const int elems = a.PB * G * RT;
+  const int rows = a.PB * G, live_rows = pb * G;
+  const int cpr = RT / VW, cpr_sh = a.cpr_shift;  // chunks of VW values per row (shift if a power of 2)
+  const int nchunks = rows * cpr;
+  const int64_t gbase = p0 * (int64_t)G * a.R + r0;
   const TIO* Xin = (const TIO*)a.Xin;
   TIO* Xout = (TIO*)a.Xout;
   const TIO* V2 = (const TIO*)a.V2;
 
   // ---- load (optionally multiplied by e^{-i th_pre V2}); padding rows/columns are zero ----
-  if (CPLX) {
-    for (int e = 2 * t; e < elems; e += 2 * GT) {
-      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
-      TC re = 0, im = 0;
-      if (pl < pb && rl < rt) {
-        const int64_t gi = ((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl;
-        re = (TC)Xin[gi];
-        im = (TC)Xin[gi + 1];
-        if (a.pre) {
-          TC sn, cs;
-          sincos_t<TC>((TC)(-a.th_pre) * (TC)V2[gi >> 1], &sn, &cs);
-          const TC nr = cs * re - sn * im, ni = sn * re + cs * im;
-          re = nr;
-          im = ni;
-        }
+  for (int k = t; k < nchunks; k += GT) {
+    const int row = cpr_sh >= 0 ? (k >> cpr_sh) : k / cpr;
+    const int rl = (k - row * cpr) * VW;
+    TIO v[VW];
+    const bool ok = row < live_rows && rl < rt;
+    const int64_t gi = gbase + (int64_t)row * a.R + rl;
+    if (ok) vload<TIO, VW, VEC>(Xin + gi, v);
+    TC c[VW];
+#pragma unroll
+    for (int m = 0; m < VW; ++m) c[m] = ok ? (TC)v[m] : (TC)0;
+    if (CPLX && a.pre && ok) {
+#pragma unroll
+      for (int m = 0; m < VW; m += 2) {
+        TC sn, cs;
+        sincos_t<TC>((TC)(-a.th_pre) * (TC)V2[(gi + m) >> 1], &sn, &cs);
+        const TC re = c[m], im = c[m + 1];
+        c[m] = cs * re - sn * im;
+        c[m + 1] = sn * re + cs * im;
       }
-      tile[e] = re;
-      tile[e + 1] = im;
     }
-  } else {
-    for (int e = t; e < elems; e += GT) {
-      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
-      TC v = 0;
-      if (pl < pb && rl < rt) v = (TC)Xin[((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl];
-      tile[e] = v;
-    }
+#pragma unroll
+    for (int m = 0; m < VW; ++m) tile[row * RT + rl + m] = c[m];
   }
   __syncthreads();
 
@@ -124,22 +159,26 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
     __syncthreads();
     if (s == a.scale_after) {
       // diagonal of the slowest group's pass: element (g, q) with q = (r0 + rl) / ncomp
-      if (CPLX) {
-        for (int e = 2 * t; e < elems; e += 2 * GT) {
-          const int rl = e % RT, g = (e / RT) % G;
-          const int64_t q = (r0 + rl) >> 1;
-          if (rl < rt) {
-            const double2 f1 = a.Eg[g], f2 = a.Er[q];
+      for (int k = t; k < nchunks; k += GT) {
+        const int row = cpr_sh >= 0 ? (k >> cpr_sh) : k / cpr;
+        const int rl = (k - row * cpr) * VW;
+        if (rl >= rt) continue;
+        const int g = row % G;
+        TC* e = tile + row * RT + rl;
+        if (CPLX) {
+          const double2 f1 = a.Eg[g];
+#pragma unroll
+          for (int m = 0; m < VW; m += 2) {
+            const double2 f2 = a.Er[(r0 + rl + m) >> 1];
             const double fr = f1.x * f2.x - f1.y * f2.y, fi = f1.x * f2.y + f1.y * f2.x;
-            const double re = tile[e], im = tile[e + 1];
-            tile[e] = (TC)(fr * re - fi * im);
-            tile[e + 1] = (TC)(fi * re + fr * im);
+            const double re = e[m], im = e[m + 1];
+            e[m] = (TC)(fr * re - fi * im);
+            e[m + 1] = (TC)(fi * re + fr * im);
           }
-        }
-      } else {
-        for (int e = t; e < elems; e += GT) {
-          const int rl = e % RT, g = (e / RT) % G;
-          if (rl < rt) tile[e] = (TC)((double)tile[e] / (a.Lg[g] + a.Lr[r0 + rl] + a.shift));
+        } else {
+          const double lg = a.Lg[g];
+#pragma unroll
+          for (int m = 0; m < VW; ++m) e[m] = (TC)((double)e[m] / (lg + a.Lr[r0 + rl + m] + a.shift));
         }
       }
       __syncthreads();
@@ -147,39 +186,52 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
   }
 
   // ---- store (optionally multiplied by e^{-i th_post V2}) ----
-  if (CPLX) {
-    for (int e = 2 * t; e < elems; e += 2 * GT) {
-      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
-      if (pl < pb && rl < rt) {
-        const int64_t gi = ((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl;
-        TC re = tile[e], im = tile[e + 1];
-        if (a.post) {
-          TC sn, cs;
-          sincos_t<TC>((TC)(-a.th_post) * (TC)V2[gi >> 1], &sn, &cs);
-          const TC nr = cs * re - sn * im, ni = sn * re + cs * im;
-          re = nr;
-          im = ni;
-        }
-        Xout[gi] = (TIO)re;
-        Xout[gi + 1] = (TIO)im;
+  for (int k = t; k < nchunks; k += GT) {
+    const int row = cpr_sh >= 0 ? (k >> cpr_sh) : k / cpr;
+    const int rl = (k - row * cpr) * VW;
+    if (row >= live_rows || rl >= rt) continue;
+    const int64_t gi = gbase + (int64_t)row * a.R + rl;
+    TC c[VW];
+#pragma unroll
+    for (int m = 0; m < VW; ++m) c[m] = tile[row * RT + rl + m];
+    if (CPLX && a.post) {
+#pragma unroll
+      for (int m = 0; m < VW; m += 2) {
+        TC sn, cs;
+        sincos_t<TC>((TC)(-a.th_post) * (TC)V2[(gi + m) >> 1], &sn, &cs);
+        const TC re = c[m], im = c[m + 1];
+        c[m] = cs * re - sn * im;
+        c[m + 1] = sn * re + cs * im;
       }
     }
-  } else {
-    for (int e = t; e < elems; e += GT) {
-      const int rl = e % RT, rest = e / RT, g = rest % G, pl = rest / G;
-      if (pl < pb && rl < rt) Xout[((p0 + pl) * (int64_t)G + g) * a.R + r0 + rl] = (TIO)tile[e];
-    }
+    TIO v[VW];
+#pragma unroll
+    for (int m = 0; m < VW; ++m) v[m] = (TIO)c[m];
+    vstore<TIO, VW, VEC>(Xout + gi, v);
   }
 }
 
-template <typename TIO, typename TC, bool CPLX>
-hipError_t launch_nmax(const GroupArgs& a, int nmax, hipStream_t st) {
+template <typename TIO, typename TC, bool CPLX, int VW, bool VEC>
+hipError_t launch_vw(const GroupArgs& a, int nmax, hipStream_t st) {
   const size_t lds = sizeof(TC) * (size_t)a.tile_elems;
   dim3 grid((unsigned)a.nblocks), block(GT);
-  if (nmax <= 16) hipLaunchKernelGGL((k_group<TIO, TC, 1, CPLX>), grid, block, lds, st, a);
-  else if (nmax <= 32) hipLaunchKernelGGL((k_group<TIO, TC, 2, CPLX>), grid, block, lds, st, a);
+  if (nmax <= 16) hipLaunchKernelGGL((k_group<TIO, TC, 1, CPLX, VW, VEC>), grid, block, lds, st, a);
+  else if (nmax <= 32) hipLaunchKernelGGL((k_group<TIO, TC, 2, CPLX, VW, VEC>), grid, block, lds, st, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+// 16-byte chunks when every tile row starts 16-byte aligned and holds whole
+// chunks (R, RT multiples of the vector width, aligned buffers), else single
+// values (pairs for complex data).
+template <typename TIO, typename TC, bool CPLX>
+hipError_t launch_nmax(GroupArgs a, int nmax, hipStream_t st) {
+  constexpr int V = 16 / (int)sizeof(TIO);
+  constexpr int S = CPLX ? 2 : 1;
+  const bool vec = a.R % V == 0 && a.RT % V == 0 && ((uintptr_t)a.Xin & 15) == 0 && ((uintptr_t)a.Xout & 15) == 0;
+  const int cpr = a.RT / (vec ? V : S);
+  a.cpr_shift = (cpr & (cpr - 1)) == 0 ? __builtin_ctz((unsigned)cpr) : -1;
+  return vec ? launch_vw<TIO, TC, CPLX, V, true>(a, nmax, st) : launch_vw<TIO, TC, CPLX, S, false>(a, nmax, st);
 }
 
 }  // namespace

@@ -21,6 +21,7 @@ struct GroupArgs {
   int64_t P = 1, R = 1;     // tensor viewed as [P][G][R] (R counts real values)
   int G = 1;
   int PB = 1, RT = 1;       // tile: PB x G x RT
+  int cpr_shift = -1;       // log2 of the chunks per tile row (set by the launcher; -1: not a power of 2)
   int tile_elems = 0;
   int64_t rtiles = 1, nblocks = 0;
   int nsteps = 0;

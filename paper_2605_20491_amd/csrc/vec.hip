@@ -78,11 +78,13 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
         }
       }
       const bool has_dn = jp > 0, has_up = jp + 1 < np;
-      double up[kRows];
+      // the next plane's values: the upper neighbours of this plane (unless
+      // the marching axis ends here) and the centre values of the next plane
+      double nx[kRows];
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
         const bool in = xin && yy[j] < NY;
-        up[j] = (in && has_up) ? ld(((p + 1) * NY + yy[j]) * NX + x) : 0.0;
+        nx[j] = (in && p + 1 < P) ? ld(((p + 1) * NY + yy[j]) * NX + x) : 0.0;
         tile[ty + kTYT * j + 1][tx + 1] = uc[j];
       }
       // halo of plane p: rows y0 - 1 and y0 + kTY, columns x0 - 1 and x0 + kTX
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
             const double hi = ((hi_ok >> k) & 1u) ? ld(idx + st) : 0.0;
             acc += a.ih2[k] * (2.0 * u0 - lo - hi);
           }
-          if (ap >= 0) acc += ihp * (2.0 * u0 - (has_dn ? um[j] : 0.0) - up[j]);
+          if (ap >= 0) acc += ihp * (2.0 * u0 - (has_dn ? um[j] : 0.0) - (has_up ? nx[j] : 0.0));
           if (ay >= 0) acc += ihy * (2.0 * u0 - tile[ly - 1][tx + 1] - tile[ly + 1][tx + 1]);
           acc += ihx * (2.0 * u0 - tile[ly][tx] - tile[ly][tx + 2]);
           const double diag = fp + fxy[j] + (a.V2 ? a.V2[idx] : 0.0);
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
           if (DOT == (int)StDot::OutdotOut) dsum += v * v;
         }
         um[j] = uc[j];
-        uc[j] = up[j];
+        uc[j] = nx[j];
       }
       __syncthreads();
     }

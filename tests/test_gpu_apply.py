@@ -232,3 +232,24 @@ def test_fp32_data_fp64_transforms(shape):
     ep = rel(out, refp)
     announce("fp32 data, fp64 transforms %s: inverse %.2e, exp %.2e" % (shape, e, ep))
     assert e <= 5e-7 and ep <= 5e-7
+
+
+@pytest.mark.parametrize("shape", [(1000,), (70, 90), (31, 40, 27), (33, 25, 128, 64), (6, 5, 7, 4, 3),
+                                   (16, 16, 16, 16, 16, 16)])
+def test_operator_matches_oracle_stencil_any_d(shape):
+    """The tiled operator kernel on 1D-6D grids, including grids where one
+    block marches through several planes across the ends of the slower axes
+    (33 x 25 x 128 x 64: three planes per block along an axis of 25; 16^6:
+    32 planes per block along an axis of 16)."""
+    L = 5.0
+    rng = np.random.default_rng(21)
+    f = [rng.uniform(0.0, 5.0, size=n) for n in shape]
+    plan = ts.ts_setup(shape, L, f, 0.0)
+    oplan = oracle.Plan(shape=shape, L=L, f=f, h=[oracle.grid_spacing(n, L) for n in shape])
+    u = W.rhs_normal(shape, 22)
+    V2 = W.gaussian_bumps(shape, L, 3, seed=23)
+    out = to_host(ts.ts_operator_apply(plan, to_dev(V2), 0.5, to_dev(u)))
+    ref = oracle.stencil_apply(oplan, u, V2, 0.5)
+    e, em = rel(out, ref), maxrel(out, ref)
+    announce("operator %s vs oracle stencil: %.2e (max-norm %.2e)" % (shape, e, em))
+    assert e <= 1e-14 and em <= 1e-14

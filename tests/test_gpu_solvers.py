@@ -179,3 +179,21 @@ def test_mixed_bf16_solvers_reach_fp64_tolerance():
     true = np.linalg.norm(f - oracle.stencil_apply(oplan, uh, V2, sigma)) / np.linalg.norm(f)
     announce("pcg bf16 preconditioner: %d iterations, relres %.2e (oracle-stencil %.2e)" % (it, rr, true))
     assert true <= 1.05e-10
+
+
+@pytest.mark.parametrize("shape,precond", [((33, 25, 128, 64), "fp64"), ((16, 16, 16, 16, 16, 16), "bf16"),
+                                           ((700, 600), "fp32")])
+def test_pcg_higher_d_true_residual(shape, precond):
+    """PCG (with the direction update fused into the operator sweep) on 2D, 4D
+    and 6D grids: the true residual of the result, recomputed by the oracle's
+    stencil, meets the tolerance."""
+    L = 6.0
+    f_list = [W.f_harmonic(n, L) for n in shape]
+    V2 = np.abs(W.gaussian_bumps(shape, L, 6, seed=31))
+    plan = ts.ts_setup(shape, L, f_list, 1.0)
+    oplan = oracle.Plan(shape=shape, L=L, f=f_list, h=[oracle.grid_spacing(n, L) for n in shape])
+    f = W.rhs_normal(shape, 32)
+    u, it, rr, _ = ts.ts_pcg_solve(plan, to_dev(V2), to_dev(f), rtol=1e-10, precond=precond)
+    true = np.linalg.norm(f - oracle.stencil_apply(oplan, to_host(u), V2, 1.0)) / np.linalg.norm(f)
+    announce("pcg %s %s: %d iterations, relres %.2e, oracle-stencil %.2e" % (shape, precond, it, rr, true))
+    assert rr <= 1e-10 and true <= 1.05e-10
