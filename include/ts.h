@@ -244,6 +244,26 @@ int ts_mass(const ts_plan* plan, int axis, double* out);
 int ts_apply_inverse(ts_plan* plan, const void* b, void* u, int dtype, int prec,
                      void* hip_stream);
 
+/* Bytes of the device array that serves ts_apply_inverse_noalloc. */
+#define TS_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* ts_apply_inverse for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and result as ts_apply_inverse (bitwise), but the
+ * apply's scratch (the pass workspace, N x 8 bytes for grids with an axis of
+ * n > 32; the diagonal tables of the grouped passes otherwise) is taken from
+ * one static device array of TS_NOALLOC_SCRATCH_BYTES (256 MiB) that every
+ * device holds from library load to process exit; the call makes no hipMalloc,
+ * hipFree or other allocating call.  The plan's device must be current.  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (two streams, two threads) race and must be ordered by the caller.
+ * Errors: as ts_apply_inverse; TS_ERR_INVALID also when the apply needs more
+ * than TS_NOALLOC_SCRATCH_BYTES (FP64 grids of more than 2^25 points with an
+ * axis of n > 32) or another device is current; TS_ERR_DEVICE if the array's
+ * address cannot be obtained. */
+int ts_apply_inverse_noalloc(ts_plan* plan, const void* b, void* u, int dtype, int prec,
+                             void* hip_stream);
+
 /* Same, with an explicit shift s replacing the plan's sigma: u = (H1 + s)^{-1} b.
  * Used for shifted inverse iteration, where s = -(shift) sits close to
  * -lambda_1 and the denominators must be formed in FP64. */

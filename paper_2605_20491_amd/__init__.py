@@ -67,6 +67,7 @@ def lib():
             "ts_mass": [_vp, ctypes.c_int, _dp],
             "ts_apply_inverse": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_apply_inverse_shift": [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
+            "ts_apply_inverse_noalloc": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_apply_exp": [_vp, ctypes.c_double, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_solve_refined": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _ip, _dp, _vp],
             "ts_pcg_solve": [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, _ip, _dp, _vp],
@@ -304,6 +305,14 @@ def ts_apply_inverse(plan: Plan, b, u=None, prec="fp64", stream=None):
         u = torch.empty_like(b)
     _check(lib().ts_apply_inverse(plan.handle, _dev(b, plan, "b"), _dev(u, plan, "u"), _dtype_code(b),
                                   _prec(prec), _stream(stream)), "ts_apply_inverse")
+    return u
+
+
+def ts_apply_inverse_noalloc(plan: Plan, b, u, prec="fp64", stream=None):
+    """ts_apply_inverse with the library's static scratch array (no device
+    allocation inside the call); u must be given."""
+    _check(lib().ts_apply_inverse_noalloc(plan.handle, _dev(b, plan, "b"), _dev(u, plan, "u"), _dtype_code(b),
+                                          _prec(prec), _stream(stream)), "ts_apply_inverse_noalloc")
     return u
 
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libts.so")
 
-SOURCES = ["eig_tridiag.cpp", "sem_setup.cpp", "ts_api.cpp", "solvers.cpp", "modeprod.hip", "modeprod_bf16.hip", "modeprod_small.hip", "small_plan.cpp", "split.cpp", "serve.cpp", "vec.hip", "gpe.cpp", "gpe_kernels.hip", "multilevel.hip", "hermite.cpp"]
+SOURCES = ["eig_tridiag.cpp", "sem_setup.cpp", "ts_api.cpp", "solvers.cpp", "modeprod.hip", "modeprod_bf16.hip", "modeprod_small.hip", "small_plan.cpp", "split.cpp", "serve.cpp", "vec.hip", "gpe.cpp", "gpe_kernels.hip", "multilevel.hip", "hermite.cpp", "noalloc.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
