@@ -127,6 +127,16 @@ int ts_destroy(ts_plan* plan);
  * ts_fold_axes reports the axes that qualify as a bit mask (bit k = axis k). */
 int ts_set_fold(ts_plan* plan, int enable);
 
+/* Output tile of the BF16 passes (Sec. 2.2 runs the apply in BF16): 0 (the
+ * default) lets the library choose, 128 forces 128 x 128 tiles, 256 asks for
+ * 256 x 256 tiles wherever they apply (real BF16 input on a non-folded axis
+ * of n >= 192 whose rows hold a multiple of 8 values, 16-byte aligned
+ * buffers).  The larger tile fetches each operand element half as often from
+ * L2; by default it is used when it still gives every compute unit a tile.
+ * Both tiles consume K in the same order, so results are bitwise equal.
+ * Returns TS_ERR_INVALID for a null plan or another value. */
+int ts_set_bf16_tile(ts_plan* plan, int tile);
+
 /* One pass of the apply (Sec. 2.1 step 2 or 4) on one axis, without the
  * scaling: forward out = in x_axis T_axis^{-1}, backward out = in x_axis
  * T_axis (spectral index in the plan's internal order, see ts_set_fold).

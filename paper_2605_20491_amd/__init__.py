@@ -54,6 +54,7 @@ def lib():
                          ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
             "ts_destroy": [_vp],
             "ts_set_fold": [_vp, ctypes.c_int],
+            "ts_set_bf16_tile": [_vp, ctypes.c_int],
             "ts_mode_pass": [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
             "ts_fold_butterfly": [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp],
             "ts_fold_axes": [_vp, _ip],
@@ -266,6 +267,10 @@ def ts_mass(plan: Plan, axis: int) -> np.ndarray:
 
 def ts_set_fold(plan: Plan, enable: bool):
     _check(lib().ts_set_fold(plan.handle, int(bool(enable))), "ts_set_fold")
+
+
+def ts_set_bf16_tile(plan: Plan, tile: int):
+    _check(lib().ts_set_bf16_tile(plan.handle, int(tile)), "ts_set_bf16_tile")
 
 
 def ts_mode_pass(plan: Plan, axis: int, forward: bool, x, out=None, prec="fp64", stream=None, folded=False):

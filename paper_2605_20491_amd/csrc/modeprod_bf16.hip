@@ -23,6 +23,7 @@ namespace {
 using namespace mp;
 
 typedef short s8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));  // one 16-byte register chunk
 
 constexpr int BM = 128, BN = 128, BK = 64, NT = 256;
 constexpr int LDK = BK + 8;  // padded row: 144 B, fragment reads are bank-conflict free
@@ -547,6 +548,257 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
       }
 }
 
+// ---- 256 x 256 output tiles (real BF16 data, no fold, 16-byte aligned rows) ----
+// With 128 x 128 tiles every operand element is fetched from L2 once per
+// tile it feeds: 2 M N K (1/BM + 1/BN) bytes per pass, 32 GB at 1000^3, which
+// the L2-to-CU path cannot deliver at the rate the matrix cores consume it.
+// Doubling both tile sides halves that traffic.  A block of 512 threads (8
+// waves as 2 x 4, each a 128 x 64 sub-tile of 8 x 4 MFMA blocks, 128 FP32
+// accumulators per lane) owns one CU's LDS (two stages of 256 x 64 BF16 for
+// each operand, 144 KB).  K is consumed in the same order as by k_mode_bf16
+// (64-wide k-tiles, two 32-wide MFMA steps each), so both kernels give
+// bitwise equal results.
+constexpr int BB = 256, NTB = 512;
+
+template <bool ROWS, int EPI, typename TOut>
+__global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
+  if (a.skip && *a.skip) return;
+  __shared__ __attribute__((aligned(16))) uint16_t smem_big[4 * BB * LDK];
+  typedef uint16_t Row[LDK];
+  Row* As = (Row*)smem_big;                  // [2][BB] rows
+  Row* Bs = As + 2 * BB;                     // [2][BB] rows
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 2, wn = wave & 3;   // 128-row x 64-column wave tile
+  const int lr = lane & 15, lg = lane >> 4;
+
+  const int64_t lb = xcd_logical_block(blockIdx.x, a.nblocks);
+  int64_t p = 0, mtile, ntile;
+  if (ROWS) {
+    mtile = lb / a.nt;
+    ntile = lb % a.nt;
+  } else {
+    mtile = lb % a.mt;
+    const int64_t rest = lb / a.mt;
+    ntile = rest % a.nt;
+    p = rest / a.nt;
+  }
+  const int64_t K = a.n;
+  const uint16_t* S = (const uint16_t*)a.S;
+  const int64_t m0 = mtile * BB, n0 = ntile * BB;
+  const uint16_t* X = (const uint16_t*)a.X;
+  const int64_t f0 = ROWS ? n0 : m0;  // first factor row of this tile
+
+  // One k-tile on its way to LDS: 64 bytes of the factor tile and 64 bytes of
+  // the data tile per thread, as raw 16-byte chunks.
+  auto load_factor = [&](int64_t k0, u32x4 (&rf)[4]) __attribute__((always_inline)) {
+    // factor rows past the zero padding of the stored factor read as zero
+    const int row = t >> 1, half = t & 1;
+    const u32x4* src = (const u32x4*)(S + (f0 + row) * a.ld + k0 + 32 * half);
+    const bool in = f0 + row < a.ld;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rf[i] = in ? src[i] : u32x4{0u, 0u, 0u, 0u};
+  };
+  auto load_data = [&](int64_t k0, u32x4 (&rx)[4]) __attribute__((always_inline)) {
+    if (!ROWS) {
+      // rows k0 + 4 kq .. + 3 of X[p], columns n0 + 8 oc .. + 7 (32 lanes per row: coalesced)
+      const int oc = t & 31, kq = t >> 5;
+      const int64_t col0 = n0 + 8 * oc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t k = k0 + 4 * kq + r;
+        rx[r] = u32x4{0u, 0u, 0u, 0u};
+        if (k < K && col0 < a.R) rx[r] = *(const u32x4*)(X + (p * a.n + k) * a.R + col0);
+      }
+    } else {
+      // rows m0 + 64 s + rg, k-chunk c of 8 (8 lanes per row: coalesced)
+      const int c = t & 7, rg = t >> 3;
+      const int64_t kk = k0 + 8 * c;
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int64_t m = m0 + 64 * s2 + rg;
+        rx[s2] = u32x4{0u, 0u, 0u, 0u};
+        if (m < a.M && kk < K) rx[s2] = *(const u32x4*)(X + m * a.n + kk);
+      }
+    }
+  };
+  auto store_factor = [&](int buf, const u32x4 (&rf)[4]) __attribute__((always_inline)) {
+    Row* Fs = (ROWS ? Bs : As) + buf * BB;
+    const int row = t >> 1, half = t & 1;
+    u32x4* dst = (u32x4*)&Fs[row][32 * half];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dst[i] = rf[i];
+  };
+  auto store_data = [&](int buf, const u32x4 (&rx)[4]) __attribute__((always_inline)) {
+    if (!ROWS) {
+      // transpose 4 k x 8 columns into Bs[col][k], k-chunks swizzled by row group
+      const int oc = t & 31, kq = t >> 5;
+      Row* D = Bs + buf * BB;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int sh = 16 * (c & 1);
+        const uint32_t v0 = (rx[0][c >> 1] >> sh) & 0xffffu, v1 = (rx[1][c >> 1] >> sh) & 0xffffu;
+        const uint32_t v2 = (rx[2][c >> 1] >> sh) & 0xffffu, v3 = (rx[3][c >> 1] >> sh) & 0xffffu;
+        const int row = 8 * oc + c;
+        *(uint2*)&D[row][swz8(row, kq >> 1) + 4 * (kq & 1)] = make_uint2(v0 | (v1 << 16), v2 | (v3 << 16));
+      }
+    } else {
+      const int c = t & 7, rg = t >> 3;
+      Row* D = As + buf * BB;
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) *(u32x4*)&D[64 * s2 + rg][8 * c] = rx[s2];
+    }
+  };
+
+  f4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  const int64_t nk = (K + BK - 1) / BK;
+  auto compute = [&](int cur) __attribute__((always_inline)) {
+    const Row* Ac = As + cur * BB;
+    const Row* Bc = Bs + cur * BB;
+#pragma unroll
+    for (int ks = 0; ks < BK / 32; ++ks) {
+      s8 bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = wn * 64 + j * 16 + lr;
+        bv[j] = *(const s8*)&Bc[row][ROWS ? ks * 32 + 8 * lg : swz8(row, 4 * ks + lg)];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const s8 av = *(const s8*)&Ac[wm * 128 + i * 16 + lr][ks * 32 + 8 * lg];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  u32x4 rf[4], rx[4];
+  load_factor(0, rf);
+  load_data(0, rx);
+  store_factor(0, rf);
+  store_data(0, rx);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) {
+      load_factor((kt + 1) * BK, rf);
+      load_data((kt + 1) * BK, rx);
+    }
+    compute(cur);
+    if (kt + 1 < nk) {
+      store_factor(cur ^ 1, rf);
+      store_data(cur ^ 1, rx);
+    }
+    __syncthreads();
+  }
+
+  TOut* Y = (TOut*)a.Y;
+  const int64_t rowlen = ROWS ? a.n : a.R;   // outputs per output row
+  const int64_t nrows = ROWS ? a.M : a.n;    // output rows
+  if constexpr (std::is_same<TOut, uint16_t>::value) {
+    // stage the BF16 tile in LDS (rows of 264 elements: 528 B) and write 16 bytes per 8 outputs
+    constexpr int LT = BB + 8;
+    static_assert(BB * LT <= 4 * BB * LDK, "staged tile must fit in the operand buffers");
+    uint16_t* Ts = smem_big;
+    double tr[4] = {0.0, 0.0, 0.0, 0.0};
+    if (EPI == (int)Epi::Inv) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = n0 + wn * 64 + j * 16 + lr;
+        tr[j] = col < a.R ? a.Lr[col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      double tm[4] = {0.0, 0.0, 0.0, 0.0};
+      if (EPI == (int)Epi::Inv) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + wm * 128 + i * 16 + out_row<float>(lane, r);
+          tm[r] = m < a.n ? a.lam[m] + a.Lp[p] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = wm * 128 + i * 16 + out_row<float>(lane, r), cl = wn * 64 + j * 16 + lr;
+          double v = (double)acc[i][j][r];
+          // (entries outside the grid are staged but never written back)
+          if (EPI == (int)Epi::Inv) v = v / (tm[r] + tr[j] + a.shift);
+          Ts[ml * LT + cl] = cvt_out<uint16_t>(v);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (BB * BB / 8) / NTB; ++q) {
+      const int idx = q * NTB + t, lrow = idx >> 5, ch = idx & 31;
+      const int64_t mg = m0 + lrow, cg = n0 + 8 * ch;
+      if (mg >= nrows || cg >= rowlen) continue;
+      const int64_t base = ROWS ? mg * a.n : (p * a.n + mg) * a.R;
+      *(uint4*)(Y + base + cg) = *(const uint4*)&Ts[lrow * LT + 8 * ch];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 128 + i * 16 + out_row<float>(lane, r);
+        if (m >= nrows) continue;
+        const double tm = EPI == (int)Epi::Inv ? a.lam[m] + a.Lp[p] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t col = n0 + wn * 64 + j * 16 + lr;
+          if (col >= rowlen) continue;
+          double v = (double)acc[i][j][r];
+          if (EPI == (int)Epi::Inv) v = v / (tm + a.Lr[col] + a.shift);
+          Y[(ROWS ? m * a.n : (p * a.n + m) * a.R) + col] = cvt_out<TOut>(v);
+        }
+      }
+    }
+  }
+}
+
+// Whether a pass runs on the 256 x 256 tiles: real BF16 input, no fold, rows
+// whose length is a multiple of 8 (every 16-byte chunk aligned) and n >= 192.
+// Chosen by default when it pads the factor's extent by at most 10 % more than
+// 128-wide tiles do and still gives every compute unit a tile.
+template <typename TIn>
+bool bf16_big_ok(const KArgs& a, const PassArgs& pa, int fold) {
+  if (!std::is_same<TIn, uint16_t>::value || pa.cplx || fold || pa.epi == Epi::Exp) return false;
+  if (pa.bf16_tile == 128) return false;
+  if ((((uintptr_t)a.X) & 15) != 0 || (((uintptr_t)a.Y) & 15) != 0) return false;
+  if ((a.rows ? a.n : a.R) % 8 != 0 || a.n < 192) return false;
+  if (pa.bf16_tile == 256) return true;
+  const int64_t pad256 = (a.n + BB - 1) / BB * BB, pad128 = (a.n + BM - 1) / BM * BM;
+  if (pad256 * 10 > pad128 * 11) return false;
+  const int64_t mt = (a.M + BB - 1) / BB, nt = (a.N + BB - 1) / BB;
+  return mt * nt * (a.rows ? 1 : pa.P) >= 256;
+}
+
+template <typename TOut>
+hipError_t launch_bf16_big(KArgs a, const PassArgs& pa, hipStream_t st) {
+  a.mt = (a.M + BB - 1) / BB;
+  a.nt = (a.N + BB - 1) / BB;
+  a.nblocks = a.mt * a.nt * (a.rows ? 1 : pa.P);
+  if (a.nblocks <= 0) return hipSuccess;
+  if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)a.nblocks), block(NTB);
+  if (a.rows) {
+    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Inv) {
+    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, TOut>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
 // Whether a pass's data allow no 16-byte access at all (then the element-wise,
 // coalesced instance runs; such passes do not fold).
 template <typename TIn>
@@ -622,6 +874,7 @@ hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
   const AxisFactor* F = pa.fac;
   fill_kargs(pa, a, pa.forward ? (const void*)F->QT16 : (const void*)F->Q16, BM, BN);
   const int fold = (pa.fold && !bf16_coalesced<TIn>(a, pa)) ? (pa.forward ? 1 : 2) : 0;
+  if (bf16_big_ok<TIn>(a, pa, fold)) return launch_bf16_big<TOut>(a, pa, st);
   if (fold) {
     a.ne = F->ne;
     a.no = F->no;

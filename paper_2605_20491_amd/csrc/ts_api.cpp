@@ -701,6 +701,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     // the mirror loads cost more than the halved MFMA work), so BF16 applies do not fold
     pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
     pa.deferred = deferred && pa.fold;
+    pa.bf16_tile = p->bf16_tile;
     if (fwd && t == d) {
       pa.epi = ap.epi;
       pa.Lp = p->Lp;
@@ -1112,6 +1113,7 @@ int ts_mode_pass(ts_plan* plan, int axis, int forward, const void* in, void* out
   pa.cplx = cplx;
   pa.fold = pa.fac->fold && plan->fold_enabled;
   pa.deferred = pa.fold && forward >= 2;
+  pa.bf16_tile = plan->bf16_tile;
   hipError_t e = launch_pass(pa, (hipStream_t)hip_stream);
   if (e != hipSuccess) { set_error(std::string("mode pass launch failed: ") + hipGetErrorString(e)); return TS_ERR_DEVICE; }
   return TS_OK;
@@ -1149,6 +1151,13 @@ int ts_fold_butterfly(ts_plan* plan, int axes, const void* in, void* out, int dt
 int ts_set_fold(ts_plan* plan, int enable) {
   if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
   plan->fold_enabled = enable != 0;
+  return TS_OK;
+}
+
+int ts_set_bf16_tile(ts_plan* plan, int tile) {
+  if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
+  if (tile != 0 && tile != 128 && tile != 256) { set_error("BF16 tile must be 0, 128 or 256"); return TS_ERR_INVALID; }
+  plan->bf16_tile = tile;
   return TS_OK;
 }
 

@@ -115,6 +115,7 @@ struct PassArgs {
   // (launch_butterfly), a backward pass leaves its butterfly to the caller
   bool deferred = false;
   int64_t kband = 0;           // > 0: the factor is banded, |k - output| <= kband (FP64 passes)
+  int bf16_tile = 0;           // BF16 passes: 0 picks the tile size, 128 or 256 forces it where allowed
 };
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);
@@ -195,6 +196,7 @@ struct ts_plan {
   int sem_k = 0;               // 0: FD or generic; k >= 1: Q^k SEM
   bool massed = false;         // SEM or generic: mass inner product, banded operator
   bool fold_enabled = true;    // use the half-extent passes on symmetric axes
+  int bf16_tile = 0;           // BF16 pass tile: 0 automatic, 128 or 256 forced
   int s = 0;                   // axis whose forward pass carries the scaling
   int64_t Ps = 1, Rs = 1;      // products of the extents before / after axis s
   double* Lp = nullptr;        // device FP64 [Ps]

@@ -13,6 +13,7 @@ struct GroupStep {
   int64_t ld = 0;
   int n = 0;
   int stride = 1;           // stride of this axis inside the group index
+  uint32_t wmul = 0;        // ceil(2^32 / (stride x RT)), 0 when that is 1 (set by the launcher)
 };
 
 struct GroupArgs {
@@ -21,7 +22,7 @@ struct GroupArgs {
   int64_t P = 1, R = 1;     // tensor viewed as [P][G][R] (R counts real values)
   int G = 1;
   int PB = 1, RT = 1;       // tile: PB x G x RT
-  int cpr_shift = -1;       // log2 of the chunks per tile row (set by the launcher; -1: not a power of 2)
+  int flat = 0;             // tile is one contiguous run (RT = R; set by the launcher)
   int tile_elems = 0;
   int64_t rtiles = 1, nblocks = 0;
   int nsteps = 0;

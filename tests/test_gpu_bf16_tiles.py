@@ -1,0 +1,84 @@
+"""BF16 passes on 256 x 256 output tiles (ts_set_bf16_tile).
+
+The larger tile halves the operand traffic from L2 but consumes K in the same
+order (64-wide k-tiles, two 32-wide MFMA steps each) as the 128 x 128 kernel,
+so every BF16 apply must give bitwise equal results under both tiles: the
+plain, scaling and last passes, BF16 / FP32 / FP64 outputs, ragged tiles
+(n = 200, 264 against 256-wide tiles) and factor rows beyond the stored
+padding (n = 264 keeps 384 padded rows against 512 tile rows).  The default
+choice is checked against the FP64 oracle at the BF16 level (parity unpinned:
+BF16 operands have no exact value, the bar is the one of the other BF16
+tests), and the PCG with a BF16 preconditioner on the large tiles still
+reaches the FP64 residual bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_20491_amd as ts
+import workloads as W
+from gpu_common import DEV, announce, make_pair, maxrel, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def to_host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(200, 256, 264), (264, 200, 256), (256, 64, 200), (512, 2048)])
+def test_large_and_small_tiles_bitwise_equal(shape):
+    # library plan only: no oracle value is needed for a comparison of two kernels
+    plan = ts.ts_setup(shape, 8.0, [W.f_harmonic(n, 8.0) for n in shape], 1.0)
+    b = to_dev(W.rhs_normal(shape, 21))
+    for dt in (torch.float64, torch.float32):
+        x = b.to(dt)
+        outs = {}
+        for tile in (128, 256):
+            ts.ts_set_bf16_tile(plan, tile)
+            outs[tile] = to_host(ts.ts_apply_inverse(plan, x, prec="bf16"))
+        ts.ts_set_bf16_tile(plan, 0)
+        auto = to_host(ts.ts_apply_inverse(plan, x, prec="bf16"))
+        same = np.array_equal(outs[128], outs[256])
+        announce("bf16 tiles %s %s: 128 vs 256 bitwise equal %s" % (shape, dt, same))
+        assert same and np.array_equal(auto, outs[128])
+        assert np.isfinite(outs[256]).all() and np.abs(outs[256]).max() > 0
+
+
+def test_tile_knob_rejects_other_values():
+    plan = ts.ts_setup((8, 8), 4.0, [W.f_harmonic(8, 4.0)] * 2, 1.0)
+    with pytest.raises(ts.TSError):
+        ts.ts_set_bf16_tile(plan, 64)
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 256), (512, 512, 64)])
+def test_default_tiles_against_oracle(shape):
+    plan, oplan, _ = make_pair(shape, 8.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 22)
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    u = to_host(ts.ts_apply_inverse(plan, to_dev(b), prec="bf16"))
+    e, em = rel(u, ref), maxrel(u, ref)
+    announce("bf16 inverse %s (default tiles): rel err %.3e, max-norm %.3e" % (shape, e, em))
+    assert 1e-3 < e <= 1.5e-2 and em <= 5e-2
+
+
+def test_pcg_bf16_preconditioner_on_large_tiles():
+    shape = (256, 256, 256)
+    L = 8.0
+    f = [W.f_harmonic(n, L) for n in shape]
+    V2 = W.gaussian_bumps(shape, L, 16, seed=3)
+    sigma = max(1.0, 0.5 - sum(float(min(fk)) for fk in f) - float(V2.min()))
+    plan = ts.ts_setup(shape, L, f, sigma)
+    rhs = W.rhs_normal(shape, 23)
+    u = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    _, its, relres, _ = ts.ts_pcg_solve(plan, to_dev(V2), to_dev(rhs), u, rtol=1e-10, maxit=200, precond="bf16")
+    op = oracle.Plan(shape=shape, L=L, f=f, h=[oracle.grid_spacing(n, L) for n in shape])
+    true = np.linalg.norm(rhs - oracle.stencil_apply(op, to_host(u), V2, sigma)) / np.linalg.norm(rhs)
+    announce("PCG bf16 preconditioner 256^3: %d iterations, recurrence %.2e, true residual %.2e" % (its, relres, true))
+    assert true <= 1.05e-10
