@@ -352,13 +352,15 @@ __global__ __launch_bounds__(NT, 2) void k_mode_mfma(KArgs a) {
   constexpr bool kDeep = FOLD != 1 && !COAL;
   if (kDeep) {
     if (nk > 1) load_tile(kbeg + BK, rres0, rdat0);
-    __syncthreads();
+    lds_barrier();
+    // LDS-only barriers: the loads of tile kt + 2 stay in flight across the
+    // barrier that ends stage kt
     auto stage = [&](int64_t kt, TC (&ra)[8], TIn (&da)[8], TC (&rb)[8], TIn (&db)[8]) {
       const int cur = (int)(kt & 1);
       if (kt + 2 < nk) load_tile(kbeg + (kt + 2) * BK, rb, db);
       compute(cur);
       if (kt + 1 < nk) store_tile(cur ^ 1, ra, da);
-      __syncthreads();
+      lds_barrier();
     };
     for (int64_t kt = 0; kt < nk; kt += 2) {
       stage(kt, rres0, rdat0, rres1, rdat1);

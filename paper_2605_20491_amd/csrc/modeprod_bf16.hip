@@ -592,34 +592,37 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
 
   // One k-tile on its way to LDS: 64 bytes of the factor tile and 64 bytes of
   // the data tile per thread, as raw 16-byte chunks.
+  // Every load is unconditional (no branches, so the compiler can wait for
+  // exactly the loads each step needs): out-of-range indices are clamped to
+  // the last row or column.  The duplicates they fetch are finite values that
+  // meet only zero factor entries (k past n: the factor's zero padding) or feed
+  // outputs that are never stored (factor rows past the stored padding, data
+  // rows or columns past the grid).
   auto load_factor = [&](int64_t k0, u32x4 (&rf)[4]) __attribute__((always_inline)) {
-    // factor rows past the zero padding of the stored factor read as zero
     const int row = t >> 1, half = t & 1;
-    const u32x4* src = (const u32x4*)(S + (f0 + row) * a.ld + k0 + 32 * half);
-    const bool in = f0 + row < a.ld;
+    const int64_t fr = f0 + row < a.ld ? f0 + row : a.ld - 1;
+    const u32x4* src = (const u32x4*)(S + fr * a.ld + k0 + 32 * half);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) rf[i] = in ? src[i] : u32x4{0u, 0u, 0u, 0u};
+    for (int i = 0; i < 4; ++i) rf[i] = src[i];
   };
   auto load_data = [&](int64_t k0, u32x4 (&rx)[4]) __attribute__((always_inline)) {
     if (!ROWS) {
       // rows k0 + 4 kq .. + 3 of X[p], columns n0 + 8 oc .. + 7 (32 lanes per row: coalesced)
       const int oc = t & 31, kq = t >> 5;
-      const int64_t col0 = n0 + 8 * oc;
+      const int64_t col0 = n0 + 8 * oc < a.R ? n0 + 8 * oc : 0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t k = k0 + 4 * kq + r;
-        rx[r] = u32x4{0u, 0u, 0u, 0u};
-        if (k < K && col0 < a.R) rx[r] = *(const u32x4*)(X + (p * a.n + k) * a.R + col0);
+        const int64_t k = k0 + 4 * kq + r < K ? k0 + 4 * kq + r : K - 1;
+        rx[r] = *(const u32x4*)(X + (p * a.n + k) * a.R + col0);
       }
     } else {
       // rows m0 + 64 s + rg, k-chunk c of 8 (8 lanes per row: coalesced)
       const int c = t & 7, rg = t >> 3;
-      const int64_t kk = k0 + 8 * c;
+      const int64_t kk = k0 + 8 * c < K ? k0 + 8 * c : K - 8;
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
-        const int64_t m = m0 + 64 * s2 + rg;
-        rx[s2] = u32x4{0u, 0u, 0u, 0u};
-        if (m < a.M && kk < K) rx[s2] = *(const u32x4*)(X + m * a.n + kk);
+        const int64_t m = m0 + 64 * s2 + rg < a.M ? m0 + 64 * s2 + rg : a.M - 1;
+        rx[s2] = *(const u32x4*)(X + m * a.n + kk);
       }
     }
   };
@@ -677,24 +680,62 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
       }
     }
   };
-  u32x4 rf[4], rx[4];
+  // The data tile (from HBM) is requested two stages ahead: the one stored to
+  // LDS at the end of stage kt was requested at the start of stage kt - 1, so
+  // it has two compute phases (about 2 x 2048 MFMA cycles per SIMD) to arrive;
+  // the factor tile (resident in L2) one stage ahead.
+  u32x4 rf[4], rx0[4];
   load_factor(0, rf);
-  load_data(0, rx);
+  load_data(0, rx0);
   store_factor(0, rf);
-  store_data(0, rx);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) {
-      load_factor((kt + 1) * BK, rf);
-      load_data((kt + 1) * BK, rx);
-    }
-    compute(cur);
-    if (kt + 1 < nk) {
+  store_data(0, rx0);
+  if constexpr (ROWS) {
+    // Row passes keep the data tile two stages ahead in registers (the one
+    // stored at the end of stage kt was requested at the start of stage kt - 1)
+    // and the factor tile, resident in L2, one stage ahead; the barriers order
+    // LDS only, so those loads stay in flight across them.  The number of
+    // k-tiles is made even: with nk odd the extra tile [64 nk, 64 nk + 64)
+    // still lies inside the stored factor (whose extent ld is a multiple of
+    // 128) and is all zero padding there, so it adds only zero products; the
+    // loop body then runs without branches (past the last k-tile the stages
+    // re-request the last tile and fill the idle LDS buffer, which nothing
+    // reads afterwards), and the compiler waits for exactly the loads each
+    // step needs.  (The column passes' transposing stores need the registers
+    // of the second stage.)
+    const int64_t nke = (nk + 1) & ~(int64_t)1;
+    u32x4 rx1[4];
+    load_data(BK, rx0);
+    lds_barrier();
+    auto stage = [&](int64_t kt, u32x4 (&xa)[4], u32x4 (&xb)[4]) __attribute__((always_inline)) {
+      const int cur = (int)(kt & 1);
+      // the factor first: the loads complete in order, so waiting for it at the
+      // end of the stage does not wait for the data requested for stage kt + 2
+      load_factor((kt + 1 < nke ? kt + 1 : nke - 1) * BK, rf);
+      load_data((kt + 2 < nke ? kt + 2 : nke - 1) * BK, xb);
+      compute(cur);
       store_factor(cur ^ 1, rf);
-      store_data(cur ^ 1, rx);
+      store_data(cur ^ 1, xa);
+      lds_barrier();
+    };
+    for (int64_t kt = 0; kt < nke; kt += 2) {
+      stage(kt, rx0, rx1);
+      stage(kt + 1, rx1, rx0);
     }
+  } else {
     __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      const int cur = (int)(kt & 1);
+      if (kt + 1 < nk) {
+        load_factor((kt + 1) * BK, rf);
+        load_data((kt + 1) * BK, rx0);
+      }
+      compute(cur);
+      if (kt + 1 < nk) {
+        store_factor(cur ^ 1, rf);
+        store_data(cur ^ 1, rx0);
+      }
+      __syncthreads();
+    }
   }
 
   TOut* Y = (TOut*)a.Y;

@@ -27,6 +27,17 @@ template <typename T> __device__ __forceinline__ int out_row(int l, int r);
 template <> __device__ __forceinline__ int out_row<double>(int l, int r) { return (l >> 4) + 4 * r; }
 template <> __device__ __forceinline__ int out_row<float>(int l, int r) { return 4 * (l >> 4) + r; }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also
+// waits for every outstanding global load, which would cut short a register
+// prefetch of the next tile issued before it; with this barrier such loads
+// stay in flight (the compiler still waits for them before their registers
+// are used).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---- element conversions ----
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) { return bf16_from_f32(f); }  // nearest even
