@@ -12,6 +12,8 @@
 // apply with g groups makes 2g - 1 round trips through HBM instead of 2d.
 // The pointwise potential factor e^{-i theta V2} of the splitting schemes
 // (Sec. 5.1) can be fused into the first load and the last store.
+#include <algorithm>
+
 #include "modeprod_common.h"
 #include "ts_internal.h"
 #include "ts_small.h"
@@ -119,6 +121,10 @@ template <typename TC> __device__ __forceinline__ int rowperm(int row);
 template <> __device__ __forceinline__ int rowperm<double>(int row) { return row; }
 template <> __device__ __forceinline__ int rowperm<float>(int row) { return (row >> 2) + 4 * (row & 3); }
 
+// Whether a pass stages each step's factor in LDS (FP32 compute) or reads the
+// fragments from memory (FP64 compute).
+template <typename TC> constexpr bool kFacLds = sizeof(TC) == 4;
+
 // One axis step of a grouped pass over the tile seen as [B][n][W]: the batched
 // product Y_b = F^T X_b over its B x W columns, 16 columns per MFMA chunk.
 // A = F^T (M = output row, K = input row; fragments af from the zero-padded
@@ -186,6 +192,7 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
   const int elems = a.PB * G * RT;
   const int live_rows = pb * G;
   const int nchunks = elems / VW;
+  TC* fac = tile + elems + 64;  // the current step's factor, n x n, behind the discard slots
   const int64_t gbase = p0 * (int64_t)G * a.R + r0;
   const TIO* Xin = (const TIO*)a.Xin;
   TIO* Xout = (TIO*)a.Xout;
@@ -240,13 +247,34 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
     const TC* F = (const TC*)S.Q;
     // A row lr of output block m is output m 16 + rowperm<TC>(lr): then lane
     // group lk holds outputs m 16 + lk + 4 r in both precisions, and the
-    // stores of one accumulator register hit 4 consecutive rows, as the reads do
+    // stores of one accumulator register hit 4 consecutive rows, as the reads do.
+    // FP32: the n x n factor goes to LDS once per block (a few loads per block
+    // instead of 8 MT scattered loads per lane, which kept the vector memory
+    // return path busy); FP64 reads the fragments from memory, because the LDS
+    // copy would cost a block per CU on the common tiles.
     TC af[MT][8];
+    if constexpr (kFacLds<TC>) {
+      for (int e = t; e < n * n; e += GT) {
+        const int i = e / n;
+        fac[e] = F[(int64_t)i * S.ld + (e - i * n)];
+      }
+      __syncthreads();
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+      for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        af[m][k] = k < kt ? F[(int64_t)(k * 4 + lk) * S.ld + m * 16 + rowperm<TC>(lr)] : (TC)0;
+        for (int k = 0; k < 8; ++k) {
+          const int i = k * 4 + lk, j = m * 16 + rowperm<TC>(lr);
+          const bool ok = k < kt && i < n && j < n;
+          const TC v = fac[ok ? i * n + j : 0];
+          af[m][k] = ok ? v : (TC)0;
+        }
+    } else {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          af[m][k] = k < kt ? F[(int64_t)(k * 4 + lk) * S.ld + m * 16 + rowperm<TC>(lr)] : (TC)0;
+    }
     // the number of 4-row k-steps is uniform over the block: one branch-free
     // instance per count, so every LDS read of a chunk is issued before its MFMAs
     switch (kt) {
@@ -268,18 +296,25 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
       Walk w(t, per_row, 0, 0, 0);
       const int drg = w.dr % G;
       int g = w.row % G;
+      // with a fixed column per thread (dc = 0) the faster axes' factor is read once
+      double2 f2c = make_double2(0.0, 0.0);
+      double lrc = 0.0;
+      if (w.dc == 0 && w.col * SC < rt) {
+        if (CPLX) f2c = a.Er[r0 / SC + w.col];
+        else lrc = a.Lr[r0 + w.col];
+      }
       for (int e = t; e < elems / SC; e += GT) {
         if (w.col * SC < rt) {
           TC* x = tile + e * SC;
           const int64_t q = r0 / SC + w.col;
           if (CPLX) {
-            const double2 f1 = a.Eg[g], f2 = a.Er[q];
+            const double2 f1 = a.Eg[g], f2 = w.dc == 0 ? f2c : a.Er[q];
             const double fr = f1.x * f2.x - f1.y * f2.y, fi = f1.x * f2.y + f1.y * f2.x;
             const double re = x[0], im = x[1];
             x[0] = (TC)(fr * re - fi * im);
             x[1] = (TC)(fi * re + fr * im);
           } else {
-            x[0] = (TC)((double)x[0] / (a.Lg[g] + a.Lr[q] + a.shift));
+            x[0] = (TC)((double)x[0] / (a.Lg[g] + (w.dc == 0 ? lrc : a.Lr[q]) + a.shift));
           }
         }
         const int row0 = w.row;
@@ -311,7 +346,10 @@ __global__ __launch_bounds__(GT) void k_group(GroupArgs a) {
 
 template <typename TIO, typename TC, bool CPLX, int VW, bool VEC>
 hipError_t launch_vw(const GroupArgs& a, int nmax, hipStream_t st) {
-  const size_t lds = sizeof(TC) * ((size_t)a.tile_elems + 64);  // the tile and 64 discard slots
+  // the tile, 64 discard slots and (FP32) the largest n x n factor of the pass
+  int nf = 0;
+  for (int s = 0; s < a.nsteps; ++s) nf = std::max(nf, a.step[s].n);
+  const size_t lds = sizeof(TC) * ((size_t)a.tile_elems + 64 + (kFacLds<TC> ? (size_t)nf * nf : 0));
   dim3 grid((unsigned)a.nblocks), block(GT);
   if (nmax <= 16) hipLaunchKernelGGL((k_group<TIO, TC, 1, CPLX, VW, VEC>), grid, block, lds, st, a);
   else if (nmax <= 32) hipLaunchKernelGGL((k_group<TIO, TC, 2, CPLX, VW, VEC>), grid, block, lds, st, a);
