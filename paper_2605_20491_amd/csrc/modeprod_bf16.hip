@@ -440,10 +440,14 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ml = wm * 64 + i * 16 + out_row<float>(lane, r), cl = wn * 64 + j * 16 + lr;
-          double v = (double)acc[i][j][r];
-          // (entries outside the grid are staged but never written back)
-          if (EPI == (int)Epi::Inv) v = v / (tm[r] + tr[j] + a.shift);
-          Ts[ml * LT + cl] = cvt_out<uint16_t>(v);
+          // BF16 output: the FP64 denominator, rounded to FP32, divides the FP32
+          // accumulator in FP32 (correctly rounded) before the rounding to BF16;
+          // the quotient is within about 2^-23 of the FP64 one, far below the BF16
+          // step, and the FP64 division would cost this epilogue more than the
+          // pass's products (entries outside the grid are staged, never written)
+          float v = acc[i][j][r];
+          if (EPI == (int)Epi::Inv) v = v / (float)(tm[r] + tr[j] + a.shift);
+          Ts[ml * LT + cl] = f32_to_bf16(v);
         }
     }
     __syncthreads();
@@ -769,10 +773,14 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ml = wm * 128 + i * 16 + out_row<float>(lane, r), cl = wn * 64 + j * 16 + lr;
-          double v = (double)acc[i][j][r];
-          // (entries outside the grid are staged but never written back)
-          if (EPI == (int)Epi::Inv) v = v / (tm[r] + tr[j] + a.shift);
-          Ts[ml * LT + cl] = cvt_out<uint16_t>(v);
+          // BF16 output: the FP64 denominator, rounded to FP32, divides the FP32
+          // accumulator in FP32 (correctly rounded) before the rounding to BF16;
+          // the quotient is within about 2^-23 of the FP64 one, far below the BF16
+          // step, and the FP64 division would cost this epilogue more than the
+          // pass's products (entries outside the grid are staged, never written)
+          float v = acc[i][j][r];
+          if (EPI == (int)Epi::Inv) v = v / (float)(tm[r] + tr[j] + a.shift);
+          Ts[ml * LT + cl] = f32_to_bf16(v);
         }
     }
     __syncthreads();
