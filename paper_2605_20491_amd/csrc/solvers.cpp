@@ -169,6 +169,10 @@ class PcgTask : public Task {
     sq_.skip = done_;
     // the update p = z + beta p rides on the next operator sweep (FD stencil only)
     can_fuse_ = sq_.bw == 0 && !sq_.dense[0];
+    // a BF16 preconditioner's input rounding rides on the residual update,
+    // which writes it where the apply's input sweep would (z, whose old values
+    // the operator sweep has consumed by then)
+    round_r_ = prec_ == TS_PREC_BF16 && bf16_sweep_applies(p_, r_, z_);
     TS_RC(enqueue_chunk(st));
     TS_TRY(snapshot(b_, st));
     return TS_OK;
@@ -218,9 +222,10 @@ class PcgTask : public Task {
       if (pending_) std::swap(pp_, pp2_);
       pending_ = false;
       TS_TRY(launch_scalar(ScalarStep::Alpha, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
-      TS_TRY(launch_cg_update(x_, r_, pp_, q_, N_, b_.sc, b_.partial, done_, st));
+      TS_TRY(launch_cg_update(x_, r_, pp_, q_, N_, b_.sc, b_.partial, done_, st,
+                              round_r_ ? (uint16_t*)z_ : nullptr));
       TS_TRY(launch_scalar(ScalarStep::RR, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
-      TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_, true));
+      TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_, true, round_r_));
       TS_TRY(launch_dot(z_, r_, N_, b_.partial, flexible_ ? q_ : nullptr, flexible_ ? b_.partial2 : nullptr,
                         done_, st));
       TS_TRY(launch_scalar(ScalarStep::Beta, b_.sc, b_.partial, flexible_ ? b_.partial2 : nullptr, flexible_,
@@ -244,7 +249,7 @@ class PcgTask : public Task {
   double *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr, *q_ = nullptr, *pp2_ = nullptr;
   int64_t N_ = 0;
   int flexible_ = 0;
-  bool can_fuse_ = false, pending_ = false;
+  bool can_fuse_ = false, pending_ = false, round_r_ = false;
   const int* done_ = nullptr;
   int chunk_ = 4, enq_ = 0;
   bool final_ = false;

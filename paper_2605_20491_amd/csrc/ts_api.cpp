@@ -667,7 +667,11 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   // the first pass reads 2 instead of 8 bytes per value (rounded as the pass
   // kernels would round it while loading)
   const int64_t Ntot = p->N * ncomp;
-  if (ap.prec == TS_PREC_BF16 && ap.tin == DT::F64 && ap.in != ap.out && Ntot % 4 == 0 &&
+  if (ap.in_rounded) {
+    // the caller's producer of the input already wrote its BF16 rounding to out
+    src = ap.out;
+    src_t = DT::BF16;
+  } else if (ap.prec == TS_PREC_BF16 && ap.tin == DT::F64 && ap.in != ap.out && Ntot % 4 == 0 &&
       ((((uintptr_t)ap.in) & 15) == 0) && ((((uintptr_t)ap.out) & 7) == 0)) {
     hipError_t e = launch_data_to_bf16((const double*)ap.in, (uint16_t*)ap.out, Ntot, ap.skip, st);
     if (e != hipSuccess) {
@@ -722,8 +726,13 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   return deferred ? butterfly(ap.out, ap.out, ap.tout) : TS_OK;
 }
 
+bool bf16_sweep_applies(const ts_plan* p, const void* in, const void* out) {
+  return !plan_is_small(p) && in != out && p->N % 4 == 0 && (((uintptr_t)in) & 15) == 0 &&
+         (((uintptr_t)out) & 7) == 0;
+}
+
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, ExecCtx& c, const int* skip, bool sym) {
+                       hipStream_t st, ExecCtx& c, const int* skip, bool sym, bool in_rounded) {
   if (!p || !b || !u) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_F64 && dtype != TS_F32) { set_error("inverse apply needs TS_F64 or TS_F32 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
@@ -758,6 +767,7 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
   ap.shift = shift;
   ap.skip = skip;
   ap.sym = sym;
+  ap.in_rounded = in_rounded && prec == TS_PREC_BF16 && dtype == TS_F64 && bf16_sweep_applies(p, b, u);
   return run_apply(p, ap, st);
 }
 

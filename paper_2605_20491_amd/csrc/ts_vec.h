@@ -71,8 +71,10 @@ hipError_t launch_dot(const double* x, const double* y, int64_t n, double* parti
                       const double* w, double* partial2, const int* skip, hipStream_t st);
 
 // x += alpha p; r -= alpha q; partial <- ||r||^2 shares.  alpha from sc.
+// r16 (optional): r rounded to BF16 as the BF16 apply's input sweep rounds it.
 hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, int64_t n,
-                            const SolverScalars* sc, double* partial, const int* skip, hipStream_t st);
+                            const SolverScalars* sc, double* partial, const int* skip, hipStream_t st,
+                            uint16_t* r16 = nullptr);
 
 // p = z + beta p (beta from sc).
 hipError_t launch_xpby(const double* z, double* p, int64_t n, const SolverScalars* sc, const int* skip,

@@ -7,6 +7,8 @@
 // writes one partial sum, and a one-block "scalar" kernel adds the partials in
 // index order and takes the solver decision (alpha, beta, convergence) on the
 // device.  Results are bitwise reproducible from run to run.
+#include "bf16_round.h"
+#include "modeprod_common.h"
 #include "ts_internal.h"
 #include "ts_reduce.h"
 #include "ts_vec.h"
@@ -40,10 +42,36 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
   const double ihx = a.ih2[ax], ihy = ay >= 0 ? a.ih2[ay] : 0.0, ihp = ap >= 0 ? a.ih2[ap] : 0.0;
   const int tx = threadIdx.x & (kTX - 1), ty = threadIdx.x / kTX;
   const int64_t ntask = tx_tiles * ty_tiles * p_tiles;
-  // operand: u, or z + beta u when the PCG direction update is fused in
+  // operand: u, or z + beta u when the PCG direction update is fused in.  A
+  // value is fetched raw (z and u) and combined only where it is used, so the
+  // loads of later planes stay in flight across the LDS-only barriers.
   const double* __restrict__ zz = a.z;
   const double beta = zz ? a.bsc->beta : 0.0;
+  struct Raw { double z, u; };
+  auto fetch = [&](bool in, int64_t i) -> Raw {
+    Raw r{0.0, 0.0};
+    if (in) {
+      r.u = a.u[i];
+      if (zz) r.z = zz[i];
+    }
+    return r;
+  };
+  auto val = [&](const Raw& r) -> double { return zz ? r.z + beta * r.u : r.u; };
   auto ld = [&](int64_t i) -> double { return zz ? zz[i] + beta * a.u[i] : a.u[i]; };
+  // the halo value this thread stages for plane q (one of rows y0 - 1, y0 + kTY,
+  // columns x0 - 1, x0 + kTX), or none
+  auto halo = [&](int64_t q, int64_t bx, int64_t by, int64_t x) -> Raw {
+    const int64_t y0 = by * kTY, x0 = bx * kTX;
+    const int64_t pb = q * NXY;
+    if (ty < 2) {
+      const int64_t yh = ty == 0 ? y0 - 1 : y0 + kTY;
+      return fetch(x < NX && yh >= 0 && yh < NY, pb + yh * NX + x);
+    } else if (tx < kTY) {
+      const int64_t xh = ty == 2 ? x0 - 1 : x0 + kTX, yh = y0 + tx;
+      return fetch(xh >= 0 && xh < NX && yh < NY, pb + yh * NX + xh);
+    }
+    return Raw{0.0, 0.0};
+  };
   double dsum = 0.0;
   for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
     const int64_t bx = task % tx_tiles, rest = task / tx_tiles;
@@ -51,7 +79,9 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
     const int64_t x = bx * kTX + tx;
     const int64_t p0 = bp * planes, p1 = p0 + planes < P ? p0 + planes : P;
     const bool xin = x < NX;
-    double fxy[kRows], um[kRows], uc[kRows];
+    // um, uc, nx: planes p - 1, p, p + 1 of this thread's rows; raw values of
+    // plane p + 2 and the halo of plane p + 1 are requested one plane ahead
+    double fxy[kRows], um[kRows], uc[kRows], nx[kRows];
     int64_t yy[kRows];
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
@@ -61,8 +91,16 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
       const int64_t idx = (p0 * NY + yy[j]) * NX + x;
       uc[j] = in ? ld(idx) : 0.0;
       um[j] = (in && p0 > 0) ? ld(idx - NXY) : 0.0;
+      nx[j] = (in && p0 + 1 < P) ? ld(idx + NXY) : 0.0;
     }
+    double hcur = val(halo(p0, bx, by, x));
     for (int64_t p = p0; p < p1; ++p) {
+      // requests for the next planes first
+      Raw nn[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j)
+        nn[j] = fetch(xin && yy[j] < NY && p + 2 < P, ((p + 2) * NY + yy[j]) * NX + x);
+      const Raw hnext = p + 1 < p1 ? halo(p + 1, bx, by, x) : Raw{0.0, 0.0};
       // position of plane p on the slower axes: diagonal part and neighbours
       const int64_t jp = ap >= 0 ? p % np : 0;
       double fp = a.s + (ap >= 0 ? a.f[ap][jp] : 0.0);
@@ -78,30 +116,11 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
         }
       }
       const bool has_dn = jp > 0, has_up = jp + 1 < np;
-      // the next plane's values: the upper neighbours of this plane (unless
-      // the marching axis ends here) and the centre values of the next plane
-      double nx[kRows];
 #pragma unroll
-      for (int j = 0; j < kRows; ++j) {
-        const bool in = xin && yy[j] < NY;
-        nx[j] = (in && p + 1 < P) ? ld(((p + 1) * NY + yy[j]) * NX + x) : 0.0;
-        tile[ty + kTYT * j + 1][tx + 1] = uc[j];
-      }
-      // halo of plane p: rows y0 - 1 and y0 + kTY, columns x0 - 1 and x0 + kTX
-      {
-        const int64_t y0 = by * kTY, x0 = bx * kTX;
-        const int64_t pb = p * NXY;
-        if (ty < 2) {
-          const int64_t yh = ty == 0 ? y0 - 1 : y0 + kTY;
-          const bool in = xin && yh >= 0 && yh < NY;
-          tile[ty == 0 ? 0 : kTY + 1][tx + 1] = in ? ld(pb + yh * NX + x) : 0.0;
-        } else if (tx < kTY) {
-          const int64_t xh = ty == 2 ? x0 - 1 : x0 + kTX, yh = y0 + tx;
-          const bool in = xh >= 0 && xh < NX && yh < NY;
-          tile[tx + 1][ty == 2 ? 0 : kLX - 1] = in ? ld(pb + yh * NX + xh) : 0.0;
-        }
-      }
-      __syncthreads();
+      for (int j = 0; j < kRows; ++j) tile[ty + kTYT * j + 1][tx + 1] = uc[j];
+      if (ty < 2) tile[ty == 0 ? 0 : kTY + 1][tx + 1] = hcur;
+      else if (tx < kTY) tile[tx + 1][ty == 2 ? 0 : kLX - 1] = hcur;
+      mp::lds_barrier();
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
         const int ly = ty + kTYT * j + 1;
@@ -130,8 +149,10 @@ __global__ __launch_bounds__(RT) void k_stencil(StencilArgs a, int64_t tx_tiles,
         }
         um[j] = uc[j];
         uc[j] = nx[j];
+        nx[j] = val(nn[j]);
       }
-      __syncthreads();
+      hcur = val(hnext);
+      mp::lds_barrier();
     }
   }
   if (DOT) {
@@ -260,9 +281,11 @@ __global__ __launch_bounds__(RT) void k_dot(const double* x, const double* y, in
   }
 }
 
+// r16 (optional): also write r rounded to BF16 (FP64 -> FP32 -> BF16, as the
+// BF16 apply's input sweep rounds it), so that sweep can be skipped.
 __global__ __launch_bounds__(RT) void k_cg_update(double* x, double* r, const double* p, const double* q,
                                                   int64_t n, const SolverScalars* sc, double* partial,
-                                                  const int* skip) {
+                                                  const int* skip, uint16_t* r16) {
   if (skip && *skip) {
     if (threadIdx.x == 0) partial[blockIdx.x] = 0.0;
     return;
@@ -273,6 +296,7 @@ __global__ __launch_bounds__(RT) void k_cg_update(double* x, double* r, const do
     x[i] += alpha * p[i];
     const double ri = r[i] - alpha * q[i];
     r[i] = ri;
+    if (r16) r16[i] = bf16_from_f32((float)ri);
     s += ri * ri;
   }
   double t = block_sum(s);
@@ -472,8 +496,9 @@ hipError_t launch_dot(const double* x, const double* y, int64_t n, double* parti
 }
 
 hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, int64_t n,
-                            const SolverScalars* sc, double* partial, const int* skip, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_update, dim3(red_grid(n)), dim3(RT), 0, st, x, r, p, q, n, sc, partial, skip);
+                            const SolverScalars* sc, double* partial, const int* skip, hipStream_t st,
+                            uint16_t* r16) {
+  hipLaunchKernelGGL(k_cg_update, dim3(red_grid(n)), dim3(RT), 0, st, x, r, p, q, n, sc, partial, skip, r16);
   return hipGetLastError();
 }
 
