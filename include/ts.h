@@ -237,6 +237,20 @@ int ts_hermite_axis(int64_t n, double* x, double* m, double* K);
  * doubles.  Errors: TS_ERR_INVALID. */
 int ts_sem_nodes(int k, int64_t cells, double L, double* x);
 
+/* Host eigen-decomposition of one Q^k SEM axis in its symmetric form
+ * M^{-1/2} S M^{-1/2} + diag(f) (Sec. 2, eq. (eigen_decomp)), computed exactly
+ * as ts_setup_sem computes it for each axis: the Gauss-Lobatto rule, the
+ * element matrices and the assembly in long double, rounded once; Householder
+ * reduction and implicit QL in double (on the even and odd blocks when f is
+ * reflection-symmetric); one refinement step of the eigenvectors against the
+ * operator before rounding.  Needs no GPU.  f: n = k cells - 1 host doubles
+ * at the nodes of ts_sem_nodes.  lam: n ascending eigenvalues; Q: row-major
+ * n x n, column j = unit eigenvector of lam[j] (the physical eigenvectors are
+ * M^{-1/2} Q); m: the n lumped masses, or NULL.  Host pointers.  Errors:
+ * TS_ERR_INVALID (bad k, cells or L, null pointer), TS_ERR_NONFINITE,
+ * TS_ERR_NOCONV. */
+int ts_sem_axis_eig(int k, int64_t cells, double L, const double* f, double* lam, double* Q, double* m);
+
 /* Host copy of the lumped mass of an axis (n[axis] doubles): the
  * Gauss-Lobatto weights times the element half-length, summed at element
  * interfaces; h for FD plans. */
@@ -481,8 +495,10 @@ int ts_tridiag_eig_even_odd(int64_t n, const double* diag, const double* off, do
 
 /* Host FP64 eigendecomposition of a dense symmetric matrix (row-major n x n;
  * the symmetric part (A + A^T)/2 is used) by Householder reduction to
- * tridiagonal form and implicit QL (the per-axis step of eq. (eigen_decomp)
- * that ts_setup_sem runs).  Needs no GPU.  lam: n ascending eigenvalues; Q:
+ * tridiagonal form and implicit QL, followed by one refinement step of the
+ * eigenvectors against A (Ogita and Aishima, 2018), with the residuals formed
+ * in long double (the per-axis step of eq. (eigen_decomp) that ts_setup_sem
+ * runs).  Needs no GPU.  lam: n ascending eigenvalues; Q:
  * row-major, column j = unit eigenvector of lam[j], largest-magnitude entry
  * positive.  Host pointers.  Errors: TS_ERR_INVALID, TS_ERR_NOCONV. */
 int ts_sym_eig(int64_t n, const double* A, double* lam, double* Q);

@@ -61,6 +61,7 @@ def lib():
             "ts_setup_sem": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_double,
                              ctypes.POINTER(_dp), ctypes.c_double, ctypes.POINTER(_vp)],
             "ts_sem_nodes": [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _dp],
+            "ts_sem_axis_eig": [ctypes.c_int, ctypes.c_int64, ctypes.c_double, _dp, _dp, _dp, _dp],
             "ts_setup_general": [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_dp),
                                  ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.c_double,
                                  ctypes.POINTER(_vp)],
@@ -258,6 +259,21 @@ def ts_sem_nodes(k: int, cells: int, L: float) -> np.ndarray:
     _check(lib().ts_sem_nodes(int(k), int(cells), float(L), _dptr(x)), "ts_sem_nodes")
     return x
 
+
+
+def ts_sem_axis_eig(k: int, cells: int, L: float, f):
+    """Host eigenpairs of one Q^k SEM axis in the symmetric form
+    M^{-1/2} S M^{-1/2} + diag(f), as ts_setup_sem computes them: (lam, Q, m)."""
+    n = int(k) * int(cells) - 1
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.shape != (n,):
+        raise ValueError("f must hold k * cells - 1 samples")
+    lam = np.empty(n)
+    Q = np.empty((n, n))
+    m = np.empty(n)
+    _check(lib().ts_sem_axis_eig(int(k), int(cells), float(L), _dptr(f), _dptr(lam), _dptr(Q), _dptr(m)),
+           "ts_sem_axis_eig")
+    return lam, Q, m
 
 def ts_mass(plan: Plan, axis: int) -> np.ndarray:
     out = np.empty(plan.shape[axis])

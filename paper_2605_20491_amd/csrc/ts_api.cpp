@@ -157,30 +157,48 @@ bool split_eig_tridiag(int64_t n, const double* dg, const double* off, double* l
   return true;
 }
 
-// Dense reflection-symmetric operator (row-major n x n).
-bool split_eig_dense(int64_t n, const std::vector<double>& A, double* lam, double* Q, FoldPlan& fp) {
+// Even and odd blocks of a reflection-symmetric operator (row-major n x n),
+// mirrored entries averaged, each block made exactly symmetric.
+template <class T>
+void reflection_blocks(int64_t n, const T* A, std::vector<T>& He, std::vector<T>& Ho) {
   const int64_t hh = n / 2, cc = n % 2, ne = hh + cc, no = hh;
-  if (hh == 0) return false;
   auto a = [&](int64_t i, int64_t j) {  // reflection average
-    return 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)((n - 1 - i) * n + (n - 1 - j))]);
+    return (T)0.5 * (A[(size_t)(i * n + j)] + A[(size_t)((n - 1 - i) * n + (n - 1 - j))]);
   };
-  std::vector<double> He((size_t)(ne * ne)), Ho((size_t)(no * no));
+  He.assign((size_t)(ne * ne), (T)0);
+  Ho.assign((size_t)(no * no), (T)0);
   for (int64_t i = 0; i < hh; ++i)
     for (int64_t j = 0; j < hh; ++j) {
       He[(size_t)(i * ne + j)] = a(i, j) + a(i, n - 1 - j);
       Ho[(size_t)(i * no + j)] = a(i, j) - a(i, n - 1 - j);
     }
   if (cc) {
-    for (int64_t i = 0; i < hh; ++i) He[(size_t)(i * ne + hh)] = He[(size_t)(hh * ne + i)] = std::sqrt(2.0) * a(i, hh);
+    const T r2 = std::sqrt((T)2);
+    for (int64_t i = 0; i < hh; ++i) He[(size_t)(i * ne + hh)] = He[(size_t)(hh * ne + i)] = r2 * a(i, hh);
     He[(size_t)(hh * ne + hh)] = a(hh, hh);
   }
-  std::vector<double> le(ne), Ue((size_t)(ne * ne)), lo(no), Uo((size_t)(no * no));
   for (int64_t i = 0; i < ne; ++i)  // exact symmetry of the blocks
-    for (int64_t j = 0; j < i; ++j) He[(size_t)(i * ne + j)] = He[(size_t)(j * ne + i)] = 0.5 * (He[(size_t)(i * ne + j)] + He[(size_t)(j * ne + i)]);
+    for (int64_t j = 0; j < i; ++j)
+      He[(size_t)(i * ne + j)] = He[(size_t)(j * ne + i)] = (T)0.5 * (He[(size_t)(i * ne + j)] + He[(size_t)(j * ne + i)]);
   for (int64_t i = 0; i < no; ++i)
-    for (int64_t j = 0; j < i; ++j) Ho[(size_t)(i * no + j)] = Ho[(size_t)(j * no + i)] = 0.5 * (Ho[(size_t)(i * no + j)] + Ho[(size_t)(j * no + i)]);
-  if (!dense_sym_eig(ne, He, le.data(), Ue.data())) return false;
-  if (!dense_sym_eig(no, Ho, lo.data(), Uo.data())) return false;
+    for (int64_t j = 0; j < i; ++j)
+      Ho[(size_t)(i * no + j)] = Ho[(size_t)(j * no + i)] = (T)0.5 * (Ho[(size_t)(i * no + j)] + Ho[(size_t)(j * no + i)]);
+}
+
+// Dense reflection-symmetric operator (row-major n x n); Aex: the same
+// operator in long double, against which each block's eigenvectors are
+// refined (null: refined against the double blocks).
+bool split_eig_dense(int64_t n, const std::vector<double>& A, double* lam, double* Q, FoldPlan& fp,
+                     const std::vector<long double>* Aex = nullptr) {
+  const int64_t hh = n / 2, cc = n % 2, ne = hh + cc, no = hh;
+  if (hh == 0) return false;
+  std::vector<double> He, Ho;
+  reflection_blocks(n, A.data(), He, Ho);
+  std::vector<long double> HeL, HoL;
+  if (Aex) reflection_blocks(n, Aex->data(), HeL, HoL);
+  std::vector<double> le(ne), Ue((size_t)(ne * ne)), lo(no), Uo((size_t)(no * no));
+  if (!dense_sym_eig(ne, He, le.data(), Ue.data(), Aex ? HeL.data() : nullptr)) return false;
+  if (!dense_sym_eig(no, Ho, lo.data(), Uo.data(), Aex ? HoL.data() : nullptr)) return false;
   assemble_split(n, le, Ue, lo, Uo, lam, Q, fp);
   return true;
 }
@@ -343,6 +361,54 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
   return TS_OK;
 }
 
+// Eigenpairs of the symmetric form A + diag(f) (row-major n x n, A is
+// overwritten): exact symmetry imposed, the even and odd blocks solved apart
+// when the operator is reflection-symmetric, and the eigenvectors refined
+// against Aex + diag(f) (the operator before rounding, long double) when given.
+static bool massed_eig(int64_t n, std::vector<double>& A, std::vector<long double>* Aex, const double* f, bool reflect,
+                       double* lam, double* Q, FoldPlan& fp) {
+  for (int64_t i = 0; i < n; ++i) A[(size_t)(i * n + i)] += f[i];
+  for (int64_t i = 0; i < n; ++i)  // exact symmetry (the input is symmetric up to rounding)
+    for (int64_t j = 0; j < i; ++j) {
+      const double a = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
+      A[(size_t)(i * n + j)] = A[(size_t)(j * n + i)] = a;
+    }
+  if (Aex) {
+    auto& E = *Aex;
+    for (int64_t i = 0; i < n; ++i) E[(size_t)(i * n + i)] += f[i];
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < i; ++j)
+        E[(size_t)(i * n + j)] = E[(size_t)(j * n + i)] = 0.5L * (E[(size_t)(i * n + j)] + E[(size_t)(j * n + i)]);
+  }
+  return n >= 2 && reflect ? split_eig_dense(n, A, lam, Q, fp, Aex)
+                           : dense_sym_eig(n, A, lam, Q, Aex ? Aex->data() : nullptr);
+}
+
+// SEM axis operator M^{-1/2} S M^{-1/2}, formed in long double (Al) and
+// rounded once (A, and its band bsym); bphys = the band of M^{-1} S.
+static void sem_operator(const SemAxis& ax, std::vector<long double>& Al, std::vector<double>& A,
+                         std::vector<double>* bsym, std::vector<double>* bphys) {
+  const int64_t n = ax.n;
+  const int k = ax.k, w = 2 * k + 1;
+  std::vector<long double> msl(n);
+  Al.assign((size_t)(n * n), 0.0L);
+  A.assign((size_t)(n * n), 0.0);
+  if (bsym) bsym->assign((size_t)(n * w), 0.0);
+  if (bphys) bphys->assign((size_t)(n * w), 0.0);
+  for (int64_t i = 0; i < n; ++i) msl[i] = std::sqrt(ax.ml[i]);
+  for (int64_t i = 0; i < n; ++i)
+    for (int t = 0; t < w; ++t) {
+      const int64_t j = i - k + t;
+      if (j < 0 || j >= n) continue;
+      const long double sij = ax.Sl[(size_t)(i * w + t)];
+      const long double aij = sij / (msl[i] * msl[j]);
+      Al[(size_t)(i * n + j)] = aij;
+      A[(size_t)(i * n + j)] = (double)aij;
+      if (bsym) (*bsym)[(size_t)(i * w + t)] = (double)aij;
+      if (bphys) (*bphys)[(size_t)(i * w + t)] = (double)(sij / ax.ml[i]);
+    }
+}
+
 // Axis of a mass-weighted operator H = K + diag(f) with K self-adjoint in the
 // weights m (diag(m) K symmetric; Q^k SEM: K = M^{-1} S).  Q diagonalises the
 // symmetric A = M^{1/2} K M^{-1/2} + F (eq. (eigen_decomp)).
@@ -354,25 +420,17 @@ static int build_axis(int64_t n, double L, const double* f, std::shared_ptr<Axis
 static int build_axis_massed(int64_t n, double L, std::vector<double>& A, const std::vector<double>* bsym,
                              const std::vector<double>* bphys, int bw, const std::vector<double>& m,
                              const std::vector<double>& x, const double* f, bool reflect,
-                             std::shared_ptr<AxisFactor>& phys, std::shared_ptr<AxisFactor>& sym) {
+                             std::shared_ptr<AxisFactor>& phys, std::shared_ptr<AxisFactor>& sym,
+                             std::vector<long double>* Aex = nullptr) {
   std::vector<double> ms(n);
   for (int64_t i = 0; i < n; ++i) ms[i] = std::sqrt(m[i]);
-  for (int64_t i = 0; i < n; ++i) A[(size_t)(i * n + i)] += f[i];
-  for (int64_t i = 0; i < n; ++i)  // exact symmetry (the input is symmetric up to rounding)
-    for (int64_t j = 0; j < i; ++j) {
-      const double a = 0.5 * (A[(size_t)(i * n + j)] + A[(size_t)(j * n + i)]);
-      A[(size_t)(i * n + j)] = A[(size_t)(j * n + i)] = a;
-    }
   auto S = std::make_shared<AxisFactor>();
   S->n = n;
   S->L = L;
   S->lam_h.resize(n);
   S->Q_h.resize((size_t)(n * n));
   FoldPlan fp;
-  const bool split = n >= 2 && reflect;
-  const bool ok = split ? split_eig_dense(n, A, S->lam_h.data(), S->Q_h.data(), fp)
-                        : dense_sym_eig(n, A, S->lam_h.data(), S->Q_h.data());
-  if (!ok) {
+  if (!massed_eig(n, A, Aex, f, reflect, S->lam_h.data(), S->Q_h.data(), fp)) {
     set_error("symmetric eigensolver did not converge");
     return TS_ERR_INVALID;
   }
@@ -424,20 +482,12 @@ static int build_axis_sem(int k, int64_t cells, double L, const double* f, bool 
                           std::shared_ptr<AxisFactor>& sym) {
   SemAxis ax;
   if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis"); return TS_ERR_INVALID; }
-  const int64_t n = ax.n, w = 2 * k + 1;
-  std::vector<double> ms(n), A((size_t)(n * n), 0.0), bsym((size_t)(n * w), 0.0), bphys((size_t)(n * w), 0.0);
-  for (int64_t i = 0; i < n; ++i) ms[i] = std::sqrt(ax.m[i]);
-  for (int64_t i = 0; i < n; ++i)
-    for (int t = 0; t < w; ++t) {
-      const int64_t j = i - k + t;
-      if (j < 0 || j >= n) continue;
-      const double sij = ax.S[(size_t)(i * w + t)];
-      bsym[(size_t)(i * w + t)] = sij / (ms[i] * ms[j]);
-      bphys[(size_t)(i * w + t)] = sij / ax.m[i];
-      A[(size_t)(i * n + j)] = sij / (ms[i] * ms[j]);
-    }
+  const int64_t n = ax.n;
+  std::vector<long double> Al;
+  std::vector<double> A, bsym, bphys;
+  sem_operator(ax, Al, A, &bsym, &bphys);
   // the mesh is symmetric; with symmetric f the operator is reflection-symmetric
-  int rc = build_axis_massed(n, L, A, &bsym, &bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym);
+  int rc = build_axis_massed(n, L, A, &bsym, &bphys, k, ax.m, ax.x, f, symmetric_samples(n, f), phys, sym, &Al);
   if (rc || !op) return rc;
   rc = upload_op_pass(n, band_to_dense(n, k, bsym), sym->op_pass);
   if (rc) return rc;
@@ -1079,6 +1129,25 @@ int ts_sem_nodes(int k, int64_t cells, double L, double* x) {
   SemAxis ax;
   if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis (k in [1, 32], cells >= 1, L > 0)"); return TS_ERR_INVALID; }
   std::memcpy(x, ax.x.data(), sizeof(double) * (size_t)ax.n);
+  return TS_OK;
+}
+
+int ts_sem_axis_eig(int k, int64_t cells, double L, const double* f, double* lam, double* Q, double* m) {
+  if (!f || !lam || !Q) { set_error("null argument"); return TS_ERR_INVALID; }
+  SemAxis ax;
+  if (!sem_axis(k, cells, L, ax)) { set_error("bad SEM axis (k in [1, 32], cells >= 1, L > 0)"); return TS_ERR_INVALID; }
+  const int64_t n = ax.n;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(f[i])) { set_error("f has a non-finite entry"); return TS_ERR_NONFINITE; }
+  std::vector<long double> Al;
+  std::vector<double> A;
+  sem_operator(ax, Al, A, nullptr, nullptr);
+  FoldPlan fp;
+  if (!massed_eig(n, A, &Al, f, symmetric_samples(n, f), lam, Q, fp)) {
+    set_error("symmetric eigensolver did not converge");
+    return TS_ERR_NOCONV;
+  }
+  if (m) std::memcpy(m, ax.m.data(), sizeof(double) * (size_t)n);
   return TS_OK;
 }
 

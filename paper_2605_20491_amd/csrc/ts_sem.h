@@ -15,12 +15,15 @@ struct SemAxis {
   std::vector<double> x;       // interior nodes, ascending
   std::vector<double> m;       // lumped (Gauss-Lobatto) mass
   std::vector<double> S;       // stiffness band [n][2k+1]: S[i][i-k+t]
+  std::vector<long double> ml, Sl;  // the mass and the band before rounding
 };
 
-bool gll_rule(int k, double* xi, double* w);                 // k+1 nodes on [-1, 1]
-void gll_derivative(int k, const double* xi, double* D);     // (k+1)^2, D[i][j] = l_j'(xi_i)
+bool gll_rule(int k, long double* xi, long double* w);              // k+1 nodes on [-1, 1]
+void gll_derivative(int k, const long double* xi, long double* D);  // (k+1)^2, D[i][j] = l_j'(xi_i)
 bool sem_axis(int k, int64_t cells, double L, SemAxis& out);
-// Eigen-decomposition of a dense symmetric matrix (A is overwritten).
-bool dense_sym_eig(int64_t n, std::vector<double>& A, double* lam, double* Q);
+// Eigen-decomposition of a dense symmetric matrix (A is overwritten), refined
+// once against Aex (row-major n x n, the same operator in long double) or,
+// when Aex is null, against A as given.
+bool dense_sym_eig(int64_t n, std::vector<double>& A, double* lam, double* Q, const long double* Aex = nullptr);
 
 }  // namespace ts

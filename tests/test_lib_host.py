@@ -145,6 +145,56 @@ def test_dense_symmetric_eig_on_sem_axis(k, cells):
     assert np.max(np.abs(lam - w)) < 1e-13 * np.max(np.abs(w)) * np.sqrt(len(w))
 
 
+@pytest.mark.parametrize("k,cells", [(2, 20), (6, 9), (10, 5), (3, 8)])
+@pytest.mark.parametrize("sym", [True, False])
+def test_sem_axis_eig_matches_oracle(k, cells, sym):
+    """ts_sem_axis_eig (the eigen step of ts_setup_sem: long double assembly,
+    Householder + QL, one refinement step) against the oracle's Jacobi on the
+    oracle's own assembly: eigenvalues (relative to the largest), orthonormality,
+    the residual of the rounded operator, and the masses; a reflection-symmetric
+    f (solved as even and odd blocks) and one that is not."""
+    L = 4.0
+    x, m, S = oracle.sem_axis(k, cells, L)
+    f = W.f_harmonic(0, L, x=x) + (0.0 if sym else 0.3 * x)
+    lam, Q, mm = ts.ts_sem_axis_eig(k, cells, L, f)
+    assert np.max(np.abs(mm - m)) <= 1e-15 * np.max(m)
+    sq = np.sqrt(m)
+    A = S / np.outer(sq, sq) + np.diag(f)
+    w, _ = oracle.jacobi_eigh(0.5 * (A + A.T))
+    scale = np.max(np.abs(w))
+    n = len(w)
+    assert np.all(np.diff(lam) >= 0)
+    assert np.max(np.abs(lam - w)) < 1e-13 * scale * np.sqrt(n)
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) < 1e-14 * max(1, np.sqrt(n))
+    assert np.max(np.abs(A @ Q - Q * lam)) < 1e-14 * scale * max(1, np.sqrt(n))
+
+
+@pytest.mark.parametrize("cv,mode", [(1.0, 1), (2.0, 2), (3.0, 3)])
+def test_sem_axis_eig_reaches_the_discrete_floor(cv, mode):
+    """1D Q^10 on 110 cells of [-1, 1] (the axis of the FP64 floor rows of Table
+    tab:accuracy_gh200), V = c x^2, u* = sin(m pi x): the inverse formed from the
+    returned eigenpairs, u = M^{-1/2} Q diag(1/lam) Q^T M^{1/2} f with
+    f = ((m pi)^2 + V) u*, meets u* to 2e-14.  The discretisation error of this
+    mesh is below 1e-14; an eigendecomposition that is only backward stable in
+    double (residual ~ eps |A|, |A| / lam_min ~ 5e5) misses it by 1e-11."""
+    k, cells, L = 10, 110, 1.0
+    x = ts.ts_sem_nodes(k, cells, L)
+    V = cv * x ** 2
+    lam, Q, m = ts.ts_sem_axis_eig(k, cells, L, V)
+    ms = np.sqrt(m)
+    ustar = np.sin(mode * np.pi * x)
+    f = ((mode * np.pi) ** 2 + V) * ustar
+    u = (Q @ ((Q.T @ (ms * f)) / lam)) / ms
+    assert np.linalg.norm(u - ustar) / np.linalg.norm(ustar) <= 2e-14
+
+
+def test_sem_axis_eig_rejects_bad_arguments():
+    with pytest.raises(ts.TSError):
+        ts.ts_sem_axis_eig(40, 3, 1.0, np.zeros(119))
+    with pytest.raises(ts.TSError):
+        ts.ts_sem_axis_eig(2, 3, 1.0, np.full(5, np.nan))
+
+
 @pytest.mark.parametrize("n", [2, 3, 64, 65, 200, 501])
 def test_even_odd_tridiagonal_eig(n):
     """ts_tridiag_eig_even_odd on a reflection-symmetric FD operator: eigenvalues
