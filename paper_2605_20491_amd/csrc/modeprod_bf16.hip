@@ -564,7 +564,14 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
 // bitwise equal results.
 constexpr int BB = 256, NTB = 512;
 
-template <bool ROWS, int EPI, typename TOut>
+// F3: forward half-extent pass on data folded beforehand (s_i at row or
+// column i < h + c, d_i at n - 1 - i; see modeprod.hip): tiles [0, te) of the
+// output dimension take the even modes from the first h + c entries against
+// Fe, the others the odd modes from the last h entries against Fr (Fo with its
+// rows reversed), so each tile runs one half-size product.  Row passes then
+// move data and outputs in 8-byte pieces (the odd half starts at h, a multiple
+// of 4 but not always of 8).
+template <bool ROWS, int EPI, typename TOut, bool F3>
 __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ __attribute__((aligned(16))) uint16_t smem_big[4 * BB * LDK];
@@ -588,8 +595,19 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
     ntile = rest % a.nt;
     p = rest / a.nt;
   }
-  const int64_t K = a.n;
+  bool odd = false;
+  int64_t K = a.n, koff = 0, ldS = a.ld;
   const uint16_t* S = (const uint16_t*)a.S;
+  if (F3) {
+    int64_t& split = ROWS ? ntile : mtile;
+    odd = split >= a.te;
+    if (odd) split -= a.te;
+    const int64_t sh = (a.hh + a.cc) & 7;  // the odd half read from n - h - sh (a multiple of 8)
+    K = odd ? a.hh + sh : a.hh + a.cc;
+    koff = odd ? a.hh + a.cc - sh : 0;
+    S = (const uint16_t*)(odd ? a.So : a.Se);
+    ldS = a.fld;
+  }
   const int64_t m0 = mtile * BB, n0 = ntile * BB;
   const uint16_t* X = (const uint16_t*)a.X;
   const int64_t f0 = ROWS ? n0 : m0;  // first factor row of this tile
@@ -604,8 +622,8 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
   // rows or columns past the grid).
   auto load_factor = [&](int64_t k0, u32x4 (&rf)[4]) __attribute__((always_inline)) {
     const int row = t >> 1, half = t & 1;
-    const int64_t fr = f0 + row < a.ld ? f0 + row : a.ld - 1;
-    const u32x4* src = (const u32x4*)(S + fr * a.ld + k0 + 32 * half);
+    const int64_t fr = f0 + row < ldS ? f0 + row : ldS - 1;
+    const u32x4* src = (const u32x4*)(S + fr * ldS + k0 + 32 * half);
 #pragma unroll
     for (int i = 0; i < 4; ++i) rf[i] = src[i];
   };
@@ -617,12 +635,14 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t k = k0 + 4 * kq + r < K ? k0 + 4 * kq + r : K - 1;
-        rx[r] = *(const u32x4*)(X + (p * a.n + k) * a.R + col0);
+        rx[r] = *(const u32x4*)(X + (p * a.n + koff + k) * a.R + col0);
       }
     } else {
-      // rows m0 + 64 s + rg, k-chunk c of 8 (8 lanes per row: coalesced)
+      // rows m0 + 64 s + rg, k-chunk c of 8 (8 lanes per row: coalesced); with
+      // F3 the chunks of a half start at koff, a multiple of 8, and a chunk
+      // may reach past K into entries that meet zero factor columns
       const int c = t & 7, rg = t >> 3;
-      const int64_t kk = k0 + 8 * c < K ? k0 + 8 * c : K - 8;
+      const int64_t kk = koff + (k0 + 8 * c < K ? k0 + 8 * c : (K - 1) / 8 * 8);
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         const int64_t m = m0 + 64 * s2 + rg < a.M ? m0 + 64 * s2 + rg : a.M - 1;
@@ -743,8 +763,13 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
   }
 
   TOut* Y = (TOut*)a.Y;
-  const int64_t rowlen = ROWS ? a.n : a.R;   // outputs per output row
-  const int64_t nrows = ROWS ? a.M : a.n;    // output rows
+  static_assert(!F3 || std::is_same<TOut, uint16_t>::value, "folded passes write BF16");
+  // outputs of this tile's half: the first `cnt` of the split dimension are
+  // valid and land at `base` on (F3 odd tiles: after the ne even modes)
+  const int64_t cnt = F3 ? (odd ? a.no : a.ne) : a.n;
+  const int64_t base = F3 && odd ? a.ne : 0;
+  const int64_t rowlen = ROWS ? cnt : a.R;   // outputs per output row (within the half)
+  const int64_t nrows = ROWS ? a.M : cnt;    // output rows (within the half)
   if constexpr (std::is_same<TOut, uint16_t>::value) {
     // stage the BF16 tile in LDS (rows of 264 elements: 528 B) and write 16 bytes per 8 outputs
     constexpr int LT = BB + 8;
@@ -765,7 +790,7 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t m = m0 + wm * 128 + i * 16 + out_row<float>(lane, r);
-          tm[r] = m < a.n ? a.lam[m] + a.Lp[p] : 0.0;
+          tm[r] = m < cnt ? a.lam[base + m] + a.Lp[p] : 0.0;
         }
       }
 #pragma unroll
@@ -784,13 +809,24 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
         }
     }
     __syncthreads();
+    if (ROWS && F3) {
+      // 8 bytes per 4 outputs: the odd half starts at column ne (a multiple of 4)
 #pragma unroll
-    for (int q = 0; q < (BB * BB / 8) / NTB; ++q) {
-      const int idx = q * NTB + t, lrow = idx >> 5, ch = idx & 31;
-      const int64_t mg = m0 + lrow, cg = n0 + 8 * ch;
-      if (mg >= nrows || cg >= rowlen) continue;
-      const int64_t base = ROWS ? mg * a.n : (p * a.n + mg) * a.R;
-      *(uint4*)(Y + base + cg) = *(const uint4*)&Ts[lrow * LT + 8 * ch];
+      for (int q = 0; q < (BB * BB / 4) / NTB; ++q) {
+        const int idx = q * NTB + t, lrow = idx >> 6, ch = idx & 63;
+        const int64_t mg = m0 + lrow, cg = n0 + 4 * ch;
+        if (mg >= nrows || cg >= rowlen) continue;
+        *(uint2*)(Y + mg * a.n + base + cg) = *(const uint2*)&Ts[lrow * LT + 4 * ch];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < (BB * BB / 8) / NTB; ++q) {
+        const int idx = q * NTB + t, lrow = idx >> 5, ch = idx & 31;
+        const int64_t mg = m0 + lrow, cg = n0 + 8 * ch;
+        if (mg >= nrows || cg >= rowlen) continue;
+        const int64_t off = ROWS ? mg * a.n : (p * a.n + base + mg) * a.R;
+        *(uint4*)(Y + off + cg) = *(const uint4*)&Ts[lrow * LT + 8 * ch];
+      }
     }
   } else {
 #pragma unroll
@@ -820,6 +856,7 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
 template <typename TIn>
 bool bf16_big_ok(const KArgs& a, const PassArgs& pa, int fold) {
   if (!std::is_same<TIn, uint16_t>::value || pa.cplx || fold || pa.epi == Epi::Exp) return false;
+  if (a.rows && pa.epi != Epi::None) return false;  // the row instance has no scaling epilogue
   if (pa.bf16_tile == 128) return false;
   if ((((uintptr_t)a.X) & 15) != 0 || (((uintptr_t)a.Y) & 15) != 0) return false;
   if ((a.rows ? a.n : a.R) % 8 != 0 || a.n < 192) return false;
@@ -828,6 +865,20 @@ bool bf16_big_ok(const KArgs& a, const PassArgs& pa, int fold) {
   if (pad256 * 10 > pad128 * 11) return false;
   const int64_t mt = (a.M + BB - 1) / BB, nt = (a.N + BB - 1) / BB;
   return mt * nt * (a.rows ? 1 : pa.P) >= 256;
+}
+
+// Whether a forward pass on data folded beforehand runs on the 256 x 256 tiles
+// (the only BF16 kernel with that input layout): real BF16 data in and out,
+// 16-byte aligned buffers, a reflection-symmetric axis of n >= 192, no
+// scaling epilogue on a row pass, and rows of a multiple of 8 values; a row
+// pass also needs n % 8 == 0, so that both halves start on 4-value boundaries.
+bool fold3_ok(const KArgs& a, const PassArgs& pa) {
+  const AxisFactor* F = pa.fac;
+  if (pa.tin != DT::BF16 || pa.tout != DT::BF16 || pa.cplx || pa.epi == Epi::Exp || !pa.forward) return false;
+  if (!F->fold || !F->Fe16w || !F->Fr16w || pa.bf16_tile == 128 || a.n < 192) return false;
+  if ((((uintptr_t)a.X) & 15) != 0 || (((uintptr_t)a.Y) & 15) != 0) return false;
+  if (a.rows) return pa.epi == Epi::None && a.n % 8 == 0;
+  return a.R % 8 == 0;
 }
 
 template <typename TOut>
@@ -839,11 +890,45 @@ hipError_t launch_bf16_big(KArgs a, const PassArgs& pa, hipStream_t st) {
   if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)a.nblocks), block(NTB);
   if (a.rows) {
-    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut, false>), grid, block, 0, st, a);
   } else if (pa.epi == Epi::Inv) {
-    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, TOut>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, TOut, false>), grid, block, 0, st, a);
   } else {
-    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut, false>), grid, block, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+// Forward pass on folded data: the split dimension holds ceil(ne / 256) even
+// tiles followed by ceil(no / 256) odd ones.
+hipError_t launch_bf16_big_fold3(KArgs a, const PassArgs& pa, hipStream_t st) {
+  const AxisFactor* F = pa.fac;
+  a.ne = F->ne;
+  a.no = F->no;
+  a.hh = F->hh;
+  a.cc = F->cc;
+  a.fld = F->fldw;
+  a.Se = F->Fe16w;
+  a.So = F->Fr16w;
+  a.te = (F->ne + BB - 1) / BB;
+  const int64_t split = a.te + (F->no + BB - 1) / BB;
+  if (a.rows) {
+    a.mt = (a.M + BB - 1) / BB;
+    a.nt = split;
+  } else {
+    a.mt = split;
+    a.nt = (a.N + BB - 1) / BB;
+  }
+  a.nblocks = a.mt * a.nt * (a.rows ? 1 : pa.P);
+  if (a.nblocks <= 0) return hipSuccess;
+  if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)a.nblocks), block(NTB);
+  if (a.rows) {
+    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, uint16_t, true>), grid, block, 0, st, a);
+  } else if (pa.epi == Epi::Inv) {
+    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, uint16_t, true>), grid, block, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, uint16_t, true>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -922,6 +1007,11 @@ hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
   KArgs a{};
   const AxisFactor* F = pa.fac;
   fill_kargs(pa, a, pa.forward ? (const void*)F->QT16 : (const void*)F->Q16, BM, BN);
+  if (pa.fold && pa.deferred) {
+    // data folded beforehand: only the 256 x 256 tiles read that layout
+    if (!fold3_ok(a, pa)) return hipErrorInvalidValue;
+    return launch_bf16_big_fold3(a, pa, st);
+  }
   const int fold = (pa.fold && !bf16_coalesced<TIn>(a, pa)) ? (pa.forward ? 1 : 2) : 0;
   if (bf16_big_ok<TIn>(a, pa, fold)) return launch_bf16_big<TOut>(a, pa, st);
   if (fold) {
@@ -957,7 +1047,113 @@ hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Input of a BF16 apply whose forward passes read folded data: the
+// butterfly s_i = x_i + x_{n-1-i} (at i), d_i = x_i - x_{n-1-i} (at n-1-i)
+// along every listed axis, taken in FP64 on the FP64 input, each result then
+// rounded FP64 -> FP32 -> BF16 as the unfolded input sweep rounds its values.
+// One thread per orbit of the reflections (a point with i_a <= n_a - 1 - i_a
+// on every listed axis, fastest axis first); an axis on which the point is its
+// own mirror (the middle of odd n) leaves it as it is.
+template <int NAX>
+__global__ __launch_bounds__(256) void k_fold_to_bf16(const double* X, uint16_t* Y, ButterflyArgs a, int64_t total) {
+  if (a.skip && *a.skip) return;
+  constexpr int NV = 1 << NAX;
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int64_t rest = e, off = 0, stride = 1;
+    int64_t delta[NAX];
+    bool act[NAX];
+#pragma unroll
+    for (int j = 0; j < NAX; ++j) {
+      delta[j] = 0;
+      act[j] = false;
+    }
+    for (int k = a.d - 1; k >= 0; --k) {
+      int jf = -1;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (a.ax[j] == k) jf = j;
+      const int64_t ext = jf >= 0 ? a.n[k] - a.hh[jf] : a.n[k];
+      const int64_t q = rest / ext;
+      const int64_t i = rest - q * ext;
+      rest = q;
+      off += i * stride;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (j == jf && i < a.hh[j]) {
+          act[j] = true;
+          delta[j] = (a.n[k] - 1 - 2 * i) * stride;
+        }
+      stride *= a.n[k];
+    }
+    double v[NV];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      v[m] = ok ? X[o] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NAX; ++j) {
+      if (!act[j]) continue;
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (!(m & (1 << j))) {
+          const double x0 = v[m], x1 = v[m | (1 << j)];
+          v[m] = x0 + x1;
+          v[m | (1 << j)] = x0 - x1;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      if (ok) Y[o] = cvt_out<uint16_t>(v[m]);
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fold_to_bf16(const ButterflyArgs& a, hipStream_t st) {
+  if (a.ncomp != 1) return hipErrorInvalidValue;
+  int64_t total = 1;
+  for (int k = 0; k < a.d; ++k) {
+    int64_t ext = a.n[k];
+    for (int j = 0; j < a.nax; ++j)
+      if (a.ax[j] == k) ext = a.n[k] - a.hh[j];
+    total *= ext;
+  }
+  if (total <= 0) return hipSuccess;
+  const double* X = (const double*)a.X;
+  uint16_t* Y = (uint16_t*)a.Y;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  switch (a.nax) {
+    case 1: hipLaunchKernelGGL((k_fold_to_bf16<1>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    case 2: hipLaunchKernelGGL((k_fold_to_bf16<2>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    case 3: hipLaunchKernelGGL((k_fold_to_bf16<3>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    case 4: hipLaunchKernelGGL((k_fold_to_bf16<4>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool bf16_fold_pass_ok(const PassArgs& pa) {
+  KArgs a{};
+  fill_kargs(pa, a, pa.fac->QT16, BM, BN);
+  return fold3_ok(a, pa);
+}
 
 hipError_t launch_pass_bf16(const PassArgs& pa, hipStream_t st) {
   // intermediates are BF16; the first pass may read FP64/FP32 and the last write FP64/FP32

@@ -47,6 +47,8 @@ AxisFactor::~AxisFactor() {
   hipFree(Fo16);
   hipFree(Be16);
   hipFree(Bo16);
+  hipFree(Fe16w);
+  hipFree(Fr16w);
   hipFree(mass);
   hipFree(msq);
   hipFree(imsq);
@@ -277,6 +279,7 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
   if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(F.QT64, F.Q16, F.ld, st);
   // half factors of a symmetric axis
   std::vector<double> H[5];
+  std::vector<uint16_t> Hw[2];
   if (e == hipSuccess && fp.on) {
     F.fold = true;
     F.ne = fp.ne;
@@ -309,6 +312,21 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
       if (e == hipSuccess) e = launch_cast_f64_to_f32(*d64[q], *d32[q], (int64_t)cnt, st);
       if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(*d64[q], *d16[q], kp, st);
     }
+    // wide BF16 copies for the 256 x 256-tile forward pass on folded data
+    const int64_t sh = (fp.hh + fp.cc) % 8, lw = round_up(fp.hh + 8, kTileF);
+    F.fldw = lw;
+    Hw[0].assign((size_t)(lw * lw), 0);
+    Hw[1].assign((size_t)(lw * lw), 0);
+    for (int64_t j = 0; j < fp.ne; ++j)
+      for (int64_t i = 0; i < fp.hh + fp.cc; ++i) Hw[0][(size_t)(j * lw + i)] = bf16_from_f64(H[0][(size_t)(i * kp + j)]);
+    for (int64_t j = 0; j < fp.no; ++j)
+      for (int64_t r = 0; r < fp.hh; ++r) Hw[1][(size_t)(j * lw + r + sh)] = bf16_from_f64(H[4][(size_t)(r * kp + j)]);
+    if (e == hipSuccess) e = hipMalloc(&F.Fe16w, sizeof(uint16_t) * (size_t)(lw * lw));
+    if (e == hipSuccess) e = hipMalloc(&F.Fr16w, sizeof(uint16_t) * (size_t)(lw * lw));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(F.Fe16w, Hw[0].data(), sizeof(uint16_t) * Hw[0].size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(F.Fr16w, Hw[1].data(), sizeof(uint16_t) * Hw[1].size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMalloc(&F.Fr64, sizeof(double) * cnt);
     if (e == hipSuccess) e = hipMalloc(&F.Fr32, sizeof(float) * cnt);
     if (e == hipSuccess) e = hipMemcpyAsync(F.Fr64, H[4].data(), sizeof(double) * cnt, hipMemcpyHostToDevice, st);
@@ -587,7 +605,7 @@ size_t plan_device_bytes(const ts_plan* p) {
     b += (size_t)(F->kpad * F->ld) * (8 + 8 + 4 + 4 + 2 + 2);
     b += sizeof(double) * (size_t)F->n * (F->msq ? 5 : 3);
     if (F->band) b += sizeof(double) * (size_t)F->n * (2 * F->bw + 1);
-    if (F->fold) b += (size_t)(F->fkp * F->fkp) * (5 * 8 + 5 * 4 + 4 * 2);
+    if (F->fold) b += (size_t)(F->fkp * F->fkp) * (5 * 8 + 5 * 4 + 4 * 2) + (size_t)(F->fldw * F->fldw) * 2 * 2;
     add(F->op_pass.get());
   };
   for (const auto& F : p->ax) add(F.get());
@@ -712,6 +730,43 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     if (rc) return rc;
     src = ap.out;
   }
+  // BF16 transforms of FP64 data: the input sweep also folds the data along
+  // the symmetric axes whose forward pass can read folded data (256 x 256
+  // tiles), and those forward passes contract half the extent; the backward
+  // passes run over the full extent on the spectral [even | odd] order, which
+  // needs no unfolding afterwards.
+  int bax[4];
+  int nb = 0;
+  if (p->fold_enabled && ap.prec == TS_PREC_BF16 && !cplx && !ap.in_rounded && ap.tin == DT::F64 &&
+      ap.tout == DT::F64 && ap.in != ap.out && ap.epi != Epi::Exp && p->N % 4 == 0 &&
+      ((((uintptr_t)ap.in) & 15) == 0)) {
+    for (int k = d - 1; k >= 0 && nb < 4; --k) {
+      const AxisFactor* F = (ap.sym ? p->ax_sym : p->ax)[k].get();
+      if (!F->fold) continue;
+      PassArgs q;
+      q.X = ap.out;
+      q.Y = ap.work;
+      q.tin = DT::BF16;
+      q.tout = DT::BF16;
+      q.prec = ap.prec;
+      q.fac = F;
+      q.forward = true;
+      q.n = p->n[k];
+      q.P = 1;
+      for (int m = 0; m < k; ++m) q.P *= p->n[m];
+      q.R = 1;
+      for (int m = k + 1; m < d; ++m) q.R *= p->n[m];
+      q.epi = k == p->s ? ap.epi : Epi::None;
+      q.bf16_tile = p->bf16_tile;
+      const bool ok = bf16_fold_pass_ok(q) && ((((uintptr_t)ap.work) & 15) == 0) && ((((uintptr_t)ap.out) & 15) == 0);
+      if (ok) bax[nb++] = k;
+    }
+  }
+  auto bf16_folded = [&](int k) {
+    for (int j = 0; j < nb; ++j)
+      if (bax[j] == k) return true;
+    return false;
+  };
   // BF16 transforms of FP64 data: round the input to BF16 in one streaming
   // sweep (into the output buffer, which the last pass overwrites), so that
   // the first pass reads 2 instead of 8 bytes per value (rounded as the pass
@@ -719,6 +774,27 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   const int64_t Ntot = p->N * ncomp;
   if (ap.in_rounded) {
     // the caller's producer of the input already wrote its BF16 rounding to out
+    src = ap.out;
+    src_t = DT::BF16;
+  } else if (nb > 0) {
+    ButterflyArgs b;
+    b.X = ap.in;
+    b.Y = ap.out;
+    b.t = DT::F64;
+    b.d = d;
+    b.ncomp = 1;
+    for (int k = 0; k < d; ++k) b.n[k] = p->n[k];
+    b.nax = nb;
+    for (int j = 0; j < nb; ++j) {
+      b.ax[j] = bax[j];
+      b.hh[j] = p->n[bax[j]] / 2;
+    }
+    b.skip = ap.skip;
+    hipError_t e = launch_fold_to_bf16(b, st);
+    if (e != hipSuccess) {
+      set_error(std::string("BF16 folding launch failed: ") + hipGetErrorString(e));
+      return TS_ERR_DEVICE;
+    }
     src = ap.out;
     src_t = DT::BF16;
   } else if (ap.prec == TS_PREC_BF16 && ap.tin == DT::F64 && ap.in != ap.out && Ntot % 4 == 0 &&
@@ -751,10 +827,12 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     for (int m = k + 1; m < d; ++m) pa.R *= p->n[m];
     pa.cplx = cplx;
     pa.skip = ap.skip;
-    // BF16 passes are not MFMA-bound: folding saves them no time (the butterfly and
-    // the mirror loads cost more than the halved MFMA work), so BF16 applies do not fold
+    // BF16 passes fold only as forward passes on data the input sweep folded
+    // (above): folding while loading (mirror loads) and a butterfly after each
+    // backward pass cost the 128 x 128 BF16 tiles more than the halved products
     pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
     pa.deferred = deferred && pa.fold;
+    if (ap.prec == TS_PREC_BF16 && fwd && bf16_folded(k)) pa.fold = pa.deferred = true;
     pa.bf16_tile = p->bf16_tile;
     if (fwd && t == d) {
       pa.epi = ap.epi;

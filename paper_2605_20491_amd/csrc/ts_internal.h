@@ -77,6 +77,12 @@ struct AxisFactor {
   float* Fr32 = nullptr;
   // BF16, K-contiguous (transposed) copies of Fe, Fo, Be, Bo for the BF16 passes
   uint16_t *Fe16 = nullptr, *Fo16 = nullptr, *Be16 = nullptr, *Bo16 = nullptr;
+  // BF16 forward pass on folded data, [fldw][fldw], K-contiguous: Fe (K from
+  // 0), and Fr with its K index shifted by sh = (h + c) % 8 (column k holds
+  // Fr row k - sh; the pass reads the odd half from n - h - sh, a multiple of
+  // 8, and the sh even entries it takes along meet zero columns)
+  uint16_t *Fe16w = nullptr, *Fr16w = nullptr;
+  int64_t fldw = 0;
   std::vector<double> lam_int_h;  // eigenvalues in the internal spectral order
   // Generic plans whose operator band is wide: the axis operator itself as an
   // FP64 pass factor (Q64 holds W with y_j = sum_i W[i][j] x_i, i.e. y = B x),
@@ -120,6 +126,9 @@ struct PassArgs {
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);
 hipError_t launch_pass_bf16(const PassArgs& a, hipStream_t st);
+// Whether a forward BF16 pass can read data folded beforehand (pa.fold and
+// pa.deferred set): the 256 x 256-tile kernel is the only one with that layout.
+bool bf16_fold_pass_ok(const PassArgs& pa);
 
 // Butterfly y_i, y_{n-1-i} = x_i + x_{n-1-i}, x_i - x_{n-1-i} (i < hh), in
 // place or not, along up to four axes of a [n_0]...[n_{d-1}][ncomp] array at once
@@ -137,6 +146,9 @@ struct ButterflyArgs {
   const int* skip = nullptr;    // if non-null and *skip != 0 the kernel returns
 };
 hipError_t launch_butterfly(const ButterflyArgs& a, hipStream_t st);
+// The same butterflies on FP64 data a.X written as BF16 to a.Y (a BF16 apply's
+// input sweep when its forward passes read folded data); real data only.
+hipError_t launch_fold_to_bf16(const ButterflyArgs& a, hipStream_t st);
 
 // Phase tables for the propagator: es[j] = e^{-i tau lam_s[j]},
 // Ep[p] = prod_{m<s} e^{-i tau lam_m[j_m(p)]}, Er[q] = prod_{m>s} (...).

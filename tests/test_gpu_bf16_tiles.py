@@ -2,14 +2,20 @@
 
 The larger tile halves the operand traffic from L2 but consumes K in the same
 order (64-wide k-tiles, two 32-wide MFMA steps each) as the 128 x 128 kernel,
-so every BF16 apply must give bitwise equal results under both tiles: the
-plain, scaling and last passes, BF16 / FP32 / FP64 outputs, ragged tiles
-(n = 200, 264 against 256-wide tiles) and factor rows beyond the stored
-padding (n = 264 keeps 384 padded rows against 512 tile rows).  The default
-choice is checked against the FP64 oracle at the BF16 level (parity unpinned:
-BF16 operands have no exact value, the bar is the one of the other BF16
-tests), and the PCG with a BF16 preconditioner on the large tiles still
+so without folding every BF16 apply must give bitwise equal results under
+both tiles: the plain, scaling and last passes, BF16 / FP32 / FP64 outputs,
+ragged tiles (n = 200, 264 against 256-wide tiles) and factor rows beyond the
+stored padding (n = 264 keeps 384 padded rows against 512 tile rows).  The
+default choice is checked against the FP64 oracle at the BF16 level (parity
+unpinned: BF16 operands have no exact value, the bar is the one of the other
+BF16 tests), and the PCG with a BF16 preconditioner on the large tiles still
 reaches the FP64 residual bar.
+
+On reflection-symmetric axes the large tiles also run the forward passes on
+data folded by the input sweep (half the extent; the odd half of an axis with
+h = n / 2 = 4 mod 8 is read from n - h - 4 against a factor shifted by 4):
+checked against the oracle and against the same apply with folding off, with
+even and odd extents, ragged half-tiles and the shifted case.
 """
 import numpy as np
 import pytest
@@ -36,6 +42,7 @@ def to_host(t):
 def test_large_and_small_tiles_bitwise_equal(shape):
     # library plan only: no oracle value is needed for a comparison of two kernels
     plan = ts.ts_setup(shape, 8.0, [W.f_harmonic(n, 8.0) for n in shape], 1.0)
+    ts.ts_set_fold(plan, 0)  # folded passes exist only on the large tiles
     b = to_dev(W.rhs_normal(shape, 21))
     for dt in (torch.float64, torch.float32):
         x = b.to(dt)
@@ -82,3 +89,30 @@ def test_pcg_bf16_preconditioner_on_large_tiles():
     true = np.linalg.norm(rhs - oracle.stencil_apply(op, to_host(u), V2, sigma)) / np.linalg.norm(rhs)
     announce("PCG bf16 preconditioner 256^3: %d iterations, recurrence %.2e, true residual %.2e" % (its, relres, true))
     assert true <= 1.05e-10
+
+
+@pytest.mark.parametrize("shape", [(200, 256, 264), (257, 200, 256), (400, 264)])
+def test_folded_forward_passes(shape):
+    """BF16 inverse of FP64 data on symmetric axes: the input sweep folds along
+    every axis whose forward pass reads folded data and those passes contract
+    half the extent.  n = 200, 264: h = 4 mod 8 (the shifted odd half); 257:
+    odd extent on a column axis (the middle value stays unfolded), 256: h = 0
+    mod 8; ragged half-tiles against 256-wide tiles everywhere.  Against the
+    oracle at the BF16 level, and against the same apply with folding off (a
+    different rounding of the same products)."""
+    plan, oplan, _ = make_pair(shape, 8.0, "harm", sigma=1.0)
+    b = W.rhs_normal(shape, 23)
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    bd = to_dev(b)
+    u = to_host(ts.ts_apply_inverse(plan, bd, prec="bf16"))
+    ush = to_host(ts.ts_apply_inverse_shift(plan, 2.5, bd, prec="bf16"))
+    ref_sh = oracle.apply_inverse(oplan, b, 2.5)
+    ts.ts_set_fold(plan, 0)
+    u0 = to_host(ts.ts_apply_inverse(plan, bd, prec="bf16"))
+    ts.ts_set_fold(plan, 1)
+    e, em, e_sh, e0, ed = rel(u, ref), maxrel(u, ref), rel(ush, ref_sh), rel(u0, ref), rel(u, u0)
+    announce("bf16 folded %s: rel err %.3e (max-norm %.3e), shifted %.3e, unfolded %.3e, between %.3e"
+             % (shape, e, em, e_sh, e0, ed))
+    assert 1e-3 < e <= 1.5e-2 and em <= 5e-2 and e_sh <= 1.5e-2
+    assert ed <= 1.5e-2 and not np.array_equal(u, u0)
+    assert np.array_equal(to_host(bd), b)
