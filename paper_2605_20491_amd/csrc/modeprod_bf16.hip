@@ -99,6 +99,26 @@ template <> __device__ __forceinline__ uint16_t fold_add<uint16_t>(uint16_t x, u
 // consecutive elements of one row (cols: one k-row of the tile; rows: one data
 // row), so every load instruction is coalesced.  A separate instance keeps the
 // 16-byte paths free of its registers.
+// Two accumulators of a staged BF16 output (rows r and r + 1 of one column),
+// rounded to nearest even by the packed conversion of gfx950 (the rounding
+// of f32_to_bf16 for finite values, in one instruction).  Scaling pass: each
+// is first multiplied by the reciprocal of its FP64 denominator rounded to
+// FP32 (v_rcp_f32, within 1 ulp), i.e. within about 2^-22 of the FP64
+// quotient, far below the BF16 step; a division, FP64 or FP32, would cost the
+// epilogue more than the pass's products.  Entries outside the grid are
+// staged and never written.
+template <int EPI>
+__device__ __forceinline__ uint32_t stage_pair(float v0, float v1, double den0, double den1) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  if (EPI == (int)Epi::Inv) {
+    v0 *= __builtin_amdgcn_rcpf((float)den0);
+    v1 *= __builtin_amdgcn_rcpf((float)den1);
+  }
+  const f32x2 v = {v0, v1};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
 template <typename TIn, typename TOut, bool ROWS, bool CPLX, int EPI, int FOLD, bool COAL>
 __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
   if (a.skip && *a.skip) return;
@@ -438,16 +458,12 @@ __global__ __launch_bounds__(NT, 2) void k_mode_bf16(KArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4; r += 2) {
           const int ml = wm * 64 + i * 16 + out_row<float>(lane, r), cl = wn * 64 + j * 16 + lr;
-          // BF16 output: the FP64 denominator, rounded to FP32, divides the FP32
-          // accumulator in FP32 (correctly rounded) before the rounding to BF16;
-          // the quotient is within about 2^-23 of the FP64 one, far below the BF16
-          // step, and the FP64 division would cost this epilogue more than the
-          // pass's products (entries outside the grid are staged, never written)
-          float v = acc[i][j][r];
-          if (EPI == (int)Epi::Inv) v = v / (float)(tm[r] + tr[j] + a.shift);
-          Ts[ml * LT + cl] = f32_to_bf16(v);
+          const uint32_t w = stage_pair<EPI>(acc[i][j][r], acc[i][j][r + 1], tm[r] + tr[j] + a.shift,
+                                             tm[r + 1] + tr[j] + a.shift);
+          Ts[ml * LT + cl] = (uint16_t)w;  // rows ml and ml + 1 (out_row of r and r + 1)
+          Ts[(ml + 1) * LT + cl] = (uint16_t)(w >> 16);
         }
     }
     __syncthreads();
@@ -796,16 +812,12 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < 4; r += 2) {
           const int ml = wm * 128 + i * 16 + out_row<float>(lane, r), cl = wn * 64 + j * 16 + lr;
-          // BF16 output: the FP64 denominator, rounded to FP32, divides the FP32
-          // accumulator in FP32 (correctly rounded) before the rounding to BF16;
-          // the quotient is within about 2^-23 of the FP64 one, far below the BF16
-          // step, and the FP64 division would cost this epilogue more than the
-          // pass's products (entries outside the grid are staged, never written)
-          float v = acc[i][j][r];
-          if (EPI == (int)Epi::Inv) v = v / (float)(tm[r] + tr[j] + a.shift);
-          Ts[ml * LT + cl] = f32_to_bf16(v);
+          const uint32_t w = stage_pair<EPI>(acc[i][j][r], acc[i][j][r + 1], tm[r] + tr[j] + a.shift,
+                                             tm[r + 1] + tr[j] + a.shift);
+          Ts[ml * LT + cl] = (uint16_t)w;  // rows ml and ml + 1 (out_row of r and r + 1)
+          Ts[(ml + 1) * LT + cl] = (uint16_t)(w >> 16);
         }
     }
     __syncthreads();
@@ -1124,6 +1136,121 @@ __global__ __launch_bounds__(256) void k_fold_to_bf16(const double* X, uint16_t*
   }
 }
 
+// The same with four consecutive points of the fastest axis per thread
+// (n_{d-1} % 8 == 0): 16-byte loads, 8-byte stores.  With the fastest axis
+// folded (FAST), the group 4q .. 4q + 3 of its lower half pairs with the
+// mirror group n - 4 - 4q .. n - 1 - 4q in reverse order; the other listed
+// axes (slots 0 .. NAX - 1 of a.ax, the fastest one excluded) as above.
+template <int NAX, bool FAST>
+__global__ __launch_bounds__(256) void k_fold_to_bf16_x4(const double* X, uint16_t* Y, ButterflyArgs a, int64_t total) {
+  if (a.skip && *a.skip) return;
+  constexpr int NB = NAX + (FAST ? 1 : 0);  // orbit bits: the slow axes, then the fastest
+  constexpr int NV = 1 << NB;
+  const int64_t nf = a.n[a.d - 1];
+  const int64_t gq = (FAST ? nf / 2 : nf) / 4;  // groups of 4 along the fastest axis
+  for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    int64_t rest = e / gq;
+    const int64_t q = e - rest * gq;
+    int64_t off = 4 * q, stride = nf;
+    int64_t delta[NB > 0 ? NB : 1];
+    bool act[NB > 0 ? NB : 1];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      delta[j] = 0;
+      act[j] = false;
+    }
+    if (FAST) {
+      act[NB - 1] = true;
+      delta[NB - 1] = nf - 4 - 8 * q;  // start of the mirror group
+    }
+    for (int k = a.d - 2; k >= 0; --k) {
+      int jf = -1;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (a.ax[j] == k) jf = j;
+      const int64_t ext = jf >= 0 ? a.n[k] - a.hh[jf] : a.n[k];
+      const int64_t qq = rest / ext;
+      const int64_t i = rest - qq * ext;
+      rest = qq;
+      off += i * stride;
+#pragma unroll
+      for (int j = 0; j < NAX; ++j)
+        if (j == jf && i < a.hh[j]) {
+          act[j] = true;
+          delta[j] = (a.n[k] - 1 - 2 * i) * stride;
+        }
+      stride *= a.n[k];
+    }
+    double v[NV][4];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      double2 lo = make_double2(0.0, 0.0), hi = make_double2(0.0, 0.0);
+      if (ok) {
+        lo = *(const double2*)(X + o);
+        hi = *(const double2*)(X + o + 2);
+      }
+      v[m][0] = lo.x;
+      v[m][1] = lo.y;
+      v[m][2] = hi.x;
+      v[m][3] = hi.y;
+    }
+    if (FAST) {
+      constexpr int fb = FAST ? 1 << (NB - 1) : 0;
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (!(m & fb)) {
+          double t0[4], t1[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            t0[c] = v[m][c] + v[m | fb][3 - c];
+            t1[3 - c] = v[m][c] - v[m | fb][3 - c];
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            v[m][c] = t0[c];
+            v[m | fb][c] = t1[c];
+          }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NAX; ++j) {
+      if (!act[j]) continue;
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (!(m & (1 << j))) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double x0 = v[m][c], x1 = v[m | (1 << j)][c];
+            v[m][c] = x0 + x1;
+            v[m | (1 << j)][c] = x0 - x1;
+          }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      if (ok)
+        *(uint2*)(Y + o) = make_uint2((uint32_t)cvt_out<uint16_t>(v[m][0]) | ((uint32_t)cvt_out<uint16_t>(v[m][1]) << 16),
+                                      (uint32_t)cvt_out<uint16_t>(v[m][2]) | ((uint32_t)cvt_out<uint16_t>(v[m][3]) << 16));
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_fold_to_bf16(const ButterflyArgs& a, hipStream_t st) {
@@ -1138,6 +1265,40 @@ hipError_t launch_fold_to_bf16(const ButterflyArgs& a, hipStream_t st) {
   if (total <= 0) return hipSuccess;
   const double* X = (const double*)a.X;
   uint16_t* Y = (uint16_t*)a.Y;
+  // four points of the fastest axis per thread: 16-byte aligned input rows and
+  // groups that never straddle the middle of a folded fastest axis
+  const int64_t nf = a.n[a.d - 1];
+  int jl = -1;
+  for (int j = 0; j < a.nax; ++j)
+    if (a.ax[j] == a.d - 1) jl = j;
+  if (nf % 8 == 0 && ((((uintptr_t)X) & 15) == 0) && ((((uintptr_t)Y) & 7) == 0)) {
+    ButterflyArgs b = a;  // the slow axes in slots 0 .. nslow - 1
+    int nslow = 0;
+    for (int j = 0; j < a.nax; ++j)
+      if (j != jl) {
+        b.ax[nslow] = a.ax[j];
+        b.hh[nslow] = a.hh[j];
+        ++nslow;
+      }
+    const int64_t units = total / 4;
+    const unsigned blocks = (unsigned)std::min<int64_t>((units + 255) / 256, 1 << 20);
+#define TS_FOLD_X4(N)                                                                                       \
+  if (jl >= 0)                                                                                            \
+    hipLaunchKernelGGL((k_fold_to_bf16_x4<N, true>), dim3(blocks), dim3(256), 0, st, X, Y, b, units);    \
+  else                                                                                                    \
+    hipLaunchKernelGGL((k_fold_to_bf16_x4<N, false>), dim3(blocks), dim3(256), 0, st, X, Y, b, units);
+    switch (nslow) {
+      case 0:  // only the fastest axis is listed
+        hipLaunchKernelGGL((k_fold_to_bf16_x4<0, true>), dim3(blocks), dim3(256), 0, st, X, Y, b, units);
+        break;
+      case 1: TS_FOLD_X4(1) break;
+      case 2: TS_FOLD_X4(2) break;
+      case 3: TS_FOLD_X4(3) break;
+      default: return hipErrorInvalidValue;
+    }
+#undef TS_FOLD_X4
+    return hipGetLastError();
+  }
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
   switch (a.nax) {
     case 1: hipLaunchKernelGGL((k_fold_to_bf16<1>), dim3(blocks), dim3(256), 0, st, X, Y, a, total); break;

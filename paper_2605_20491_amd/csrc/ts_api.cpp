@@ -47,7 +47,7 @@ AxisFactor::~AxisFactor() {
   hipFree(Fo16);
   hipFree(Be16);
   hipFree(Bo16);
-  hipFree(Fe16w);
+  if (Fe16w != Fe16) hipFree(Fe16w);  // the same array when the widths agree
   hipFree(Fr16w);
   hipFree(mass);
   hipFree(msq);
@@ -312,19 +312,28 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
       if (e == hipSuccess) e = launch_cast_f64_to_f32(*d64[q], *d32[q], (int64_t)cnt, st);
       if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(*d64[q], *d16[q], kp, st);
     }
-    // wide BF16 copies for the 256 x 256-tile forward pass on folded data
-    const int64_t sh = (fp.hh + fp.cc) % 8, lw = round_up(fp.hh + 8, kTileF);
+    // BF16 factors of the 256 x 256-tile forward pass on folded data: Fe, and
+    // Fr with its K index shifted by sh, both K-contiguous with a common width
+    // covering h + c and h + sh in 128-wide k-tiles (Fe16 itself when that is
+    // its own width)
+    const int64_t sh = (fp.hh + fp.cc) % 8, lw = round_up(std::max(fp.hh + fp.cc, fp.hh + sh), kTileF);
     F.fldw = lw;
-    Hw[0].assign((size_t)(lw * lw), 0);
+    if (lw != kp) {
+      Hw[0].assign((size_t)(lw * lw), 0);
+      for (int64_t j = 0; j < fp.ne; ++j)
+        for (int64_t i = 0; i < fp.hh + fp.cc; ++i) Hw[0][(size_t)(j * lw + i)] = bf16_from_f64(H[0][(size_t)(i * kp + j)]);
+    }
     Hw[1].assign((size_t)(lw * lw), 0);
-    for (int64_t j = 0; j < fp.ne; ++j)
-      for (int64_t i = 0; i < fp.hh + fp.cc; ++i) Hw[0][(size_t)(j * lw + i)] = bf16_from_f64(H[0][(size_t)(i * kp + j)]);
     for (int64_t j = 0; j < fp.no; ++j)
       for (int64_t r = 0; r < fp.hh; ++r) Hw[1][(size_t)(j * lw + r + sh)] = bf16_from_f64(H[4][(size_t)(r * kp + j)]);
-    if (e == hipSuccess) e = hipMalloc(&F.Fe16w, sizeof(uint16_t) * (size_t)(lw * lw));
+    if (lw != kp) {
+      if (e == hipSuccess) e = hipMalloc(&F.Fe16w, sizeof(uint16_t) * (size_t)(lw * lw));
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(F.Fe16w, Hw[0].data(), sizeof(uint16_t) * Hw[0].size(), hipMemcpyHostToDevice, st);
+    } else {
+      F.Fe16w = F.Fe16;
+    }
     if (e == hipSuccess) e = hipMalloc(&F.Fr16w, sizeof(uint16_t) * (size_t)(lw * lw));
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(F.Fe16w, Hw[0].data(), sizeof(uint16_t) * Hw[0].size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(F.Fr16w, Hw[1].data(), sizeof(uint16_t) * Hw[1].size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMalloc(&F.Fr64, sizeof(double) * cnt);
@@ -605,7 +614,8 @@ size_t plan_device_bytes(const ts_plan* p) {
     b += (size_t)(F->kpad * F->ld) * (8 + 8 + 4 + 4 + 2 + 2);
     b += sizeof(double) * (size_t)F->n * (F->msq ? 5 : 3);
     if (F->band) b += sizeof(double) * (size_t)F->n * (2 * F->bw + 1);
-    if (F->fold) b += (size_t)(F->fkp * F->fkp) * (5 * 8 + 5 * 4 + 4 * 2) + (size_t)(F->fldw * F->fldw) * 2 * 2;
+    if (F->fold)
+      b += (size_t)(F->fkp * F->fkp) * (5 * 8 + 5 * 4 + 4 * 2) + (size_t)(F->fldw * F->fldw) * 2 * (F->fldw == F->fkp ? 1 : 2);
     add(F->op_pass.get());
   };
   for (const auto& F : p->ax) add(F.get());
