@@ -162,7 +162,7 @@ class PcgTask : public Task {
     TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_, true));
     TS_TRY(launch_dot(r_, z_, N_, b_.partial, nullptr, nullptr, done_, st));
     TS_TRY(launch_scalar(ScalarStep::InitRZ, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
-    TS_TRY(hipMemcpyAsync(pp_, z_, sizeof(double) * N_, hipMemcpyDeviceToDevice, st));
+    std::swap(pp_, z_);  // p = z: the buffers trade roles instead of a copy
     sq_ = stencil_args(p_, V2_, s_op_, pp_, q_, true);
     sq_.dot = StDot::UdotOut;
     sq_.partial = b_.partial;
@@ -173,6 +173,10 @@ class PcgTask : public Task {
     // which writes it where the apply's input sweep would (z, whose old values
     // the operator sweep has consumed by then)
     round_r_ = prec_ == TS_PREC_BF16 && bf16_sweep_applies(p_, r_, z_);
+    // and when that apply folds its input, the update folds it too
+    fold_r_ = round_r_ && bf16_fold_axes(p_, r_, z_, true, fb_) &&
+              cg_update_fold_ok(fb_, x_, r_, pp_, q_, (const uint16_t*)z_) &&
+              cg_update_fold_ok(fb_, x_, r_, pp2_, q_, (const uint16_t*)z_);
     TS_RC(enqueue_chunk(st));
     TS_TRY(snapshot(b_, st));
     return TS_OK;
@@ -222,10 +226,12 @@ class PcgTask : public Task {
       if (pending_) std::swap(pp_, pp2_);
       pending_ = false;
       TS_TRY(launch_scalar(ScalarStep::Alpha, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
-      TS_TRY(launch_cg_update(x_, r_, pp_, q_, N_, b_.sc, b_.partial, done_, st,
-                              round_r_ ? (uint16_t*)z_ : nullptr));
+      if (fold_r_)
+        TS_TRY(launch_cg_update_fold(x_, r_, pp_, q_, fb_, b_.sc, b_.partial, done_, (uint16_t*)z_, st));
+      else
+        TS_TRY(launch_cg_update(x_, r_, pp_, q_, N_, b_.sc, b_.partial, done_, st, round_r_ ? (uint16_t*)z_ : nullptr));
       TS_TRY(launch_scalar(ScalarStep::RR, b_.sc, b_.partial, nullptr, flexible_, maxit_, st));
-      TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_, true, round_r_));
+      TS_RC(apply_inverse_impl(p_, s_pc_, r_, z_, TS_F64, prec_, st, c_, done_, true, round_r_, fold_r_));
       TS_TRY(launch_dot(z_, r_, N_, b_.partial, flexible_ ? q_ : nullptr, flexible_ ? b_.partial2 : nullptr,
                         done_, st));
       TS_TRY(launch_scalar(ScalarStep::Beta, b_.sc, b_.partial, flexible_ ? b_.partial2 : nullptr, flexible_,
@@ -249,7 +255,8 @@ class PcgTask : public Task {
   double *r_ = nullptr, *z_ = nullptr, *pp_ = nullptr, *q_ = nullptr, *pp2_ = nullptr;
   int64_t N_ = 0;
   int flexible_ = 0;
-  bool can_fuse_ = false, pending_ = false, round_r_ = false;
+  bool can_fuse_ = false, pending_ = false, round_r_ = false, fold_r_ = false;
+  ButterflyArgs fb_;  // the axes along which the BF16 preconditioner folds its input
   const int* done_ = nullptr;
   int chunk_ = 4, enq_ = 0;
   bool final_ = false;

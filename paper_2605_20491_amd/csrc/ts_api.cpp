@@ -684,6 +684,43 @@ size_t need_exp(const ts_plan* p, int slot) {
 static DT dt_of(int dtype) { return (dtype == TS_F64 || dtype == TS_C128) ? DT::F64 : DT::F32; }
 
 // Run the 2d passes of one apply.  Intermediates have the precision's type.
+bool bf16_fold_axes(const ts_plan* p, const void* in, void* out, bool sym, ButterflyArgs& b) {
+  b = ButterflyArgs{};
+  if (!p->fold_enabled || in == out || p->N % 4 != 0 || (((uintptr_t)in) & 15) != 0 || (((uintptr_t)out) & 15) != 0)
+    return false;
+  const int d = p->d;
+  b.X = in;
+  b.Y = out;
+  b.t = DT::F64;
+  b.d = d;
+  b.ncomp = 1;
+  for (int k = 0; k < d; ++k) b.n[k] = p->n[k];
+  for (int k = d - 1; k >= 0 && b.nax < 4; --k) {  // fastest first, as the sweep applies them
+    const AxisFactor* F = (sym ? p->ax_sym : p->ax)[k].get();
+    if (!F->fold) continue;
+    PassArgs q;
+    q.X = out;
+    q.Y = out;  // the work buffers are library allocations, 256-byte aligned like out's check
+    q.tin = DT::BF16;
+    q.tout = DT::BF16;
+    q.prec = TS_PREC_BF16;
+    q.fac = F;
+    q.forward = true;
+    q.n = p->n[k];
+    q.P = 1;
+    for (int m = 0; m < k; ++m) q.P *= p->n[m];
+    q.R = 1;
+    for (int m = k + 1; m < d; ++m) q.R *= p->n[m];
+    q.epi = k == p->s ? Epi::Inv : Epi::None;
+    q.bf16_tile = p->bf16_tile;
+    if (!bf16_fold_pass_ok(q)) continue;
+    b.ax[b.nax] = k;
+    b.hh[b.nax] = p->n[k] / 2;
+    ++b.nax;
+  }
+  return b.nax > 0;
+}
+
 int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   const int d = p->d;
   const bool cplx = ap.cplx;
@@ -744,33 +781,20 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   // the symmetric axes whose forward pass can read folded data (256 x 256
   // tiles), and those forward passes contract half the extent; the backward
   // passes run over the full extent on the spectral [even | odd] order, which
-  // needs no unfolding afterwards.
-  int bax[4];
+  // needs no unfolding afterwards.  (A caller that wrote the input itself,
+  // in_rounded, folded it along the same axes when in_folded is set.)
+  ButterflyArgs fb;
   int nb = 0;
-  if (p->fold_enabled && ap.prec == TS_PREC_BF16 && !cplx && !ap.in_rounded && ap.tin == DT::F64 &&
-      ap.tout == DT::F64 && ap.in != ap.out && ap.epi != Epi::Exp && p->N % 4 == 0 &&
-      ((((uintptr_t)ap.in) & 15) == 0)) {
-    for (int k = d - 1; k >= 0 && nb < 4; --k) {
-      const AxisFactor* F = (ap.sym ? p->ax_sym : p->ax)[k].get();
-      if (!F->fold) continue;
-      PassArgs q;
-      q.X = ap.out;
-      q.Y = ap.work;
-      q.tin = DT::BF16;
-      q.tout = DT::BF16;
-      q.prec = ap.prec;
-      q.fac = F;
-      q.forward = true;
-      q.n = p->n[k];
-      q.P = 1;
-      for (int m = 0; m < k; ++m) q.P *= p->n[m];
-      q.R = 1;
-      for (int m = k + 1; m < d; ++m) q.R *= p->n[m];
-      q.epi = k == p->s ? ap.epi : Epi::None;
-      q.bf16_tile = p->bf16_tile;
-      const bool ok = bf16_fold_pass_ok(q) && ((((uintptr_t)ap.work) & 15) == 0) && ((((uintptr_t)ap.out) & 15) == 0);
-      if (ok) bax[nb++] = k;
+  const int* bax = fb.ax;
+  if (!cplx && ap.tin == DT::F64 && ap.tout == DT::F64 && (!ap.in_rounded || ap.in_folded) &&
+      ap.epi != Epi::Exp && ap.prec == TS_PREC_BF16 && bf16_fold_axes(p, ap.in, ap.out, ap.sym, fb))
+    nb = fb.nax;
+  if (nb > 0 && (((uintptr_t)ap.work) & 15) != 0) {  // the folded passes read 16-byte chunks of it
+    if (ap.in_folded) {
+      set_error("BF16 apply on folded input needs a 16-byte aligned workspace");
+      return TS_ERR_INVALID;
     }
+    nb = 0;
   }
   auto bf16_folded = [&](int k) {
     for (int j = 0; j < nb; ++j)
@@ -787,20 +811,8 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     src = ap.out;
     src_t = DT::BF16;
   } else if (nb > 0) {
-    ButterflyArgs b;
-    b.X = ap.in;
-    b.Y = ap.out;
-    b.t = DT::F64;
-    b.d = d;
-    b.ncomp = 1;
-    for (int k = 0; k < d; ++k) b.n[k] = p->n[k];
-    b.nax = nb;
-    for (int j = 0; j < nb; ++j) {
-      b.ax[j] = bax[j];
-      b.hh[j] = p->n[bax[j]] / 2;
-    }
-    b.skip = ap.skip;
-    hipError_t e = launch_fold_to_bf16(b, st);
+    fb.skip = ap.skip;
+    hipError_t e = launch_fold_to_bf16(fb, st);
     if (e != hipSuccess) {
       set_error(std::string("BF16 folding launch failed: ") + hipGetErrorString(e));
       return TS_ERR_DEVICE;
@@ -870,7 +882,7 @@ bool bf16_sweep_applies(const ts_plan* p, const void* in, const void* out) {
 }
 
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, ExecCtx& c, const int* skip, bool sym, bool in_rounded) {
+                       hipStream_t st, ExecCtx& c, const int* skip, bool sym, bool in_rounded, bool in_folded) {
   if (!p || !b || !u) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_F64 && dtype != TS_F32) { set_error("inverse apply needs TS_F64 or TS_F32 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
@@ -906,6 +918,7 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
   ap.skip = skip;
   ap.sym = sym;
   ap.in_rounded = in_rounded && prec == TS_PREC_BF16 && dtype == TS_F64 && bf16_sweep_applies(p, b, u);
+  ap.in_folded = ap.in_rounded && in_folded;
   return run_apply(p, ap, st);
 }
 

@@ -18,6 +18,7 @@ struct ApplyParams {
   const double2* phase = nullptr;  // Exp: tables Ep | Er | es of the scaling axis
   bool sym = false;                // use the plan's orthogonal (solver) factors
   bool in_rounded = false;         // BF16 of FP64 data: out already holds the input rounded to BF16
+  bool in_folded = false;          // ... and folded along the axes bf16_fold_axes lists
 };
 
 int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st);
@@ -31,12 +32,17 @@ size_t need_exp(const ts_plan* p, int slot);
 // symmetric form's inverse (the solvers' variables; differs from the public
 // apply only for SEM plans).
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, ExecCtx& c, const int* skip, bool sym = false, bool in_rounded = false);
+                       hipStream_t st, ExecCtx& c, const int* skip, bool sym = false, bool in_rounded = false,
+                       bool in_folded = false);
 
 // Whether a BF16 inverse apply of FP64 data `in` -> `out` (N values) starts
 // with the streaming input sweep into `out`, which a producer of `in` may
 // write itself instead (apply_inverse_impl's in_rounded).
 bool bf16_sweep_applies(const ts_plan* p, const void* in, const void* out);
+// The axes along which a BF16 inverse apply of FP64 data in -> out folds its
+// input (the symmetric axes whose forward pass can read folded data), as the
+// arguments of that fold (X = in, Y = out, fastest axis first); false if none.
+bool bf16_fold_axes(const ts_plan* p, const void* in, void* out, bool sym, ButterflyArgs& b);
 // psi_out = exp(-i tau H1) psi_in.
 int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
                    hipStream_t st, ExecCtx& c);

@@ -75,6 +75,16 @@ hipError_t launch_dot(const double* x, const double* y, int64_t n, double* parti
 hipError_t launch_cg_update(double* x, double* r, const double* p, const double* q, int64_t n,
                             const SolverScalars* sc, double* partial, const int* skip, hipStream_t st,
                             uint16_t* r16 = nullptr);
+// The same with r16 = the BF16 rounding of r folded along the axes of b (the
+// input a BF16 apply with those folded axes reads, see bf16_fold_axes): the
+// data walked by orbits of the reflections, four fastest-axis points per
+// thread.  Needs n_{d-1} % 8 == 0, 16-byte aligned vectors and an 8-byte
+// aligned r16 (cg_update_fold_ok).
+bool cg_update_fold_ok(const ButterflyArgs& b, const double* x, const double* r, const double* p, const double* q,
+                       const uint16_t* r16);
+hipError_t launch_cg_update_fold(double* x, double* r, const double* p, const double* q, const ButterflyArgs& b,
+                                 const SolverScalars* sc, double* partial, const int* skip, uint16_t* r16,
+                                 hipStream_t st);
 
 // p = z + beta p (beta from sc).
 hipError_t launch_xpby(const double* z, double* p, int64_t n, const SolverScalars* sc, const int* skip,

@@ -303,6 +303,144 @@ __global__ __launch_bounds__(RT) void k_cg_update(double* x, double* r, const do
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
+// The same update walking the data by orbits of the reflections of the axes
+// the next BF16 apply folds (b.ax: the slow ones in slots 0 .. NSLOW - 1, the
+// fastest last when FAST; four consecutive fastest-axis points per thread, as
+// the folding input sweep of the apply): after x and r of an orbit are
+// updated, its r values are folded (s = r_i + r_{n-1-i} at i, d = r_i -
+// r_{n-1-i} at n-1-i, in FP64, fastest axis first) and rounded FP64 -> FP32
+// -> BF16 into r16, which is exactly what that sweep would write.  <r, r> is
+// summed in orbit order.
+template <int NSLOW, bool FAST>
+__global__ __launch_bounds__(RT) void k_cg_update_fold(double* x, double* r, const double* p, const double* q,
+                                                       ButterflyArgs b, int64_t units, const SolverScalars* sc,
+                                                       double* partial, const int* skip, uint16_t* r16) {
+  if (skip && *skip) {
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0.0;
+    return;
+  }
+  constexpr int NB = NSLOW + (FAST ? 1 : 0);
+  constexpr int NV = 1 << NB;
+  const double alpha = sc->alpha;
+  const int64_t nf = b.n[b.d - 1];
+  const int64_t gq = (FAST ? nf / 2 : nf) / 4;
+  double s = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)RT + threadIdx.x; e < units; e += (int64_t)gridDim.x * RT) {
+    int64_t rest = e / gq;
+    const int64_t qg = e - rest * gq;
+    int64_t off = 4 * qg, stride = nf;
+    int64_t delta[NB > 0 ? NB : 1];
+    bool act[NB > 0 ? NB : 1];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      delta[j] = 0;
+      act[j] = false;
+    }
+    if (FAST) {
+      act[NB - 1] = true;
+      delta[NB - 1] = nf - 4 - 8 * qg;
+    }
+    for (int k = b.d - 2; k >= 0; --k) {
+      int jf = -1;
+#pragma unroll
+      for (int j = 0; j < NSLOW; ++j)
+        if (b.ax[j] == k) jf = j;
+      const int64_t ext = jf >= 0 ? b.n[k] - b.hh[jf] : b.n[k];
+      const int64_t qq = rest / ext;
+      const int64_t i = rest - qq * ext;
+      rest = qq;
+      off += i * stride;
+#pragma unroll
+      for (int j = 0; j < NSLOW; ++j)
+        if (j == jf && i < b.hh[j]) {
+          act[j] = true;
+          delta[j] = (b.n[k] - 1 - 2 * i) * stride;
+        }
+      stride *= b.n[k];
+    }
+    double v[NV][4];
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      if (ok) {
+        const double2 x0 = *(const double2*)(x + o), x1 = *(const double2*)(x + o + 2);
+        const double2 p0 = *(const double2*)(p + o), p1 = *(const double2*)(p + o + 2);
+        const double2 r0 = *(const double2*)(r + o), r1 = *(const double2*)(r + o + 2);
+        const double2 q0 = *(const double2*)(q + o), q1 = *(const double2*)(q + o + 2);
+        *(double2*)(x + o) = make_double2(x0.x + alpha * p0.x, x0.y + alpha * p0.y);
+        *(double2*)(x + o + 2) = make_double2(x1.x + alpha * p1.x, x1.y + alpha * p1.y);
+        v[m][0] = r0.x - alpha * q0.x;
+        v[m][1] = r0.y - alpha * q0.y;
+        v[m][2] = r1.x - alpha * q1.x;
+        v[m][3] = r1.y - alpha * q1.y;
+        *(double2*)(r + o) = make_double2(v[m][0], v[m][1]);
+        *(double2*)(r + o + 2) = make_double2(v[m][2], v[m][3]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s += v[m][c] * v[m][c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[m][c] = 0.0;
+      }
+    }
+    if (FAST) {
+      constexpr int fb = FAST ? 1 << (NB - 1) : 0;
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (!(m & fb)) {
+          double t0[4], t1[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            t0[c] = v[m][c] + v[m | fb][3 - c];
+            t1[3 - c] = v[m][c] - v[m | fb][3 - c];
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            v[m][c] = t0[c];
+            v[m | fb][c] = t1[c];
+          }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NSLOW; ++j) {
+      if (!act[j]) continue;
+#pragma unroll
+      for (int m = 0; m < NV; ++m)
+        if (!(m & (1 << j))) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double x0 = v[m][c], x1 = v[m | (1 << j)][c];
+            v[m][c] = x0 + x1;
+            v[m | (1 << j)][c] = x0 - x1;
+          }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      bool ok = true;
+      int64_t o = off;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (m & (1 << j)) {
+          ok = ok && act[j];
+          o += delta[j];
+        }
+      if (ok)
+        *(uint2*)(r16 + o) =
+            make_uint2((uint32_t)bf16_from_f32((float)v[m][0]) | ((uint32_t)bf16_from_f32((float)v[m][1]) << 16),
+                       (uint32_t)bf16_from_f32((float)v[m][2]) | ((uint32_t)bf16_from_f32((float)v[m][3]) << 16));
+    }
+  }
+  double t = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
 __global__ __launch_bounds__(RT) void k_xpby(const double* z, double* p, int64_t n, const SolverScalars* sc,
                                              const int* skip) {
   if (skip && *skip) return;
@@ -499,6 +637,63 @@ hipError_t launch_cg_update(double* x, double* r, const double* p, const double*
                             const SolverScalars* sc, double* partial, const int* skip, hipStream_t st,
                             uint16_t* r16) {
   hipLaunchKernelGGL(k_cg_update, dim3(red_grid(n)), dim3(RT), 0, st, x, r, p, q, n, sc, partial, skip, r16);
+  return hipGetLastError();
+}
+
+bool cg_update_fold_ok(const ButterflyArgs& b, const double* x, const double* r, const double* p, const double* q,
+                       const uint16_t* r16) {
+  const uintptr_t al = ((uintptr_t)x | (uintptr_t)r | (uintptr_t)p | (uintptr_t)q) & 15;
+  if (b.nax < 1 || b.nax > 4 || b.ncomp != 1 || b.n[b.d - 1] % 8 != 0 || al != 0 || (((uintptr_t)r16) & 7) != 0)
+    return false;
+  int nslow = 0;
+  for (int j = 0; j < b.nax; ++j)
+    if (b.ax[j] != b.d - 1) ++nslow;
+  return nslow <= 3;
+}
+
+hipError_t launch_cg_update_fold(double* x, double* r, const double* p, const double* q, const ButterflyArgs& a,
+                                 const SolverScalars* sc, double* partial, const int* skip, uint16_t* r16,
+                                 hipStream_t st) {
+  if (!cg_update_fold_ok(a, x, r, p, q, r16)) return hipErrorInvalidValue;
+  ButterflyArgs b = a;  // the slow axes in slots 0 .. nslow - 1 (order kept)
+  int nslow = 0;
+  bool fast = false;
+  for (int j = 0; j < a.nax; ++j) {
+    if (a.ax[j] == a.d - 1) {
+      fast = true;
+      continue;
+    }
+    b.ax[nslow] = a.ax[j];
+    b.hh[nslow] = a.hh[j];
+    ++nslow;
+  }
+  int64_t units = 1;
+  for (int k = 0; k < a.d - 1; ++k) {
+    int64_t ext = a.n[k];
+    for (int j = 0; j < nslow; ++j)
+      if (b.ax[j] == k) ext = a.n[k] - b.hh[j];
+    units *= ext;
+  }
+  units *= (fast ? a.n[a.d - 1] / 2 : a.n[a.d - 1]) / 4;
+  const dim3 grid(red_grid(units)), block(RT);
+#define TS_UPD_FOLD(NS)                                                                                        \
+  if (fast)                                                                                                  \
+    hipLaunchKernelGGL((k_cg_update_fold<NS, true>), grid, block, 0, st, x, r, p, q, b, units, sc, partial, skip, \
+                       r16);                                                                                 \
+  else                                                                                                       \
+    hipLaunchKernelGGL((k_cg_update_fold<NS, false>), grid, block, 0, st, x, r, p, q, b, units, sc, partial,     \
+                       skip, r16);
+  switch (nslow) {
+    case 0:
+      hipLaunchKernelGGL((k_cg_update_fold<0, true>), grid, block, 0, st, x, r, p, q, b, units, sc, partial, skip,
+                         r16);
+      break;
+    case 1: TS_UPD_FOLD(1) break;
+    case 2: TS_UPD_FOLD(2) break;
+    case 3: TS_UPD_FOLD(3) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef TS_UPD_FOLD
   return hipGetLastError();
 }
 
