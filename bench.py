@@ -716,7 +716,8 @@ def cpu_baseline(n, depth):
                       "O(N) diagonal scaling is not timed" % (depth, n, n, depth, n, depth, n, n)}
 
 
-SECTIONS = ["headline", "variants", "bf16", "small64", "pcg", "split", "qhop", "table", "hermite", "gpe", "serve", "cpu"]
+SECTIONS = ["headline", "variants", "bf16", "vendor_gemm", "small64", "pcg", "split", "qhop", "table", "hermite", "gpe",
+            "serve", "cpu"]
 
 
 def apply_rooflines(N, n, d, t_ms, prec, flops_exec=None):
@@ -886,6 +887,34 @@ def bf16_section(ts, W, torch, dev, args):
     return {"inverse_bf16_ms": ms, "roofline": apply_rooflines(n ** 3, n, 3, ms, "bf16")}
 
 
+def vendor_gemm_section(torch, dev, n, reps=10):
+    """Yardstick only (not the library): the vendor BF16 GEMM (torch.matmul /
+    torch.bmm on random BF16 tensors) on the shapes of the BF16 passes of the
+    n^3 apply: the row passes' [n^2 x n] x [n x n], the column passes' n batched
+    [n x n] x [n x n], and axis 0 as one [n x n] x [n x n^2] product; one warm-up,
+    then `reps` timed products each."""
+    def t(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+    N = n ** 3
+    X = torch.randn(N // n, n, device=dev, dtype=torch.bfloat16)
+    Q = torch.randn(n, n, device=dev, dtype=torch.bfloat16)
+    Qb = Q.t().contiguous().expand(n, n, n)
+    out = {"n": n}
+    for key, fn in (("rows_ms", lambda: torch.matmul(X, Q)), ("cols_batched_ms", lambda: torch.bmm(Qb, X.view(n, n, n))),
+                    ("axis0_ms", lambda: torch.matmul(Q, X.view(n, n * n)))):
+        ms = t(fn)
+        out[key] = ms
+        log("vendor BF16 GEMM n=%d %s: %.3f ms = %.0f TFLOP/s" % (n, key, ms, 2.0 * N * n / ms / 1e9))
+    del X, Q, Qb
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -965,6 +994,9 @@ def main():
         torch.cuda.empty_cache()
     if "bf16" in run and args.only:
         extra["bf16_only"] = bf16_section(ts, W, torch, dev, args)
+        torch.cuda.empty_cache()
+    if "vendor_gemm" in run and args.only:
+        extra["vendor_gemm"] = vendor_gemm_section(torch, dev, n)
         torch.cuda.empty_cache()
     if "small64" in run:
         extra["small_64"] = small_section(ts, W, torch, dev)
