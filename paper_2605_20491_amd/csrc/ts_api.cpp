@@ -683,7 +683,6 @@ size_t need_exp(const ts_plan* p, int slot) {
 
 static DT dt_of(int dtype) { return (dtype == TS_F64 || dtype == TS_C128) ? DT::F64 : DT::F32; }
 
-// Run the 2d passes of one apply.  Intermediates have the precision's type.
 bool bf16_fold_axes(const ts_plan* p, const void* in, void* out, bool sym, ButterflyArgs& b) {
   b = ButterflyArgs{};
   if (!p->fold_enabled || in == out || p->N % 4 != 0 || (((uintptr_t)in) & 15) != 0 || (((uintptr_t)out) & 15) != 0)
@@ -721,6 +720,7 @@ bool bf16_fold_axes(const ts_plan* p, const void* in, void* out, bool sym, Butte
   return b.nax > 0;
 }
 
+// Run the 2d passes of one apply.  Intermediates have the precision's type.
 int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   const int d = p->d;
   const bool cplx = ap.cplx;
