@@ -587,7 +587,8 @@ constexpr int BB = 256, NTB = 512;
 // rows reversed), so each tile runs one half-size product.  Row passes then
 // move data and outputs in 8-byte pieces (the odd half starts at h, a multiple
 // of 4 but not always of 8).
-template <bool ROWS, int EPI, typename TOut, bool F3>
+// ACC (FP64 output): the pass adds its result to Y instead of storing it.
+template <bool ROWS, int EPI, typename TOut, bool F3, bool ACC = false>
 __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ __attribute__((aligned(16))) uint16_t smem_big[4 * BB * LDK];
@@ -854,7 +855,9 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
           if (col >= rowlen) continue;
           double v = (double)acc[i][j][r];
           if (EPI == (int)Epi::Inv) v = v / (tm + a.Lr[col] + a.shift);
-          Y[(ROWS ? m * a.n : (p * a.n + m) * a.R) + col] = cvt_out<TOut>(v);
+          TOut* y = Y + (ROWS ? m * a.n : (p * a.n + m) * a.R) + col;
+          if constexpr (ACC) *y += v;
+          else *y = cvt_out<TOut>(v);
         }
       }
     }
@@ -901,6 +904,12 @@ hipError_t launch_bf16_big(KArgs a, const PassArgs& pa, hipStream_t st) {
   if (a.nblocks <= 0) return hipSuccess;
   if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)a.nblocks), block(NTB);
+  if (pa.accumulate) {
+    if (!std::is_same<TOut, double>::value || pa.epi != Epi::None) return hipErrorInvalidValue;
+    if (a.rows) hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut, false, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut, false, true>), grid, block, 0, st, a);
+    return hipGetLastError();
+  }
   if (a.rows) {
     hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut, false>), grid, block, 0, st, a);
   } else if (pa.epi == Epi::Inv) {
@@ -1026,6 +1035,7 @@ hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
   }
   const int fold = (pa.fold && !bf16_coalesced<TIn>(a, pa)) ? (pa.forward ? 1 : 2) : 0;
   if (bf16_big_ok<TIn>(a, pa, fold)) return launch_bf16_big<TOut>(a, pa, st);
+  if (pa.accumulate) return hipErrorInvalidValue;  // only the large tiles add into their output
   if (fold) {
     a.ne = F->ne;
     a.no = F->no;
@@ -1308,6 +1318,12 @@ hipError_t launch_fold_to_bf16(const ButterflyArgs& a, hipStream_t st) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+bool bf16_big_pass_ok(const PassArgs& pa) {
+  KArgs a{};
+  fill_kargs(pa, a, pa.forward ? (const void*)pa.fac->QT16 : (const void*)pa.fac->Q16, BM, BN);
+  return pa.tin == DT::BF16 && bf16_big_ok<uint16_t>(a, pa, 0);
 }
 
 bool bf16_fold_pass_ok(const PassArgs& pa) {

@@ -298,6 +298,7 @@ class RefineTask : public Task {
     TS_TRY(launch_scalar(ScalarStep::SetRR, b_.sc, b_.partial, nullptr, 0, maxit_, st));
     TS_TRY(snapshot(b_, st));
     sweeps_ = 1;
+    acc_ = inner_ == TS_PREC_BF16 && bf16_accumulate_ok(p_, r_, u_, true);
     return TS_OK;
   }
 
@@ -338,8 +339,12 @@ class RefineTask : public Task {
       cg_ = make_pcg_task(p_, nullptr, sigma_, sigma_, f_, u_, rtol_, maxit_ - sweeps_, inner_, c_, false);
       return cg_->start(st);
     }
-    TS_RC(apply_inverse_impl(p_, sigma_, r_, dlt_, TS_F64, inner_, st, c_, nullptr, true));
-    TS_TRY(launch_axpy1(u_, dlt_, N_, nullptr, st));
+    if (acc_) {  // u += M^{-1} r in the apply's last pass
+      TS_RC(apply_inverse_impl(p_, sigma_, r_, u_, TS_F64, inner_, st, c_, nullptr, true, false, false, true));
+    } else {
+      TS_RC(apply_inverse_impl(p_, sigma_, r_, dlt_, TS_F64, inner_, st, c_, nullptr, true));
+      TS_TRY(launch_axpy1(u_, dlt_, N_, nullptr, st));
+    }
     TS_TRY(launch_stencil(sa_, st));
     TS_TRY(launch_scalar(ScalarStep::SetRR, b_.sc, b_.partial, nullptr, 0, maxit_, st));
     TS_TRY(snapshot(b_, st));
@@ -348,6 +353,7 @@ class RefineTask : public Task {
   }
 
   ts_plan* p_;
+  bool acc_ = false;  // BF16 inner applies add their correction to u themselves
   double sigma_;
   const double* f_;
   double* u_;

@@ -783,11 +783,19 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   // passes run over the full extent on the spectral [even | odd] order, which
   // needs no unfolding afterwards.  (A caller that wrote the input itself,
   // in_rounded, folded it along the same axes when in_folded is set.)
+  // With accumulate (out += the result), the intermediates that would go to
+  // out go to the upper half of the workspace instead (BF16: 2 bytes a value,
+  // the workspace holds 8).
+  if (ap.accumulate && (ap.prec != TS_PREC_BF16 || ap.tout != DT::F64 || cplx || ap.in_rounded || ap.in == ap.out)) {
+    set_error("accumulating applies are BF16 applies of FP64 data");
+    return TS_ERR_INVALID;
+  }
+  void* const ob = ap.accumulate ? (void*)((char*)ap.work + 2 * (size_t)p->N) : ap.out;
   ButterflyArgs fb;
   int nb = 0;
   const int* bax = fb.ax;
   if (!cplx && ap.tin == DT::F64 && ap.tout == DT::F64 && (!ap.in_rounded || ap.in_folded) &&
-      ap.epi != Epi::Exp && ap.prec == TS_PREC_BF16 && bf16_fold_axes(p, ap.in, ap.out, ap.sym, fb))
+      ap.epi != Epi::Exp && ap.prec == TS_PREC_BF16 && bf16_fold_axes(p, ap.in, ob, ap.sym, fb))
     nb = fb.nax;
   if (nb > 0 && (((uintptr_t)ap.work) & 15) != 0) {  // the folded passes read 16-byte chunks of it
     if (ap.in_folded) {
@@ -817,22 +825,22 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
       set_error(std::string("BF16 folding launch failed: ") + hipGetErrorString(e));
       return TS_ERR_DEVICE;
     }
-    src = ap.out;
+    src = ob;
     src_t = DT::BF16;
   } else if (ap.prec == TS_PREC_BF16 && ap.tin == DT::F64 && ap.in != ap.out && Ntot % 4 == 0 &&
-      ((((uintptr_t)ap.in) & 15) == 0) && ((((uintptr_t)ap.out) & 7) == 0)) {
-    hipError_t e = launch_data_to_bf16((const double*)ap.in, (uint16_t*)ap.out, Ntot, ap.skip, st);
+      ((((uintptr_t)ap.in) & 15) == 0) && ((((uintptr_t)ob) & 7) == 0)) {
+    hipError_t e = launch_data_to_bf16((const double*)ap.in, (uint16_t*)ob, Ntot, ap.skip, st);
     if (e != hipSuccess) {
       set_error(std::string("BF16 rounding launch failed: ") + hipGetErrorString(e));
       return TS_ERR_DEVICE;
     }
-    src = ap.out;
+    src = ob;
     src_t = DT::BF16;
   }
   for (int t = 1; t <= T; ++t) {
     const bool fwd = t <= d;
     const int k = fwd ? order[t - 1] : (t == d + 1 ? p->s : order[t - d - 2]);
-    void* dst = ((T - t) % 2 == 0) ? ap.out : ap.work;
+    void* dst = ((T - t) % 2 == 0) ? (t == T ? ap.out : ob) : ap.work;
     DT dst_t = (t == T) ? ap.tout : inter;
     PassArgs pa;
     pa.X = src;
@@ -855,6 +863,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
     pa.deferred = deferred && pa.fold;
     if (ap.prec == TS_PREC_BF16 && fwd && bf16_folded(k)) pa.fold = pa.deferred = true;
+    pa.accumulate = ap.accumulate && t == T;
     pa.bf16_tile = p->bf16_tile;
     if (fwd && t == d) {
       pa.epi = ap.epi;
@@ -881,8 +890,35 @@ bool bf16_sweep_applies(const ts_plan* p, const void* in, const void* out) {
          (((uintptr_t)out) & 7) == 0;
 }
 
+bool bf16_accumulate_ok(const ts_plan* p, const void* in, const void* out, bool sym) {
+  if (plan_is_small(p) || in == out || p->N % 8 != 0 || (((uintptr_t)out) & 15) != 0) return false;
+  // the last pass (run_apply's order): backward along the lowest axis other
+  // than the scaling axis s, or along s itself in 1D
+  const int d = p->d;
+  int k = p->s;
+  for (int m = d - 1; m >= 0; --m)
+    if (m != p->s) k = m;
+  PassArgs q;
+  q.X = out;  // stands for the workspace (library allocation, 256-byte aligned)
+  q.Y = (void*)out;
+  q.tin = DT::BF16;
+  q.tout = DT::F64;
+  q.prec = TS_PREC_BF16;
+  q.fac = (sym ? p->ax_sym : p->ax)[k].get();
+  q.forward = false;
+  q.n = p->n[k];
+  q.P = 1;
+  for (int m = 0; m < k; ++m) q.P *= p->n[m];
+  q.R = 1;
+  for (int m = k + 1; m < d; ++m) q.R *= p->n[m];
+  q.bf16_tile = p->bf16_tile;
+  q.accumulate = true;
+  return bf16_big_pass_ok(q);
+}
+
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
-                       hipStream_t st, ExecCtx& c, const int* skip, bool sym, bool in_rounded, bool in_folded) {
+                       hipStream_t st, ExecCtx& c, const int* skip, bool sym, bool in_rounded, bool in_folded,
+                       bool accumulate) {
   if (!p || !b || !u) { set_error("null argument"); return TS_ERR_INVALID; }
   if (dtype != TS_F64 && dtype != TS_F32) { set_error("inverse apply needs TS_F64 or TS_F32 data"); return TS_ERR_INVALID; }
   if (prec < TS_PREC_FP64 || prec > TS_PREC_BF16) { set_error("bad precision"); return TS_ERR_INVALID; }
@@ -919,6 +955,7 @@ int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dty
   ap.sym = sym;
   ap.in_rounded = in_rounded && prec == TS_PREC_BF16 && dtype == TS_F64 && bf16_sweep_applies(p, b, u);
   ap.in_folded = ap.in_rounded && in_folded;
+  ap.accumulate = accumulate;
   return run_apply(p, ap, st);
 }
 

@@ -19,6 +19,7 @@ struct ApplyParams {
   bool sym = false;                // use the plan's orthogonal (solver) factors
   bool in_rounded = false;         // BF16 of FP64 data: out already holds the input rounded to BF16
   bool in_folded = false;          // ... and folded along the axes bf16_fold_axes lists
+  bool accumulate = false;         // out += the result (BF16 of FP64 data, see bf16_accumulate_ok)
 };
 
 int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st);
@@ -33,7 +34,7 @@ size_t need_exp(const ts_plan* p, int slot);
 // apply only for SEM plans).
 int apply_inverse_impl(ts_plan* p, double shift, const void* b, void* u, int dtype, int prec,
                        hipStream_t st, ExecCtx& c, const int* skip, bool sym = false, bool in_rounded = false,
-                       bool in_folded = false);
+                       bool in_folded = false, bool accumulate = false);
 
 // Whether a BF16 inverse apply of FP64 data `in` -> `out` (N values) starts
 // with the streaming input sweep into `out`, which a producer of `in` may
@@ -43,6 +44,11 @@ bool bf16_sweep_applies(const ts_plan* p, const void* in, const void* out);
 // input (the symmetric axes whose forward pass can read folded data), as the
 // arguments of that fold (X = in, Y = out, fastest axis first); false if none.
 bool bf16_fold_axes(const ts_plan* p, const void* in, void* out, bool sym, ButterflyArgs& b);
+// Whether a BF16 inverse apply of FP64 data in -> out can add its result to
+// out (apply_inverse_impl's accumulate): the last pass must run on the
+// 256 x 256 tiles, and N % 8 == 0 places the workspace's two halves on
+// 16-byte boundaries.
+bool bf16_accumulate_ok(const ts_plan* p, const void* in, const void* out, bool sym);
 // psi_out = exp(-i tau H1) psi_in.
 int apply_exp_impl(ts_plan* p, double tau, const void* in, void* out, int dtype, int prec,
                    hipStream_t st, ExecCtx& c);

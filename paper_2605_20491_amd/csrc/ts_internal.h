@@ -120,6 +120,9 @@ struct PassArgs {
   // with fold: a forward pass reads data already folded along this axis
   // (launch_butterfly), a backward pass leaves its butterfly to the caller
   bool deferred = false;
+  // FP64 output of a BF16 pass on 256 x 256 tiles: Y += the result instead of
+  // Y = the result (bf16_big_pass_ok tells whether the pass runs there)
+  bool accumulate = false;
   int64_t kband = 0;           // > 0: the factor is banded, |k - output| <= kband (FP64 passes)
   int bf16_tile = 0;           // BF16 passes: 0 picks the tile size, 128 or 256 forces it where allowed
 };
@@ -129,6 +132,8 @@ hipError_t launch_pass_bf16(const PassArgs& a, hipStream_t st);
 // Whether a forward BF16 pass can read data folded beforehand (pa.fold and
 // pa.deferred set): the 256 x 256-tile kernel is the only one with that layout.
 bool bf16_fold_pass_ok(const PassArgs& pa);
+// Whether a BF16 pass of BF16 input runs on the 256 x 256 tiles.
+bool bf16_big_pass_ok(const PassArgs& pa);
 
 // Butterfly y_i, y_{n-1-i} = x_i + x_{n-1-i}, x_i - x_{n-1-i} (i < hh), in
 // place or not, along up to four axes of a [n_0]...[n_{d-1}][ncomp] array at once

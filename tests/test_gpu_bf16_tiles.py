@@ -144,3 +144,29 @@ def test_pcg_folded_residual_update():
         assert true <= 1.05e-10
         sols.append(uh)
     assert rel(sols[0], sols[1]) <= 1e-8
+
+
+def test_refined_bf16_adds_in_last_pass():
+    """BF16-refined direct inverse: on the large tiles each correction is added
+    to u inside the last pass of its apply (no separate update sweep).  With
+    folding off the large and small tiles are bitwise equal per pass, so the
+    refined solutions with the large tiles (adding in the pass) and the small
+    ones (correction, then a separate update) must be bitwise equal too; the
+    true residual meets the bar."""
+    shape = (256, 200, 264)
+    L = 8.0
+    f = [W.f_harmonic(n, L) for n in shape]
+    plan = ts.ts_setup(shape, L, f, 1.0)
+    ts.ts_set_fold(plan, 0)
+    b = to_dev(W.rhs_normal(shape, 25))
+    outs = {}
+    for tile in (256, 128):
+        ts.ts_set_bf16_tile(plan, tile)
+        u = torch.empty_like(b)
+        _, its, relres = ts.ts_solve_refined(plan, b, u, inner="bf16", rtol=1e-10, maxit=60)
+        outs[tile] = (to_host(u), its, relres)
+    announce("refined bf16 %s: %d / %d sweeps, relres %.2e / %.2e, bitwise equal %s"
+             % (shape, outs[256][1], outs[128][1], outs[256][2], outs[128][2],
+                np.array_equal(outs[256][0], outs[128][0])))
+    assert outs[256][1] == outs[128][1] and np.array_equal(outs[256][0], outs[128][0])
+    assert outs[256][2] <= 1e-10
