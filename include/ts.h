@@ -120,11 +120,18 @@ int ts_destroy(ts_plan* plan);
  * after each backward pass; with two or more such axes an apply folds its
  * input and unfolds its output once for all of them (ts_fold_butterfly) and
  * its passes run on folded data.  The result is the same up to rounding.  Applies
- * with BF16 transforms do not fold (their passes are not bound by the matrix
- * cores, and the mirror loads and the butterfly cost more than they save);
- * ts_mode_pass folds in every precision.
- * ts_set_fold(plan, 0) turns this off for the plan (1 turns it back on);
- * ts_fold_axes reports the axes that qualify as a bit mask (bit k = axis k). */
+ * with BF16 transforms of FP64 data fold in the sweep that rounds the input to
+ * BF16 (s_i and d_i are formed in FP64, then rounded) and run their forward
+ * passes over half extents on 256 x 256 tiles; in 2D and 3D, with every axis
+ * but the fastest folded and of even extent, the backward passes over those
+ * axes also run over half extents and leave their output folded, and the last
+ * pass (backward over the fastest axis, FP64 output) unfolds it in registers.
+ * BF16 results differ from the unfolded BF16 apply by the different rounding
+ * (both at the BF16 level); ts_mode_pass folds in every precision.
+ * ts_set_fold(plan, 0) turns folding off for the plan, 1 turns it back on (the
+ * default), 2 keeps it but runs the BF16 backward passes over full extents;
+ * ts_fold_axes reports the axes that qualify as a bit mask (bit k = axis k).
+ * Errors: TS_ERR_INVALID for a null plan or another mode. */
 int ts_set_fold(ts_plan* plan, int enable);
 
 /* Output tile of the BF16 passes (Sec. 2.2 runs the apply in BF16): 0 (the

@@ -281,8 +281,10 @@ def ts_mass(plan: Plan, axis: int) -> np.ndarray:
     return out
 
 
-def ts_set_fold(plan: Plan, enable: bool):
-    _check(lib().ts_set_fold(plan.handle, int(bool(enable))), "ts_set_fold")
+def ts_set_fold(plan: Plan, enable):
+    """enable: False / 0 off, True / 1 on, 2 on with the BF16 backward passes
+    over full extents."""
+    _check(lib().ts_set_fold(plan.handle, int(enable)), "ts_set_fold")
 
 
 def ts_set_bf16_tile(plan: Plan, tile: int):

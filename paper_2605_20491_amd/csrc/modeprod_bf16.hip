@@ -588,8 +588,33 @@ constexpr int BB = 256, NTB = 512;
 // move data and outputs in 8-byte pieces (the odd half starts at h, a multiple
 // of 4 but not always of 8).
 // ACC (FP64 output): the pass adds its result to Y instead of storing it.
-template <bool ROWS, int EPI, typename TOut, bool F3, bool ACC = false>
-__global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
+// NU (row pass with FP64 output, the last pass of a BF16 apply whose other
+// passes all ran over half extents): the data are folded along the NU slower
+// axes (u_i at i, w_i at n - 1 - i on each), and the tile's rows are gathered
+// by reflection orbits, the 2^NU rows of an orbit consecutive, so that one
+// lane holds a whole orbit of outputs (its four accumulator rows) and unfolds
+// them, x_i = u_i + w_i and x_{n-1-i} = u_i - w_i along each axis, before
+// the FP64 stores.
+struct UGeom {
+  int64_t na = 0;  // extent of the slowest axis
+  int64_t nb = 1;  // NU = 2: extent of the next axis
+  int64_t hb = 1;  // NU = 2: nb / 2
+  int64_t no = 0;  // orbits: (na / 2) (nb / 2)
+};
+template <int NU>
+__device__ __forceinline__ int64_t unf_row(const UGeom& u, int64_t o, int b) {
+  if constexpr (NU == 1) {
+    return b ? u.na - 1 - o : o;
+  } else {
+    const int64_t i0 = o / u.hb, i1 = o - i0 * u.hb;
+    return ((b & 2) ? u.na - 1 - i0 : i0) * u.nb + ((b & 1) ? u.nb - 1 - i1 : i1);
+  }
+}
+
+template <bool ROWS, int EPI, typename TOut, bool F3, bool ACC = false, int NU = 0>
+__global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a, UGeom u) {
+  static_assert(NU == 0 || (ROWS && !F3 && EPI == 0 && std::is_same<TOut, double>::value),
+                "orbit-gathered rows: row passes with FP64 output only");
   if (a.skip && *a.skip) return;
   __shared__ __attribute__((aligned(16))) uint16_t smem_big[4 * BB * LDK];
   typedef uint16_t Row[LDK];
@@ -628,6 +653,19 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
   const int64_t m0 = mtile * BB, n0 = ntile * BB;
   const uint16_t* X = (const uint16_t*)a.X;
   const int64_t f0 = ROWS ? n0 : m0;  // first factor row of this tile
+  // NU: the data rows this thread loads (tile row 64 s2 + t / 8 is member
+  // (row & (2^NU - 1)) of orbit mtile 256 / 2^NU + row / 2^NU; orbits past the
+  // last are clamped to it, and their outputs are not stored)
+  int64_t urow[4] = {0, 0, 0, 0};
+  if constexpr (NU > 0) {
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int rho = 64 * s2 + (t >> 3);
+      int64_t o = mtile * (BB >> NU) + (rho >> NU);
+      o = o < u.no ? o : u.no - 1;
+      urow[s2] = unf_row<NU>(u, o, rho & ((1 << NU) - 1));
+    }
+  }
 
   // One k-tile on its way to LDS: 64 bytes of the factor tile and 64 bytes of
   // the data tile per thread, as raw 16-byte chunks.
@@ -662,7 +700,7 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
       const int64_t kk = koff + (k0 + 8 * c < K ? k0 + 8 * c : (K - 1) / 8 * 8);
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
-        const int64_t m = m0 + 64 * s2 + rg < a.M ? m0 + 64 * s2 + rg : a.M - 1;
+        const int64_t m = NU ? urow[s2] : (m0 + 64 * s2 + rg < a.M ? m0 + 64 * s2 + rg : a.M - 1);
         rx[s2] = *(const u32x4*)(X + m * a.n + kk);
       }
     }
@@ -841,6 +879,43 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a) {
         *(uint4*)(Y + off + cg) = *(const uint4*)&Ts[lrow * LT + 8 * ch];
       }
     }
+  } else if constexpr (NU > 0) {
+    // rows 4 lg .. 4 lg + 3 of each 16-row block are the lane's accumulator
+    // rows r = 0..3: one orbit (NU = 2) or two (NU = 1)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int rho = wm * 128 + i * 16 + 4 * lg;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = n0 + wn * 64 + j * 16 + lr;
+        if (col >= a.n) continue;
+        double x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = (double)acc[i][j][r];
+#pragma unroll
+        for (int q = 0; q < 4; q += 2) {  // along the faster unfolded axis
+          const double s0 = x[q] + x[q + 1], d0 = x[q] - x[q + 1];
+          x[q] = s0;
+          x[q + 1] = d0;
+        }
+        if constexpr (NU == 2) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {  // along the slowest axis
+            const double s0 = x[q] + x[q + 2], d0 = x[q] - x[q + 2];
+            x[q] = s0;
+            x[q + 2] = d0;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t o = mtile * (BB >> NU) + ((rho + r) >> NU);
+          if (o >= u.no) continue;
+          double* y = Y + unf_row<NU>(u, o, (rho + r) & ((1 << NU) - 1)) * a.n + col;
+          if constexpr (ACC) *y += x[r];
+          else *y = x[r];
+        }
+      }
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -887,10 +962,16 @@ bool bf16_big_ok(const KArgs& a, const PassArgs& pa, int fold) {
 // 16-byte aligned buffers, a reflection-symmetric axis of n >= 192, no
 // scaling epilogue on a row pass, and rows of a multiple of 8 values; a row
 // pass also needs n % 8 == 0, so that both halves start on 4-value boundaries.
+// A backward pass runs the same kernel on the spectral [even | odd] order with
+// the backward half factors (Be, and Bo with its physical index reversed): it
+// leaves u_i at i and w_i at n - 1 - i, the folded layout, for the unfolding
+// last pass.
 bool fold3_ok(const KArgs& a, const PassArgs& pa) {
   const AxisFactor* F = pa.fac;
-  if (pa.tin != DT::BF16 || pa.tout != DT::BF16 || pa.cplx || pa.epi == Epi::Exp || !pa.forward) return false;
-  if (!F->fold || !F->Fe16w || !F->Fr16w || pa.bf16_tile == 128 || a.n < 192) return false;
+  if (pa.tin != DT::BF16 || pa.tout != DT::BF16 || pa.cplx || pa.epi == Epi::Exp) return false;
+  if (!pa.forward && pa.epi != Epi::None) return false;
+  if (!F->fold || pa.bf16_tile == 128 || a.n < 192) return false;
+  if (pa.forward ? (!F->Fe16w || !F->Fr16w) : (!F->Be16w || !F->Br16w)) return false;
   if ((((uintptr_t)a.X) & 15) != 0 || (((uintptr_t)a.Y) & 15) != 0) return false;
   if (a.rows) return pa.epi == Epi::None && a.n % 8 == 0;
   return a.R % 8 == 0;
@@ -906,16 +987,16 @@ hipError_t launch_bf16_big(KArgs a, const PassArgs& pa, hipStream_t st) {
   dim3 grid((unsigned)a.nblocks), block(NTB);
   if (pa.accumulate) {
     if (!std::is_same<TOut, double>::value || pa.epi != Epi::None) return hipErrorInvalidValue;
-    if (a.rows) hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut, false, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut, false, true>), grid, block, 0, st, a);
+    if (a.rows) hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut, false, true>), grid, block, 0, st, a, UGeom{});
+    else hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut, false, true>), grid, block, 0, st, a, UGeom{});
     return hipGetLastError();
   }
   if (a.rows) {
-    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut, false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, TOut, false>), grid, block, 0, st, a, UGeom{});
   } else if (pa.epi == Epi::Inv) {
-    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, TOut, false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, TOut, false>), grid, block, 0, st, a, UGeom{});
   } else {
-    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut, false>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, TOut, false>), grid, block, 0, st, a, UGeom{});
   }
   return hipGetLastError();
 }
@@ -929,8 +1010,8 @@ hipError_t launch_bf16_big_fold3(KArgs a, const PassArgs& pa, hipStream_t st) {
   a.hh = F->hh;
   a.cc = F->cc;
   a.fld = F->fldw;
-  a.Se = F->Fe16w;
-  a.So = F->Fr16w;
+  a.Se = pa.forward ? F->Fe16w : F->Be16w;
+  a.So = pa.forward ? F->Fr16w : F->Br16w;
   a.te = (F->ne + BB - 1) / BB;
   const int64_t split = a.te + (F->no + BB - 1) / BB;
   if (a.rows) {
@@ -945,11 +1026,53 @@ hipError_t launch_bf16_big_fold3(KArgs a, const PassArgs& pa, hipStream_t st) {
   if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
   dim3 grid((unsigned)a.nblocks), block(NTB);
   if (a.rows) {
-    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, uint16_t, true>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<true, 0, uint16_t, true>), grid, block, 0, st, a, UGeom{});
   } else if (pa.epi == Epi::Inv) {
-    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, uint16_t, true>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<false, (int)Epi::Inv, uint16_t, true>), grid, block, 0, st, a, UGeom{});
   } else {
-    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, uint16_t, true>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_mode_bf16_big<false, 0, uint16_t, true>), grid, block, 0, st, a, UGeom{});
+  }
+  return hipGetLastError();
+}
+
+// The last pass of a BF16 apply whose other passes all ran over half extents:
+// a row pass with FP64 output on data folded along the pa.unf slower axes
+// (extents pa.un[0..unf-1], all even), unfolded in registers (k_mode_bf16_big, NU).
+bool unfold_ok(const KArgs& a, const PassArgs& pa) {
+  if (pa.unf < 1 || pa.unf > 2 || !a.rows || pa.cplx || pa.epi != Epi::None || pa.forward) return false;
+  if (pa.tin != DT::BF16 || pa.tout != DT::F64 || pa.bf16_tile == 128 || a.n < 192 || a.n % 8 != 0) return false;
+  if ((((uintptr_t)a.X) & 15) != 0 || (((uintptr_t)a.Y) & 15) != 0) return false;
+  int64_t M = 1;
+  for (int j = 0; j < pa.unf; ++j) {
+    if (pa.un[j] < 2 || pa.un[j] % 2 != 0) return false;
+    M *= pa.un[j];
+  }
+  if (M != a.M) return false;
+  if (pa.bf16_tile == 256) return true;
+  // by default only where the tiles pad the extent as little as 128-wide ones
+  // would and every compute unit gets one (as bf16_big_ok)
+  const int64_t pad256 = (a.n + BB - 1) / BB * BB, pad128 = (a.n + BM - 1) / BM * BM;
+  return pad256 * 10 <= pad128 * 11 && ((a.M + BB - 1) / BB) * ((a.N + BB - 1) / BB) >= 256;
+}
+
+hipError_t launch_bf16_big_unfold(KArgs a, const PassArgs& pa, hipStream_t st) {
+  UGeom u;
+  u.na = pa.un[0];
+  u.nb = pa.unf == 2 ? pa.un[1] : 1;
+  u.hb = u.nb / 2 > 0 ? u.nb / 2 : 1;
+  u.no = (u.na / 2) * (pa.unf == 2 ? u.nb / 2 : 1);
+  a.mt = (a.M + BB - 1) / BB;  // 256 / 2^NU orbits of 2^NU rows per tile
+  a.nt = (a.N + BB - 1) / BB;
+  a.nblocks = a.mt * a.nt;
+  if (a.nblocks <= 0) return hipSuccess;
+  if (a.nblocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)a.nblocks), block(NTB);
+  if (pa.unf == 2) {
+    if (pa.accumulate) hipLaunchKernelGGL((k_mode_bf16_big<true, 0, double, false, true, 2>), grid, block, 0, st, a, u);
+    else hipLaunchKernelGGL((k_mode_bf16_big<true, 0, double, false, false, 2>), grid, block, 0, st, a, u);
+  } else {
+    if (pa.accumulate) hipLaunchKernelGGL((k_mode_bf16_big<true, 0, double, false, true, 1>), grid, block, 0, st, a, u);
+    else hipLaunchKernelGGL((k_mode_bf16_big<true, 0, double, false, false, 1>), grid, block, 0, st, a, u);
   }
   return hipGetLastError();
 }
@@ -1032,6 +1155,13 @@ hipError_t launch_bf16_typed(const PassArgs& pa, hipStream_t st) {
     // data folded beforehand: only the 256 x 256 tiles read that layout
     if (!fold3_ok(a, pa)) return hipErrorInvalidValue;
     return launch_bf16_big_fold3(a, pa, st);
+  }
+  if (pa.unf > 0) {
+    if constexpr (std::is_same<TIn, uint16_t>::value && std::is_same<TOut, double>::value) {
+      if (!unfold_ok(a, pa)) return hipErrorInvalidValue;
+      return launch_bf16_big_unfold(a, pa, st);
+    }
+    return hipErrorInvalidValue;
   }
   const int fold = (pa.fold && !bf16_coalesced<TIn>(a, pa)) ? (pa.forward ? 1 : 2) : 0;
   if (bf16_big_ok<TIn>(a, pa, fold)) return launch_bf16_big<TOut>(a, pa, st);
@@ -1330,6 +1460,12 @@ bool bf16_fold_pass_ok(const PassArgs& pa) {
   KArgs a{};
   fill_kargs(pa, a, pa.fac->QT16, BM, BN);
   return fold3_ok(a, pa);
+}
+
+bool bf16_unfold_pass_ok(const PassArgs& pa) {
+  KArgs a{};
+  fill_kargs(pa, a, pa.fac->Q16, BM, BN);
+  return unfold_ok(a, pa);
 }
 
 hipError_t launch_pass_bf16(const PassArgs& pa, hipStream_t st) {

@@ -49,6 +49,8 @@ AxisFactor::~AxisFactor() {
   hipFree(Bo16);
   if (Fe16w != Fe16) hipFree(Fe16w);  // the same array when the widths agree
   hipFree(Fr16w);
+  if (Be16w != Be16) hipFree(Be16w);
+  hipFree(Br16w);
   hipFree(mass);
   hipFree(msq);
   hipFree(imsq);
@@ -279,7 +281,7 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
   if (e == hipSuccess) e = launch_cast_f64_to_bf16_t(F.QT64, F.Q16, F.ld, st);
   // half factors of a symmetric axis
   std::vector<double> H[5];
-  std::vector<uint16_t> Hw[2];
+  std::vector<uint16_t> Hw[4];
   if (e == hipSuccess && fp.on) {
     F.fold = true;
     F.ne = fp.ne;
@@ -326,6 +328,18 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
     Hw[1].assign((size_t)(lw * lw), 0);
     for (int64_t j = 0; j < fp.no; ++j)
       for (int64_t r = 0; r < fp.hh; ++r) Hw[1][(size_t)(j * lw + r + sh)] = bf16_from_f64(H[4][(size_t)(r * kp + j)]);
+    // the backward pass that leaves its output folded: Be (rows = physical
+    // i < h + c, K = even modes), and Bo with its rows reversed (row r is
+    // i = h - 1 - r) and its K index (odd modes) shifted by sh
+    if (lw != kp) {
+      Hw[2].assign((size_t)(lw * lw), 0);
+      for (int64_t i = 0; i < fp.hh + fp.cc; ++i)
+        for (int64_t j = 0; j < fp.ne; ++j) Hw[2][(size_t)(i * lw + j)] = bf16_from_f64(H[2][(size_t)(j * kp + i)]);
+    }
+    Hw[3].assign((size_t)(lw * lw), 0);
+    for (int64_t r = 0; r < fp.hh; ++r)
+      for (int64_t j = 0; j < fp.no; ++j)
+        Hw[3][(size_t)(r * lw + j + sh)] = bf16_from_f64(H[3][(size_t)(j * kp + (fp.hh - 1 - r))]);
     if (lw != kp) {
       if (e == hipSuccess) e = hipMalloc(&F.Fe16w, sizeof(uint16_t) * (size_t)(lw * lw));
       if (e == hipSuccess)
@@ -336,6 +350,16 @@ int upload_factor(AxisFactor& F, const double* f, const std::vector<double>& Fwd
     if (e == hipSuccess) e = hipMalloc(&F.Fr16w, sizeof(uint16_t) * (size_t)(lw * lw));
     if (e == hipSuccess)
       e = hipMemcpyAsync(F.Fr16w, Hw[1].data(), sizeof(uint16_t) * Hw[1].size(), hipMemcpyHostToDevice, st);
+    if (lw != kp) {
+      if (e == hipSuccess) e = hipMalloc(&F.Be16w, sizeof(uint16_t) * (size_t)(lw * lw));
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(F.Be16w, Hw[2].data(), sizeof(uint16_t) * Hw[2].size(), hipMemcpyHostToDevice, st);
+    } else {
+      F.Be16w = F.Be16;  // K-contiguous Be at width kp is the same matrix
+    }
+    if (e == hipSuccess) e = hipMalloc(&F.Br16w, sizeof(uint16_t) * (size_t)(lw * lw));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(F.Br16w, Hw[3].data(), sizeof(uint16_t) * Hw[3].size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMalloc(&F.Fr64, sizeof(double) * cnt);
     if (e == hipSuccess) e = hipMalloc(&F.Fr32, sizeof(float) * cnt);
     if (e == hipSuccess) e = hipMemcpyAsync(F.Fr64, H[4].data(), sizeof(double) * cnt, hipMemcpyHostToDevice, st);
@@ -615,7 +639,7 @@ size_t plan_device_bytes(const ts_plan* p) {
     b += sizeof(double) * (size_t)F->n * (F->msq ? 5 : 3);
     if (F->band) b += sizeof(double) * (size_t)F->n * (2 * F->bw + 1);
     if (F->fold)
-      b += (size_t)(F->fkp * F->fkp) * (5 * 8 + 5 * 4 + 4 * 2) + (size_t)(F->fldw * F->fldw) * 2 * (F->fldw == F->fkp ? 1 : 2);
+      b += (size_t)(F->fkp * F->fkp) * (5 * 8 + 5 * 4 + 4 * 2) + (size_t)(F->fldw * F->fldw) * 2 * (F->fldw == F->fkp ? 2 : 4);
     add(F->op_pass.get());
   };
   for (const auto& F : p->ax) add(F.get());
@@ -720,6 +744,50 @@ bool bf16_fold_axes(const ts_plan* p, const void* in, void* out, bool sym, Butte
   return b.nax > 0;
 }
 
+// Whether a BF16 apply whose input sweep folds along fb's axes also runs its
+// backward passes over the slower axes on half extents: d = 2 or 3 with every
+// slower axis folded and of even extent; those passes leave their output
+// folded, and the last pass, backward over the fastest axis, unfolds it
+// before its FP64 stores.  `buf` stands for the buffers the passes use (the
+// caller's output and the library's 256-byte aligned workspace).
+static bool bf16_unfold_route(const ts_plan* p, const ButterflyArgs& fb, bool sym, const void* buf, bool accumulate) {
+  const int d = p->d;
+  if (!p->bf16_bwd_fold || (d != 2 && d != 3)) return false;
+  for (int k = 0; k < d - 1; ++k) {
+    bool in = false;
+    for (int j = 0; j < fb.nax; ++j) in = in || fb.ax[j] == k;
+    if (!in || p->n[k] % 2 != 0) return false;
+  }
+  PassArgs q;
+  q.X = buf;
+  q.Y = (void*)buf;
+  q.tin = DT::BF16;
+  q.prec = TS_PREC_BF16;
+  q.forward = false;
+  q.bf16_tile = p->bf16_tile;
+  for (int k = 0; k < d; ++k) {
+    q.fac = (sym ? p->ax_sym : p->ax)[k].get();
+    q.n = p->n[k];
+    q.P = 1;
+    for (int m = 0; m < k; ++m) q.P *= p->n[m];
+    q.R = 1;
+    for (int m = k + 1; m < d; ++m) q.R *= p->n[m];
+    if (k < d - 1) {
+      q.tout = DT::BF16;
+      q.fold = q.deferred = true;
+      if (!bf16_fold_pass_ok(q)) return false;
+    } else {
+      q.tout = DT::F64;
+      q.fold = q.deferred = false;
+      q.accumulate = accumulate;
+      q.unf = d - 1;
+      for (int m = 0; m < d - 1; ++m) q.un[m] = p->n[m];
+      if (!bf16_unfold_pass_ok(q)) return false;
+    }
+  }
+  return true;
+}
+
 // Run the 2d passes of one apply.  Intermediates have the precision's type.
 int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   const int d = p->d;
@@ -809,6 +877,17 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
       if (bax[j] == k) return true;
     return false;
   };
+  // with every slower axis folded, the backward passes over them run on half
+  // extents too, and the fastest axis goes last to unfold the output
+  const bool unfold = nb > 0 && ap.tout == DT::F64 && bf16_unfold_route(p, fb, ap.sym, ap.out, ap.accumulate);
+  std::vector<int> border{p->s};
+  if (unfold) {
+    for (int k = 0; k < d - 1; ++k)
+      if (k != p->s) border.push_back(k);
+    border.push_back(d - 1);
+  } else {
+    for (int j = 0; j + 1 < d; ++j) border.push_back(order[j]);
+  }
   // BF16 transforms of FP64 data: round the input to BF16 in one streaming
   // sweep (into the output buffer, which the last pass overwrites), so that
   // the first pass reads 2 instead of 8 bytes per value (rounded as the pass
@@ -839,7 +918,7 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
   }
   for (int t = 1; t <= T; ++t) {
     const bool fwd = t <= d;
-    const int k = fwd ? order[t - 1] : (t == d + 1 ? p->s : order[t - d - 2]);
+    const int k = fwd ? order[t - 1] : border[t - d - 1];
     void* dst = ((T - t) % 2 == 0) ? (t == T ? ap.out : ob) : ap.work;
     DT dst_t = (t == T) ? ap.tout : inter;
     PassArgs pa;
@@ -863,6 +942,14 @@ int run_apply(ts_plan* p, const ApplyParams& ap, hipStream_t st) {
     pa.fold = pa.fac->fold && p->fold_enabled && ap.prec != TS_PREC_BF16;
     pa.deferred = deferred && pa.fold;
     if (ap.prec == TS_PREC_BF16 && fwd && bf16_folded(k)) pa.fold = pa.deferred = true;
+    if (unfold && !fwd) {
+      if (t < T) {
+        pa.fold = pa.deferred = true;
+      } else {
+        pa.unf = d - 1;
+        for (int m = 0; m < d - 1; ++m) pa.un[m] = p->n[m];
+      }
+    }
     pa.accumulate = ap.accumulate && t == T;
     pa.bf16_tile = p->bf16_tile;
     if (fwd && t == d) {
@@ -892,6 +979,8 @@ bool bf16_sweep_applies(const ts_plan* p, const void* in, const void* out) {
 
 bool bf16_accumulate_ok(const ts_plan* p, const void* in, const void* out, bool sym) {
   if (plan_is_small(p) || in == out || p->N % 8 != 0 || (((uintptr_t)out) & 15) != 0) return false;
+  ButterflyArgs fb;
+  if (bf16_fold_axes(p, in, (void*)out, sym, fb) && bf16_unfold_route(p, fb, sym, out, true)) return true;
   // the last pass (run_apply's order): backward along the lowest axis other
   // than the scaling axis s, or along s itself in 1D
   const int d = p->d;
@@ -1367,7 +1456,9 @@ int ts_fold_butterfly(ts_plan* plan, int axes, const void* in, void* out, int dt
 
 int ts_set_fold(ts_plan* plan, int enable) {
   if (!plan) { set_error("null plan"); return TS_ERR_INVALID; }
+  if (enable < 0 || enable > 2) { set_error("fold mode must be 0, 1 or 2"); return TS_ERR_INVALID; }
   plan->fold_enabled = enable != 0;
+  plan->bf16_bwd_fold = enable == 1;
   return TS_OK;
 }
 

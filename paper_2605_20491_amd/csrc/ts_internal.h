@@ -82,6 +82,10 @@ struct AxisFactor {
   // Fr row k - sh; the pass reads the odd half from n - h - sh, a multiple of
   // 8, and the sh even entries it takes along meet zero columns)
   uint16_t *Fe16w = nullptr, *Fr16w = nullptr;
+  // and of the backward pass that leaves its output folded: Be (K from 0), and
+  // Br = Bo with its physical index reversed (row r is i = h - 1 - r, written
+  // at n - h + r) and its K index shifted by sh, both [fldw][fldw]
+  uint16_t *Be16w = nullptr, *Br16w = nullptr;
   int64_t fldw = 0;
   std::vector<double> lam_int_h;  // eigenvalues in the internal spectral order
   // Generic plans whose operator band is wide: the axis operator itself as an
@@ -123,17 +127,25 @@ struct PassArgs {
   // FP64 output of a BF16 pass on 256 x 256 tiles: Y += the result instead of
   // Y = the result (bf16_big_pass_ok tells whether the pass runs there)
   bool accumulate = false;
+  // BF16 row pass with FP64 output, the last of an apply whose other passes
+  // left the data folded along the unf (1 or 2) slower axes of extents un[]
+  // (slowest first): the pass unfolds them (bf16_unfold_pass_ok)
+  int unf = 0;
+  int64_t un[2] = {0, 0};
   int64_t kband = 0;           // > 0: the factor is banded, |k - output| <= kband (FP64 passes)
   int bf16_tile = 0;           // BF16 passes: 0 picks the tile size, 128 or 256 forces it where allowed
 };
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t st);
 hipError_t launch_pass_bf16(const PassArgs& a, hipStream_t st);
-// Whether a forward BF16 pass can read data folded beforehand (pa.fold and
-// pa.deferred set): the 256 x 256-tile kernel is the only one with that layout.
+// Whether a BF16 pass can read data folded beforehand (pa.fold and pa.deferred
+// set; a backward pass also leaves its output folded): the 256 x 256-tile
+// kernel is the only one with that layout.
 bool bf16_fold_pass_ok(const PassArgs& pa);
 // Whether a BF16 pass of BF16 input runs on the 256 x 256 tiles.
 bool bf16_big_pass_ok(const PassArgs& pa);
+// Whether the last pass of a BF16 apply can unfold its input (pa.unf, pa.un).
+bool bf16_unfold_pass_ok(const PassArgs& pa);
 
 // Butterfly y_i, y_{n-1-i} = x_i + x_{n-1-i}, x_i - x_{n-1-i} (i < hh), in
 // place or not, along up to four axes of a [n_0]...[n_{d-1}][ncomp] array at once
@@ -213,6 +225,7 @@ struct ts_plan {
   int sem_k = 0;               // 0: FD or generic; k >= 1: Q^k SEM
   bool massed = false;         // SEM or generic: mass inner product, banded operator
   bool fold_enabled = true;    // use the half-extent passes on symmetric axes
+  bool bf16_bwd_fold = true;   // BF16 applies: backward passes over half extents too (ts_set_fold)
   int bf16_tile = 0;           // BF16 pass tile: 0 automatic, 128 or 256 forced
   int s = 0;                   // axis whose forward pass carries the scaling
   int64_t Ps = 1, Rs = 1;      // products of the extents before / after axis s

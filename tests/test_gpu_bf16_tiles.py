@@ -170,3 +170,59 @@ def test_refined_bf16_adds_in_last_pass():
                 np.array_equal(outs[256][0], outs[128][0])))
     assert outs[256][1] == outs[128][1] and np.array_equal(outs[256][0], outs[128][0])
     assert outs[256][2] <= 1e-10
+
+
+@pytest.mark.parametrize("shape,tile", [((256, 264, 256), 0), ((202, 200, 200), 256), ((400, 256), 256)])
+def test_folded_backward_passes(shape, tile):
+    """BF16 inverse of FP64 data with every slower axis folded and of even
+    extent (2D and 3D): the backward passes over the slower axes also contract
+    half the extent and leave their output folded, and the last pass (the
+    fastest axis, FP64 output) gathers the rows of each reflection orbit into
+    one lane and unfolds them before storing.  n = 264, 200: h = 4 mod 8 (the
+    shifted odd half); 202: h = 101, 5 mod 8; orbits per tile 64 (3D) or 128
+    (2D), with ragged last tiles (10100 orbits for 202 x 200, 200 for 400).
+    Against the oracle at the BF16 level (every output stored: the output starts
+    as NaN), and against the same apply with full backward passes (ts_set_fold
+    mode 2: a different rounding of the same products)."""
+    plan, oplan, _ = make_pair(shape, 8.0, "harm", sigma=1.0)
+    ts.ts_set_bf16_tile(plan, tile)
+    b = W.rhs_normal(shape, 26)
+    ref = oracle.apply_inverse(oplan, b, 1.0)
+    bd = to_dev(b)
+    out = torch.full(shape, float("nan"), dtype=torch.float64, device=DEV)
+    u = to_host(ts.ts_apply_inverse(plan, bd, out, prec="bf16"))
+    ts.ts_set_fold(plan, 2)
+    u2 = to_host(ts.ts_apply_inverse(plan, bd, prec="bf16"))
+    ts.ts_set_fold(plan, 1)
+    e, em, e2, ed = rel(u, ref), maxrel(u, ref), rel(u2, ref), rel(u, u2)
+    announce("bf16 folded backward %s tile %d: rel err %.3e (max-norm %.3e), full backward %.3e, between %.3e"
+             % (shape, tile, e, em, e2, ed))
+    assert np.isfinite(u).all()
+    assert 1e-3 < e <= 1.5e-2 and em <= 5e-2
+    assert ed <= 1.5e-2 and not np.array_equal(u, u2)
+    with pytest.raises(ts.TSError):
+        ts.ts_set_fold(plan, 3)
+
+
+def test_refined_bf16_folded_backward():
+    """The BF16-refined direct inverse on a shape that takes the folded
+    backward passes: each correction is added to u by the unfolding last pass.
+    The true residual (oracle stencil) meets the bar, and the solution agrees
+    with the refined solve whose BF16 applies run full backward passes."""
+    shape = (256, 264, 256)
+    L = 8.0
+    f = [W.f_harmonic(n, L) for n in shape]
+    plan = ts.ts_setup(shape, L, f, 1.0)
+    b = W.rhs_normal(shape, 27)
+    op = oracle.Plan(shape=shape, L=L, f=f, h=[oracle.grid_spacing(n, L) for n in shape])
+    sols = []
+    for mode in (1, 2):
+        ts.ts_set_fold(plan, mode)
+        u = torch.empty(shape, dtype=torch.float64, device=DEV)
+        _, its, relres = ts.ts_solve_refined(plan, to_dev(b), u, inner="bf16", rtol=1e-10, maxit=60)
+        uh = to_host(u)
+        true = np.linalg.norm(b - oracle.stencil_apply(op, uh, None, 1.0)) / np.linalg.norm(b)
+        announce("refined bf16 %s fold mode %d: %d sweeps, relres %.2e, true residual %.2e" % (shape, mode, its, relres, true))
+        assert relres <= 1e-10 and true <= 1.05e-10
+        sols.append(uh)
+    assert rel(sols[0], sols[1]) <= 1e-8

@@ -178,10 +178,10 @@ def test_plan_cache_within_reserve_and_busy():
     srv.submit(ts.TS_REQ_INVERSE, shape, L, f, 1.0, x, out)
     srv.drain()
     srv.close()
-    # a reserve that holds one 256^3 plan (~2.9 MB with its half factors) but not
+    # a reserve that holds one 256^3 plan (~3.2 MB with its half factors) but not
     # that and a 1.4 MB plan: a submit made while a long 256^3 PCG holds its plan
     # is told to come back later, and succeeds once that request has finished
-    srv = ts.Server(2 << 30, 2, 0, plan_reserve=3 << 20)
+    srv = ts.Server(2 << 30, 2, 0, plan_reserve=13 << 18)
     big = (256, 256, 256)
     fb = [W.f_harmonic(n, L) for n in big]
     V2b = torch.from_numpy(W.gaussian_bumps(big, L, 8, seed=5)).to(DEV).abs()
