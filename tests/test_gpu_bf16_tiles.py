@@ -16,6 +16,13 @@ data folded by the input sweep (half the extent; the odd half of an axis with
 h = n / 2 = 4 mod 8 is read from n - h - 4 against a factor shifted by 4):
 checked against the oracle and against the same apply with folding off, with
 even and odd extents, ragged half-tiles and the shifted case.
+
+With every slower axis folded and even (2D, 3D) the backward passes over them
+also run on half extents and the last pass unfolds in registers (rows gathered
+by reflection orbits); that pass also adds the refinement's corrections.
+Checked against the oracle, against the same apply with full backward passes
+(ts_set_fold mode 2), and through the refined inverse (true residual by the
+oracle's stencil); PCG on such a shape is the 256^3 test above.
 """
 import numpy as np
 import pytest
@@ -226,3 +233,4 @@ def test_refined_bf16_folded_backward():
         assert relres <= 1e-10 and true <= 1.05e-10
         sols.append(uh)
     assert rel(sols[0], sols[1]) <= 1e-8
+
