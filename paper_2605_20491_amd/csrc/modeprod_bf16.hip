@@ -831,22 +831,33 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a, UGeom u) {
     static_assert(BB * LT <= 4 * BB * LDK, "staged tile must fit in the operand buffers");
     uint16_t* Ts = smem_big;
     double tr[4] = {0.0, 0.0, 0.0, 0.0};
-    if (EPI == (int)Epi::Inv) {
+    const double* tmS = nullptr;
+    if constexpr (EPI == (int)Epi::Inv) {
+      // the row parts lam + Lp of the denominators of the tile's 256 rows: one
+      // load per thread into LDS behind the staged tile (the main loop's last
+      // barrier left LDS idle), instead of each lane loading its 32 just
+      // before their use, one dependent round trip per 16-row block
+      static_assert(BB * LT * sizeof(uint16_t) + BB * sizeof(double) <= 4 * BB * LDK * sizeof(uint16_t),
+                    "denominator table must fit behind the staged tile");
+      double* tmw = (double*)(smem_big + BB * LT);
+      if (t < BB) {
+        const int64_t m = m0 + t;
+        tmw[t] = m < cnt ? a.lam[base + m] + a.Lp[p] : 0.0;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t col = n0 + wn * 64 + j * 16 + lr;
         tr[j] = col < a.R ? a.Lr[col] : 0.0;
       }
+      __syncthreads();
+      tmS = tmw;
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       double tm[4] = {0.0, 0.0, 0.0, 0.0};
-      if (EPI == (int)Epi::Inv) {
+      if constexpr (EPI == (int)Epi::Inv) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t m = m0 + wm * 128 + i * 16 + out_row<float>(lane, r);
-          tm[r] = m < cnt ? a.lam[base + m] + a.Lp[p] : 0.0;
-        }
+        for (int r = 0; r < 4; ++r) tm[r] = tmS[wm * 128 + i * 16 + out_row<float>(lane, r)];
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j)
