@@ -896,6 +896,21 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a, UGeom u) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int rho = wm * 128 + i * 16 + 4 * lg;
+      // ACC: the block's 16 old values are loaded together before its stores (a
+      // load after a store waits for it: one load and add per store would make
+      // every element a round trip)
+      double yo[4][4];
+      if constexpr (ACC) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int64_t col = n0 + wn * 64 + j * 16 + lr;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t o = mtile * (BB >> NU) + ((rho + r) >> NU);
+            yo[j][r] = col < a.n && o < u.no ? Y[unf_row<NU>(u, o, (rho + r) & ((1 << NU) - 1)) * a.n + col] : 0.0;
+          }
+        }
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t col = n0 + wn * 64 + j * 16 + lr;
@@ -922,7 +937,7 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a, UGeom u) {
           const int64_t o = mtile * (BB >> NU) + ((rho + r) >> NU);
           if (o >= u.no) continue;
           double* y = Y + unf_row<NU>(u, o, (rho + r) & ((1 << NU) - 1)) * a.n + col;
-          if constexpr (ACC) *y += x[r];
+          if constexpr (ACC) *y = yo[j][r] + x[r];
           else *y = x[r];
         }
       }
@@ -935,6 +950,15 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a, UGeom u) {
         const int64_t m = m0 + wm * 128 + i * 16 + out_row<float>(lane, r);
         if (m >= nrows) continue;
         const double tm = EPI == (int)Epi::Inv ? a.lam[m] + a.Lp[p] : 0.0;
+        // ACC: the row's four old values are loaded before its stores
+        double yo[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (ACC) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int64_t col = n0 + wn * 64 + j * 16 + lr;
+            if (col < rowlen) yo[j] = Y[(ROWS ? m * a.n : (p * a.n + m) * a.R) + col];
+          }
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int64_t col = n0 + wn * 64 + j * 16 + lr;
@@ -942,7 +966,7 @@ __global__ __launch_bounds__(NTB, 1) void k_mode_bf16_big(KArgs a, UGeom u) {
           double v = (double)acc[i][j][r];
           if (EPI == (int)Epi::Inv) v = v / (tm + a.Lr[col] + a.shift);
           TOut* y = Y + (ROWS ? m * a.n : (p * a.n + m) * a.R) + col;
-          if constexpr (ACC) *y += v;
+          if constexpr (ACC) *y = yo[j] + v;
           else *y = cvt_out<TOut>(v);
         }
       }
