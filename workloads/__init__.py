@@ -8,7 +8,7 @@ Grid: n interior nodes of [-L, L], x_j = -L + j h, h = 2L/(n+1), j = 1..n
 (homogeneous Dirichlet; the paper's n interior grid points per direction).
 Axis order is C order: axis d-1 is the fastest index (the paper's x).
 
-Workload recipes (each reading is listed in the design doc):
+Workload recipes (where the paper leaves a detail open, the choice is stated here):
 * ``rhs_normal``: i.i.d. N(0, 1) right-hand side (numpy PCG64 from the seed).
 * ``gaussian_wavepacket``: psi0(x) = exp(-|x - x0|^2 / (2 s^2) + i k0 . x),
   x0 ~ U[-2, 2]^d, s ~ U(0.5, 1.5), k0 ~ U[-2, 2]^d, normalised to unit 2-norm.
